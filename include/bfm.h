@@ -1,0 +1,175 @@
+/*
+ * bfm.h - C ABI of the MI355X fast-multipole boundary-element library.
+ *
+ * The library solves the discrete boundary integral equation of a cluster
+ * of gas bubbles in potential flow (Gumerov, Pityuk, Abramova, Akhatov,
+ * "GPU accelerated fast multipole boundary element method for simulation
+ * of 3D bubble dynamics in potential flow"): given the surface mesh and the
+ * potential phi at every vertex, it returns q = dphi/dn at every vertex.
+ *
+ *   Problem (Section 2.2, eq2_11 - eq2_13):  L[q] - M[phi] = -phi/2 on S,
+ *     G = 1/(4 pi |r - r'|),  dG/dn' = n'.(r - r')/(4 pi |r - r'|^3),
+ *     n' points out of the bubble into the liquid.
+ *   Discretisation (Section 3.1, eq3_1/eq3_2): vertex collocation,
+ *     L q = b,  b = -phi/2 + M phi.
+ *   Non-singular entries (Section 3.2, ns1): L_ij = s_j G(r_i, r_j),
+ *     M_ij = s_j dG/dn_j(r_i, r_j), i != j; s_j = (1/3) sum of the areas of
+ *     the triangles at j, n_j = normalised area-weighted triangle normal.
+ *   Singular diagonals (Section 3.3, s3 and s5): M_ii = -1/2 - sum_{j!=i}
+ *     M_ij;  L_ii = n_i . [sum_{j!=i}(M_ij r_j - L_ij n_j) + (1/2 + M_ii) r_i].
+ *   Products with L and M (Section 3.9, eq3_27) use the fast multipole
+ *     method over an octree (scaled to a cube, empty boxes skipped);
+ *     the system is solved by restarted GMRES (Section 3.8).
+ *
+ * Conventions for every entry point:
+ *   - Return value: BFM_OK (0) or a negative BFM_E* code; the message of
+ *     the last failure on the calling thread is bfm_last_error().
+ *   - Host pointers ("host" below) are read or written before the call
+ *     returns and never retained. Device pointers ("_dev" entry points)
+ *     must be HBM allocations on the handle's device, valid until the
+ *     handle's stream has been synchronised; the _dev entry points are
+ *     ordered on the handle's stream and do not synchronise it unless
+ *     stated.
+ *   - A handle is not thread-safe; separate handles are independent.
+ *   - Arrays of vertices are indexed in the caller's vertex order.
+ */
+#ifndef BFM_H
+#define BFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BFM_ABI_VERSION 1
+
+enum {
+    BFM_OK = 0,
+    BFM_EINVAL = -1,      /* invalid argument or option */
+    BFM_ENOMEM = -2,      /* device or host allocation failed */
+    BFM_EDEVICE = -3,     /* a HIP call failed */
+    BFM_ENOCONV = -4,     /* GMRES hit its iteration limit; q holds the best iterate */
+    BFM_EMESH = -5,       /* degenerate mesh: zero-area triangle, zero normal, index out of range */
+    BFM_EUNSUPPORTED = -6 /* option combination not built */
+};
+
+/* Arithmetic of the fast multipole product. */
+enum {
+    BFM_PREC_FP64 = 0, /* FP64 near field and FP64 translations */
+    BFM_PREC_FP32 = 1  /* FP32 near field (leaf-relative coordinates), FP32 translations */
+};
+
+typedef struct bfm_options {
+    int abi_version;   /* must be BFM_ABI_VERSION */
+    int device;        /* HIP device ordinal */
+    void *stream;      /* hipStream_t to run on; NULL = the library creates one */
+    int p;             /* expansion degrees 0..p-1 (p^2 coefficients); multiple of 4, 4..20 */
+    int lmax;          /* octree depth; 0 = choose from leaf_target */
+    int leaf_target;   /* mean points per non-empty leaf aimed at when lmax = 0 */
+    int precision;     /* BFM_PREC_* for the products inside GMRES */
+    double gmres_tol;  /* stop when ||b - L q||_2 <= gmres_tol ||b||_2 */
+    int gmres_restart; /* Krylov dimension before restart (1..128) */
+    int gmres_maxit;   /* total iteration limit */
+} bfm_options;
+
+typedef struct bfm_solve_info {
+    int iterations;      /* GMRES iterations (one product with L each) */
+    int restarts;        /* completed restart cycles */
+    int matvecs;         /* products with L, including explicit residuals */
+    int converged;       /* 1 if the tolerance was met */
+    double rel_residual; /* final ||b - L q|| / ||b|| (true residual at exit) */
+    double t_tree_ms;    /* geometry + octree build */
+    double t_diag_ms;    /* singular diagonals + right-hand side pass */
+    double t_solve_ms;   /* GMRES */
+} bfm_solve_info;
+
+typedef struct bfm_ctx bfm_ctx;
+
+/* Fill *opt with defaults: p = 12, lmax = 0, leaf_target = 64, FP64,
+ * tol 1e-10, restart 30, maxit 300, device 0, stream NULL. */
+int bfm_default_options(bfm_options *opt);
+
+/* Create a handle on opt->device. The handle owns every device buffer
+ * (mesh, octree, expansions, translation operators, Krylov basis). */
+int bfm_create(const bfm_options *opt, bfm_ctx **out);
+int bfm_destroy(bfm_ctx *ctx);
+
+/* Replace the options of an existing handle (same device and stream).
+ * Changing p rebuilds the translation operators; changing lmax or
+ * leaf_target rebuilds the octree at the next call that needs it. */
+int bfm_set_options(bfm_ctx *ctx, const bfm_options *opt);
+
+/*
+ * Set the surface mesh (Section 3.1): nv vertices xyz (host, [nv][3]
+ * row-major, FP64), nt triangles tri (host, [nt][3] int32 vertex indices,
+ * ordered r1 -> r2 -> r3 so that (r2 - r1) x (r3 - r1) points into the
+ * liquid). nb bubbles own contiguous vertex ranges vtx_off[b]..vtx_off[b+1]
+ * and triangle ranges tri_off[b]..tri_off[b+1] (host, int64 [nb + 1]; may
+ * be NULL when nb <= 1). Copies everything; connectivity is kept until the
+ * next bfm_set_mesh, positions until bfm_set_positions*.
+ * Errors: BFM_EINVAL (nv < 4, nt < 4, bad ranges), BFM_EMESH (index out of
+ * range, a vertex in no triangle).
+ */
+int bfm_set_mesh(bfm_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, const int32_t *tri,
+                 int32_t nb, const int64_t *vtx_off, const int64_t *tri_off);
+
+/* Move the vertices (same connectivity): xyz host [nv][3] or device
+ * (_dev, FP64 [nv][3]). Geometry and octree are rebuilt at the next use. */
+int bfm_set_positions(bfm_ctx *ctx, const double *xyz);
+int bfm_set_positions_dev(bfm_ctx *ctx, const double *xyz_dev);
+
+/* Vertex weights s_j and unit normals n_j of ns1 (Section 3.2): host
+ * outputs s [nv], n [nv][3]. Errors: BFM_EMESH on a zero-area triangle or
+ * a vertex whose area-weighted normal vanishes. */
+int bfm_geometry(bfm_ctx *ctx, double *s, double *n);
+
+/*
+ * Singular diagonals and right-hand side (Section 3.3 s3/s5, eq3_1) by one
+ * five-channel fast multipole pass at the handle's p, in FP64:
+ *   Mii[i] = -1/2 - sum_{j!=i} M_ij
+ *   Lii[i] = n_i . [sum_{j!=i} M_ij (r_j - r_i) - sum_{j!=i} L_ij n_j]
+ *   b[i]   = -phi_i/2 + Mii[i] phi_i + sum_{j!=i} M_ij phi_j
+ * phi host [nv]; outputs host [nv] (any may be NULL except phi).
+ */
+int bfm_diagonals(bfm_ctx *ctx, const double *phi, double *Mii, double *Lii, double *b);
+
+/*
+ * Product with A = f L + g M (eq3_27) by the fast multipole method:
+ *   out_i = sum_{j != i} (f L_ij x_j + g M_ij y_j) [+ f L_ii x_i + g M_ii y_i if add_diag]
+ * x, y, out host [nv] (x may be NULL if f == 0, y if g == 0). precision
+ * selects BFM_PREC_*. add_diag needs the diagonals of the current mesh
+ * (computed on demand). direct = 1 replaces the fast multipole method by
+ * the all-pairs sum on the GPU (FP64), for checking.
+ */
+int bfm_matvec(bfm_ctx *ctx, double f, const double *x, double g, const double *y, double *out,
+               int add_diag, int precision, int direct);
+
+/*
+ * Solve L q = b for q = dphi/dn (eq3_2): geometry, octree, diagonals and
+ * right-hand side, then restarted GMRES from the initial guess.
+ *   phi  host [nv] (bfm_solve) or device FP64 [nv] (bfm_solve_dev)
+ *   q    in: initial guess if use_guess != 0, else ignored (zero guess);
+ *        out: the solution. Host [nv] or device [nv] respectively.
+ *   info may be NULL.
+ * Returns BFM_ENOCONV (q = last iterate, info filled) when gmres_maxit is
+ * reached first. bfm_solve_dev synchronises the stream before returning.
+ */
+int bfm_solve(bfm_ctx *ctx, const double *phi, double *q, int use_guess, bfm_solve_info *info);
+int bfm_solve_dev(bfm_ctx *ctx, const double *phi_dev, double *q_dev, int use_guess,
+                  bfm_solve_info *info);
+
+/* Octree statistics of the current mesh (builds the tree if needed):
+ * stats[0] = lmax, [1] = leaves, [2] = boxes (all levels), [3] = near-field
+ * pairs, [4] = M2L pairs, [5] = M2M+L2L pairs, [6] = max points per leaf. */
+int bfm_tree_stats(bfm_ctx *ctx, int64_t stats[8]);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *bfm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFM_H */

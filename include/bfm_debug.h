@@ -1,0 +1,34 @@
+/*
+ * bfm_debug.h - host-only introspection of libbfm for tests (no GPU needed).
+ *
+ * The fast multipole translations of the paper's FMM (Section 3.9:
+ * multipole and local expansions of degrees 0..p_fmm-1, translated between
+ * boxes of the octree) are stored by libbfm as dense real p^2 x p^2
+ * matrices in a normalised, box-scaled basis. This call exposes one of them
+ * so that tests can check it against independent expansions on the CPU.
+ */
+#ifndef BFM_DEBUG_H
+#define BFM_DEBUG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * kind 0: multipole-to-multipole, child octant `index` (0..7) -> parent
+ * kind 1: local-to-local, parent -> child octant `index` (0..7)
+ * kind 2: multipole-to-local, offset operator `index` (0..315)
+ * Octant o: child box integer coordinates have low bits (o>>2 & 1, o>>1 & 1,
+ * o & 1). Offset operator k: the k-th (dx, dy, dz) in lexicographic order of
+ * [-3,3]^3 excluding [-1,1]^3, meaning c_target - c_source = d * h.
+ * out: host, p^2 * p^2 doubles, row-major (out[row * p^2 + col]).
+ * d_out (may be NULL): for kind 2 receives the offset (dx, dy, dz).
+ * Returns 0, or -1 (BFM_EINVAL) on a bad p, kind or index.
+ */
+int bfm_debug_operator(int p, int kind, int index, double *out, int *d_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFM_DEBUG_H */

@@ -1,0 +1,226 @@
+"""Python binding of libbfm (ctypes, argument marshalling only).
+
+Every numerical step runs in the HIP library; this module converts numpy
+arrays or torch device tensors to pointers and back. It raises if the
+compiled library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfm.so")
+
+BFM_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "EMESH", -6: "EUNSUPPORTED"}
+PREC_FP64 = 0
+PREC_FP32 = 1
+ABI_VERSION = 1
+
+
+class BfmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bfm error {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int),
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("p", ctypes.c_int),
+        ("lmax", ctypes.c_int),
+        ("leaf_target", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("gmres_tol", ctypes.c_double),
+        ("gmres_restart", ctypes.c_int),
+        ("gmres_maxit", ctypes.c_int),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("matvecs", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("rel_residual", ctypes.c_double),
+        ("t_tree_ms", ctypes.c_double),
+        ("t_diag_ms", ctypes.c_double),
+        ("t_solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbfm.so (raises FileNotFoundError if it was never built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with paper_1905_01341_amd.build.build() "
+            "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    sig = {
+        "bfm_default_options": ([ctypes.POINTER(Options)], I),
+        "bfm_create": ([ctypes.POINTER(Options), ctypes.POINTER(P)], I),
+        "bfm_destroy": ([P], I),
+        "bfm_set_options": ([P, ctypes.POINTER(Options)], I),
+        "bfm_set_mesh": ([P, I64, P, I64, P, ctypes.c_int32, P, P], I),
+        "bfm_set_positions": ([P, P], I),
+        "bfm_set_positions_dev": ([P, P], I),
+        "bfm_geometry": ([P, P, P], I),
+        "bfm_diagonals": ([P, P, P, P, P], I),
+        "bfm_matvec": ([P, D, P, D, P, P, I, I, I], I),
+        "bfm_solve": ([P, P, P, I, ctypes.POINTER(SolveInfo)], I),
+        "bfm_solve_dev": ([P, P, P, I, ctypes.POINTER(SolveInfo)], I),
+        "bfm_tree_stats": ([P, ctypes.POINTER(I64)], I),
+        "bfm_last_error": ([], ctypes.c_char_p),
+        "bfm_debug_operator": ([I, I, I, P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != BFM_OK:
+        msg = load().bfm_last_error().decode(errors="replace")
+        raise BfmError(rc, msg)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _check(load().bfm_default_options(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def debug_operator(p: int, kind: int, index: int):
+    """Dense translation operator (see include/bfm_debug.h)."""
+    P = p * p
+    out = np.empty((P, P))
+    d = np.zeros(3, dtype=np.int32)
+    _check(load().bfm_debug_operator(p, kind, index, _ptr(out), _ptr(d)))
+    return out, d
+
+
+class Solver:
+    """One library handle (owns all device state for one mesh)."""
+
+    def __init__(self, **opts):
+        self.lib = load()
+        self.opt = default_options(**opts)
+        h = ctypes.c_void_p()
+        _check(self.lib.bfm_create(ctypes.byref(self.opt), ctypes.byref(h)))
+        self.h = h
+        self.nv = 0
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.bfm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opt, k, v)
+        _check(self.lib.bfm_set_options(self.h, ctypes.byref(self.opt)))
+
+    def set_mesh(self, xyz, tri, vtx_off=None, tri_off=None):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        nb = 0
+        vo = to = None
+        if vtx_off is not None:
+            vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+            to = np.ascontiguousarray(tri_off, dtype=np.int64)
+            nb = vo.shape[0] - 1
+        _check(self.lib.bfm_set_mesh(self.h, xyz.shape[0], _ptr(xyz), tri.shape[0], _ptr(tri), nb,
+                                     _ptr(vo), _ptr(to)))
+        self.nv = xyz.shape[0]
+
+    def set_cluster(self, cl):
+        self.set_mesh(cl.xyz, cl.tri, cl.vtx_off, cl.tri_off)
+
+    def set_positions(self, xyz):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        _check(self.lib.bfm_set_positions(self.h, _ptr(xyz)))
+
+    def geometry(self):
+        s = np.empty(self.nv)
+        n = np.empty((self.nv, 3))
+        _check(self.lib.bfm_geometry(self.h, _ptr(s), _ptr(n)))
+        return s, n
+
+    def diagonals(self, phi):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        Mii, Lii, b = (np.empty(self.nv) for _ in range(3))
+        _check(self.lib.bfm_diagonals(self.h, _ptr(phi), _ptr(Mii), _ptr(Lii), _ptr(b)))
+        return Mii, Lii, b
+
+    def matvec(self, f=1.0, x=None, g=0.0, y=None, add_diag=False, precision=PREC_FP64, direct=False):
+        xx = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+        yy = None if y is None else np.ascontiguousarray(y, dtype=np.float64)
+        out = np.empty(self.nv)
+        _check(self.lib.bfm_matvec(self.h, float(f), _ptr(xx), float(g), _ptr(yy), _ptr(out),
+                                   int(add_diag), int(precision), int(direct)))
+        return out
+
+    def solve(self, phi, q0=None, check=True):
+        """Host arrays in, (q, info dict) out."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        q = np.zeros(self.nv) if q0 is None else np.array(q0, dtype=np.float64)
+        info = SolveInfo()
+        rc = self.lib.bfm_solve(self.h, _ptr(phi), _ptr(q), int(q0 is not None), ctypes.byref(info))
+        if check or rc not in (BFM_OK, -4):
+            _check(rc)
+        return q, info.as_dict()
+
+    def solve_dev(self, phi_t, q_t, use_guess=False):
+        """torch float64 device tensors (contiguous); q_t is overwritten."""
+        import torch
+        assert phi_t.dtype == torch.float64 and q_t.dtype == torch.float64
+        assert phi_t.is_contiguous() and q_t.is_contiguous()
+        assert phi_t.numel() == self.nv and q_t.numel() == self.nv
+        torch.cuda.current_stream().synchronize()
+        info = SolveInfo()
+        _check(self.lib.bfm_solve_dev(self.h, ctypes.c_void_p(phi_t.data_ptr()),
+                                      ctypes.c_void_p(q_t.data_ptr()), int(use_guess),
+                                      ctypes.byref(info)))
+        return info.as_dict()
+
+    def tree_stats(self):
+        st = (ctypes.c_int64 * 8)()
+        _check(self.lib.bfm_tree_stats(self.h, st))
+        keys = ["lmax", "leaves", "boxes", "near_pairs", "m2l_pairs", "tree_pairs", "max_leaf"]
+        return {k: int(st[i]) for i, k in enumerate(keys)}

@@ -1,0 +1,394 @@
+// C ABI of libbfm (declared in include/bfm.h). Every entry point catches
+// internal errors and turns them into a return code plus a thread-local
+// message; nothing throws across the boundary.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+#include "ops.h"
+
+namespace bfm {
+
+static thread_local std::string g_last_error;
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+template <class F>
+static int guarded(F &&f) {
+    try {
+        f();
+        return BFM_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return BFM_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return BFM_EINVAL;
+    }
+}
+
+static void check_options(const bfm_options &o) {
+    BFM_CHECK(o.abi_version == BFM_ABI_VERSION, BFM_EINVAL, "abi_version mismatch");
+    BFM_CHECK(o.p >= 4 && o.p <= kMaxP && o.p % 4 == 0, BFM_EINVAL,
+              "p must be a multiple of 4 in [4, 20]");
+    BFM_CHECK(o.lmax == 0 || (o.lmax >= 2 && o.lmax <= 15), BFM_EINVAL, "lmax must be 0 or in [2, 15]");
+    BFM_CHECK(o.leaf_target >= 1, BFM_EINVAL, "leaf_target must be >= 1");
+    BFM_CHECK(o.precision == BFM_PREC_FP64 || o.precision == BFM_PREC_FP32, BFM_EINVAL,
+              "unknown precision");
+    BFM_CHECK(o.gmres_tol > 0.0 && o.gmres_tol < 1.0, BFM_EINVAL, "gmres_tol must be in (0, 1)");
+    BFM_CHECK(o.gmres_restart >= 1 && o.gmres_restart <= 128, BFM_EINVAL,
+              "gmres_restart must be in [1, 128]");
+    BFM_CHECK(o.gmres_maxit >= 1, BFM_EINVAL, "gmres_maxit must be >= 1");
+}
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        BFM_HIP(hipGetDevice(&prev));
+        if (prev != dev) BFM_HIP(hipSetDevice(dev));
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+static void invalidate_positions(bfm_ctx *c) {
+    c->geom_valid = false;
+    c->tree_valid = false;
+    c->diag_valid = false;
+}
+
+// Timing with HIP events on the handle's stream.
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st;
+    explicit Timer(hipStream_t s) : st(s) {
+        BFM_HIP(hipEventCreate(&a));
+        BFM_HIP(hipEventCreate(&b));
+        BFM_HIP(hipEventRecord(a, st));
+    }
+    double stop_ms() {
+        BFM_HIP(hipEventRecord(b, st));
+        BFM_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        BFM_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+static void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, bool use_guess,
+                       bfm_solve_info *info) {
+    bfm_solve_info loc{};
+    const int64_t n = c->nv;
+    {
+        Timer t(c->stream);
+        ensure_tree(c);
+        loc.t_tree_ms = t.stop_ms();
+    }
+    {
+        Timer t(c->stream);
+        diagonal_pass(c, phi_dev);
+        loc.t_diag_ms = t.stop_ms();
+    }
+    {
+        Timer t(c->stream);
+        double *x = c->x_s.ensure(n);
+        if (use_guess) to_sorted(c, q_dev, x);
+        gmres_sorted(c, x, use_guess, &loc);
+        to_original(c, x, q_dev);
+        loc.t_solve_ms = t.stop_ms();
+    }
+    if (info) *info = loc;
+    if (!loc.converged) fail(BFM_ENOCONV, "GMRES reached gmres_maxit before the tolerance");
+}
+
+}  // namespace bfm
+
+using namespace bfm;
+
+extern "C" {
+
+const char *bfm_last_error(void) { return g_last_error.c_str(); }
+
+int bfm_default_options(bfm_options *opt) {
+    if (!opt) return BFM_EINVAL;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->abi_version = BFM_ABI_VERSION;
+    opt->device = 0;
+    opt->stream = nullptr;
+    opt->p = 12;
+    opt->lmax = 0;
+    opt->leaf_target = 64;
+    opt->precision = BFM_PREC_FP64;
+    opt->gmres_tol = 1e-10;
+    opt->gmres_restart = 30;
+    opt->gmres_maxit = 300;
+    return BFM_OK;
+}
+
+int bfm_create(const bfm_options *opt, bfm_ctx **out) {
+    return guarded([&] {
+        BFM_CHECK(opt && out, BFM_EINVAL, "null argument");
+        check_options(*opt);
+        int ndev = 0;
+        BFM_HIP(hipGetDeviceCount(&ndev));
+        BFM_CHECK(opt->device >= 0 && opt->device < ndev, BFM_EINVAL, "device ordinal out of range");
+        DeviceScope ds(opt->device);
+        auto *c = new bfm_ctx();
+        c->opt = *opt;
+        c->device = opt->device;
+        if (opt->stream) {
+            c->stream = (hipStream_t)opt->stream;
+        } else {
+            hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                delete c;
+                fail(BFM_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+            }
+            c->own_stream = true;
+        }
+        *out = c;
+    });
+}
+
+int bfm_destroy(bfm_ctx *c) {
+    return guarded([&] {
+        if (!c) return;
+        DeviceScope ds(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        if (c->host_small) (void)hipHostFree(c->host_small);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+    });
+}
+
+int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
+    return guarded([&] {
+        BFM_CHECK(c && opt, BFM_EINVAL, "null argument");
+        check_options(*opt);
+        BFM_CHECK(opt->device == c->device, BFM_EINVAL, "cannot change the device of a handle");
+        const bool tree_change = opt->lmax != c->opt.lmax || opt->leaf_target != c->opt.leaf_target;
+        const bool p_change = opt->p != c->opt.p;
+        void *keep_stream = c->opt.stream;
+        c->opt = *opt;
+        c->opt.stream = keep_stream;
+        if (tree_change) {
+            c->tree_valid = false;
+            c->diag_valid = false;
+        }
+        if (p_change) c->diag_valid = false;
+    });
+}
+
+int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const int32_t *tri, int32_t nb,
+                 const int64_t *vtx_off, const int64_t *tri_off) {
+    return guarded([&] {
+        BFM_CHECK(c && xyz && tri, BFM_EINVAL, "null argument");
+        BFM_CHECK(nv >= 4 && nt >= 4, BFM_EINVAL, "a closed surface needs >= 4 vertices and triangles");
+        BFM_CHECK(nv < (int64_t)1 << 30 && nt < (int64_t)1 << 30, BFM_EINVAL, "mesh too large");
+        BFM_CHECK(nb >= 0, BFM_EINVAL, "negative bubble count");
+        if (nb > 1) BFM_CHECK(vtx_off && tri_off, BFM_EINVAL, "bubble ranges required when nb > 1");
+        DeviceScope ds(c->device);
+        std::vector<int64_t> vo, to;
+        if (nb >= 1 && vtx_off && tri_off) {
+            vo.assign(vtx_off, vtx_off + nb + 1);
+            to.assign(tri_off, tri_off + nb + 1);
+            BFM_CHECK(vo[0] == 0 && vo[nb] == nv && to[0] == 0 && to[nb] == nt, BFM_EINVAL,
+                      "bubble ranges must cover all vertices and triangles");
+            for (int b = 0; b < nb; ++b)
+                BFM_CHECK(vo[b + 1] > vo[b] && to[b + 1] > to[b], BFM_EINVAL, "empty bubble range");
+        }
+        // vertex -> triangle adjacency (ascending triangle index)
+        std::vector<int> cnt(nv + 1, 0);
+        for (int64_t k = 0; k < 3 * nt; ++k) {
+            const int v = tri[k];
+            BFM_CHECK(v >= 0 && v < nv, BFM_EMESH, "triangle vertex index out of range");
+            cnt[v + 1]++;
+        }
+        for (int64_t v = 0; v < nv; ++v) {
+            BFM_CHECK(cnt[v + 1] > 0, BFM_EMESH, "vertex " + std::to_string(v) + " is in no triangle");
+            cnt[v + 1] += cnt[v];
+        }
+        std::vector<int> adj(3 * nt), cur(cnt.begin(), cnt.end() - 1);
+        for (int64_t k = 0; k < nt; ++k)
+            for (int e = 0; e < 3; ++e) adj[cur[tri[3 * k + e]]++] = (int)k;
+        c->nv = nv;
+        c->nt = nt;
+        c->nb = nb;
+        c->vtx_off = vo;
+        c->tri_off = to;
+        c->xyz.ensure(3 * nv);
+        c->tri.ensure(3 * nt);
+        c->v2t_off.ensure(nv + 1);
+        c->v2t.ensure(3 * nt);
+        hipStream_t st = c->stream;
+        BFM_HIP(hipMemcpyAsync(c->xyz.get(), xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, st));
+        BFM_HIP(hipMemcpyAsync(c->tri.get(), tri, sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st));
+        BFM_HIP(hipMemcpyAsync(c->v2t_off.get(), cnt.data(), sizeof(int) * (nv + 1), hipMemcpyHostToDevice, st));
+        BFM_HIP(hipMemcpyAsync(c->v2t.get(), adj.data(), sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st));
+        BFM_HIP(hipStreamSynchronize(st));
+        invalidate_positions(c);
+    });
+}
+
+int bfm_set_positions(bfm_ctx *c, const double *xyz) {
+    return guarded([&] {
+        BFM_CHECK(c && xyz, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        BFM_HIP(hipMemcpyAsync(c->xyz.get(), xyz, sizeof(double) * 3 * c->nv, hipMemcpyHostToDevice,
+                               c->stream));
+        BFM_HIP(hipStreamSynchronize(c->stream));
+        invalidate_positions(c);
+    });
+}
+
+int bfm_set_positions_dev(bfm_ctx *c, const double *xyz) {
+    return guarded([&] {
+        BFM_CHECK(c && xyz, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        BFM_HIP(hipMemcpyAsync(c->xyz.get(), xyz, sizeof(double) * 3 * c->nv, hipMemcpyDeviceToDevice,
+                               c->stream));
+        invalidate_positions(c);
+    });
+}
+
+int bfm_geometry(bfm_ctx *c, double *s, double *n) {
+    return guarded([&] {
+        BFM_CHECK(c && s && n, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        ensure_geometry(c);
+        std::vector<double> tmp(3 * c->nv);
+        BFM_HIP(hipMemcpyAsync(s, c->s.get(), sizeof(double) * c->nv, hipMemcpyDeviceToHost, c->stream));
+        BFM_HIP(hipMemcpyAsync(tmp.data(), c->nrm.get(), sizeof(double) * 3 * c->nv, hipMemcpyDeviceToHost,
+                               c->stream));
+        BFM_HIP(hipStreamSynchronize(c->stream));
+        for (int64_t j = 0; j < c->nv; ++j)
+            for (int d = 0; d < 3; ++d) n[3 * j + d] = tmp[d * c->nv + j];
+    });
+}
+
+int bfm_diagonals(bfm_ctx *c, const double *phi, double *Mii, double *Lii, double *b) {
+    return guarded([&] {
+        BFM_CHECK(c && phi, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        const int64_t n = c->nv;
+        BFM_CHECK(n > 0, BFM_EINVAL, "no mesh set");
+        DevBuf<double> dphi, tmp;
+        dphi.ensure(n);
+        tmp.ensure(n);
+        BFM_HIP(hipMemcpyAsync(dphi.get(), phi, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        diagonal_pass(c, dphi.get());
+        double *outs[3] = {Mii, Lii, b};
+        const double *srcs[3] = {c->mii_s.get(), c->lii_s.get(), c->b_s.get()};
+        for (int k = 0; k < 3; ++k) {
+            if (!outs[k]) continue;
+            to_original(c, srcs[k], tmp.get());
+            BFM_HIP(hipMemcpyAsync(outs[k], tmp.get(), sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+            BFM_HIP(hipStreamSynchronize(c->stream));
+        }
+    });
+}
+
+int bfm_matvec(bfm_ctx *c, double f, const double *x, double g, const double *y, double *out,
+               int add_diag, int precision, int direct) {
+    return guarded([&] {
+        BFM_CHECK(c && out, BFM_EINVAL, "null argument");
+        BFM_CHECK(f == 0.0 || x, BFM_EINVAL, "x required when f != 0");
+        BFM_CHECK(g == 0.0 || y, BFM_EINVAL, "y required when g != 0");
+        DeviceScope ds(c->device);
+        const int64_t n = c->nv;
+        BFM_CHECK(n > 0, BFM_EINVAL, "no mesh set");
+        ensure_tree(c);
+        DevBuf<double> dx, dy, ds_, dout;
+        hipStream_t st = c->stream;
+        double *xs = nullptr, *ys = nullptr;
+        if (f != 0.0) {
+            dx.ensure(n);
+            xs = ds_.ensure(2 * n);
+            BFM_HIP(hipMemcpyAsync(dx.get(), x, sizeof(double) * n, hipMemcpyHostToDevice, st));
+            to_sorted(c, dx.get(), xs);
+        }
+        if (g != 0.0) {
+            dy.ensure(n);
+            if (!ds_.get()) ds_.ensure(2 * n);
+            ys = ds_.get() + n;
+            BFM_HIP(hipMemcpyAsync(dy.get(), y, sizeof(double) * n, hipMemcpyHostToDevice, st));
+            to_sorted(c, dy.get(), ys);
+        }
+        double *os = dout.ensure(2 * n);
+        matvec_sorted(c, f, xs, g, ys, os, add_diag != 0, precision, direct != 0);
+        to_original(c, os, os + n);
+        BFM_HIP(hipMemcpyAsync(out, os + n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
+    });
+}
+
+int bfm_solve_dev(bfm_ctx *c, const double *phi_dev, double *q_dev, int use_guess, bfm_solve_info *info) {
+    return guarded([&] {
+        BFM_CHECK(c && phi_dev && q_dev, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        solve_impl(c, phi_dev, q_dev, use_guess != 0, info);
+        BFM_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int bfm_solve(bfm_ctx *c, const double *phi, double *q, int use_guess, bfm_solve_info *info) {
+    int rc_solve = BFM_OK;
+    int rc = guarded([&] {
+        BFM_CHECK(c && phi && q, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        const int64_t n = c->nv;
+        DevBuf<double> buf;
+        buf.ensure(2 * n);
+        hipStream_t st = c->stream;
+        BFM_HIP(hipMemcpyAsync(buf.get(), phi, sizeof(double) * n, hipMemcpyHostToDevice, st));
+        if (use_guess)
+            BFM_HIP(hipMemcpyAsync(buf.get() + n, q, sizeof(double) * n, hipMemcpyHostToDevice, st));
+        try {
+            solve_impl(c, buf.get(), buf.get() + n, use_guess != 0, info);
+        } catch (const Error &e) {
+            if (e.code != BFM_ENOCONV) throw;
+            g_last_error = e.msg;
+            rc_solve = e.code;
+        }
+        BFM_HIP(hipMemcpyAsync(q, buf.get() + n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
+    });
+    return rc != BFM_OK ? rc : rc_solve;
+}
+
+int bfm_tree_stats(bfm_ctx *c, int64_t stats[8]) {
+    return guarded([&] {
+        BFM_CHECK(c && stats, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        ensure_tree(c);
+        const Tree &t = c->tree;
+        int64_t tr = 0;
+        for (size_t l = 0; l < t.m2m.size(); ++l)
+            if (t.m2m[l]) tr += t.m2m[l]->ntasks;
+        stats[0] = t.lmax;
+        stats[1] = t.nleaf;
+        stats[2] = t.nbox;
+        stats[3] = t.npairs_near;
+        stats[4] = t.m2l.ntasks;
+        stats[5] = 2 * tr;
+        stats[6] = t.max_leaf;
+        stats[7] = 0;
+    });
+}
+
+}  // extern "C"

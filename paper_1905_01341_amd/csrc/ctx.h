@@ -1,0 +1,66 @@
+// Library handle and the solve pipeline.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "fmm.h"
+#include "tree.h"
+
+struct bfm_ctx {
+    bfm_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    // mesh (original vertex order)
+    int64_t nv = 0, nt = 0;
+    int32_t nb = 0;
+    std::vector<int64_t> vtx_off, tri_off;
+    bfm::DevBuf<double> xyz;      // [nv][3]
+    bfm::DevBuf<int> tri;         // [nt][3]
+    bfm::DevBuf<int> v2t_off, v2t;  // vertex -> incident triangles (ascending)
+
+    // geometry (original order): s [nv], normals SoA [3][nv]
+    bfm::DevBuf<double> s, nrm, tri_hc, tri_area;
+    bfm::DevBuf<int> flag;
+    bool geom_valid = false;
+
+    bfm::Tree tree;
+    bool tree_valid = false;
+
+    bfm::FmmWork fmm;
+
+    // sorted-order solve data
+    bfm::DevBuf<double> src_q, src_mu;  // channel strengths
+    bfm::DevBuf<double> ysum;           // channel sums
+    bfm::DevBuf<double> mii_s, lii_s, b_s, phi_s;
+    bool diag_valid = false;            // mii_s / lii_s current for the mesh
+
+    // GMRES workspace (sorted order)
+    bfm::DevBuf<double> V, work, x_s, part, small;
+    double *host_small = nullptr;       // pinned
+};
+
+namespace bfm {
+
+void ensure_geometry(bfm_ctx *c);
+void ensure_tree(bfm_ctx *c);
+void ensure_ops(bfm_ctx *c);
+
+// Five-channel pass: M_ii, L_ii (sorted) and, if phi_dev != null, b (sorted).
+// phi_dev in original order.
+void diagonal_pass(bfm_ctx *c, const double *phi_dev);
+
+// out_s = f L x_s + g M y_s (+ diag) in sorted order; x_s, y_s sorted.
+void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const double *y_s,
+                   double *out_s, bool add_diag, int precision, bool direct);
+
+// GMRES in sorted order: solves L x = b_s, x_s in/out.
+void gmres_sorted(bfm_ctx *c, double *x_s, bool use_guess, bfm_solve_info *info);
+
+// gather (original -> sorted) and scatter (sorted -> original)
+void to_sorted(bfm_ctx *c, const double *in_orig, double *out_s);
+void to_original(bfm_ctx *c, const double *in_s, double *out_orig);
+
+}  // namespace bfm

@@ -1,0 +1,36 @@
+// Fast multipole product for the BEM operators (Section 3.9, eq3_27):
+// out_i = sum_{j != i} [ q_j / |r_i - r_j| + mu_j . (r_i - r_j) / |r_i - r_j|^3 ] / (4 pi)
+// for nch independent channels of monopole strengths q and dipole moments mu
+// over the same points. Point data are in the tree's sorted order.
+#pragma once
+
+#include "common.h"
+#include "tree.h"
+
+namespace bfm {
+
+struct Sources {
+    int nch = 1;
+    bool mono = true, dip = false;
+    const double *q = nullptr;   // [nch][n]
+    const double *mu = nullptr;  // [nch][3][n]
+};
+
+struct FmmWork {
+    int p = 0;
+    int nch_cap = 0;
+    int64_t nbox_cap = 0;
+    DevBuf<double> mexp, lexp;      // [nbox][nch][P]
+    DevBuf<double> ops_m2m, ops_l2l, ops_m2l;  // operators, column-major per op: [op][k][row]
+    int ops_p = 0;
+};
+
+// Build translation operators for p (host build + upload); no-op if current.
+void fmm_prepare_ops(FmmWork &w, int p, hipStream_t st);
+
+// y[c][i] (sorted order) = raw sums without the 1/(4 pi) factor.
+// direct = true: all-pairs sum (no tree approximation).
+void fmm_apply(FmmWork &w, const Tree &t, const Sources &src, double *y, bool direct,
+               hipStream_t st);
+
+}  // namespace bfm

@@ -1,0 +1,211 @@
+// Host construction of the translation operators (multipole-to-multipole,
+// multipole-to-local, local-to-local) as dense real P x P matrices in the
+// normalised, box-scaled basis of common.h.
+//
+// Scaling. A box of side h stores Mt_n^m = M_n^m nu_n^m / h^n (multipole)
+// and Lt_n^m = L_n^m h^{n+1} / nu_n^m (local), where M, L are the plain
+// coefficients of phi(r) = sum M_n^m I_n^m(r - c) = sum L_n^m R_n^m(r - c).
+// Then every operator depends only on the offset between box centres in
+// units of the box side, so one set serves every level:
+//   M2M (child side h, parent 2h, e = (c_child - c_parent)/h):
+//     Mt_n^m(parent) = 2^-n nu_n^m sum_{j,k} Mt_j^k conj(Rt_{n-j}^{m-k}(e)) / (nu_j^k nu_{n-j}^{m-k})
+//   M2L (both side h, d = (c_target - c_source)/h, |d|_inf in {2,3}):
+//     Lt_j^k = (-1)^{j+k} sum_{n,m} Mt_n^m It_{n+j}^{m-k}(d) nu_{n+j}^{m-k} / (nu_j^k nu_n^m)
+//   L2L (parent side 2h, child h, e = (c_child - c_parent)/h):
+//     Lt_j^k(child) = sum_{n,m} 2^-(n+1) Lt_n^m nu_n^m Rt_{n-j}^{m-k}(e) / (nu_{n-j}^{m-k} nu_j^k)
+// These follow from the addition theorem Rt-form of R_n^m(a + b) =
+// sum R_j^k(a) R_{n-j}^{m-k}(b) and I_n^m(D + rho) = sum (-1)^j
+// conj(R_j^k(rho)) I_{n+j}^{m+k}(D) (standard solid-harmonic translation
+// theorems for the Laplace kernel; the paper uses such expansions truncated
+// to degrees 0..p_fmm-1, Section 3.9).
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "common.h"
+#include "ops.h"
+#include "../../include/bfm_debug.h"
+
+namespace bfm {
+
+using cplx = std::complex<double>;
+
+static long double fact(int n) {
+    long double f = 1.0L;
+    for (int i = 2; i <= n; ++i) f *= (long double)i;
+    return f;
+}
+
+static double nu(int n, int m) {
+    if (m < 0) m = -m;
+    return (double)sqrtl(fact(n - m) * fact(n + m));
+}
+
+static inline int tri_index(int n, int m) { return n * (n + 1) / 2 + m; }
+
+// Regular (irregular = false) or irregular normalised harmonics of degrees
+// 0..nmax-1, orders m >= 0, at (x, y, z); out indexed by tri_index.
+static void harmonics(bool irregular, int nmax, double x, double y, double z, std::vector<cplx> &out) {
+    out.assign((size_t)nmax * (nmax + 1) / 2, cplx(0.0, 0.0));
+    const double r2 = x * x + y * y + z * z;
+    const cplx xy(x, y);
+    cplx diag = irregular ? cplx(1.0 / std::sqrt(r2), 0.0) : cplx(1.0, 0.0);
+    for (int m = 0; m < nmax; ++m) {
+        if (m > 0) {
+            double f = std::sqrt((2.0 * m - 1.0) / (2.0 * m));
+            diag = irregular ? diag * xy * (f / r2) : diag * xy * f;
+        }
+        out[tri_index(m, m)] = diag;
+        for (int n = m + 1; n < nmax; ++n) {
+            const double a = std::sqrt((double)(n - m) * (n + m));
+            const double b = (n - m - 1 > 0) ? std::sqrt((double)(n - m - 1) * (n + m - 1)) : 0.0;
+            cplx prev2 = (n - 2 >= m) ? out[tri_index(n - 2, m)] : cplx(0.0, 0.0);
+            cplx v;
+            if (irregular)
+                v = ((2.0 * n - 1.0) * z * out[tri_index(n - 1, m)] - b * prev2) / (r2 * a);
+            else
+                v = ((2.0 * n - 1.0) * z * out[tri_index(n - 1, m)] - r2 * b * prev2) / a;
+            out[tri_index(n, m)] = v;
+        }
+    }
+}
+
+// Value of order m (any sign) from the m >= 0 table.
+static cplx at(const std::vector<cplx> &t, int n, int m) {
+    if (m >= 0) return t[tri_index(n, m)];
+    cplx v = std::conj(t[tri_index(n, -m)]);
+    return ((-m) & 1) ? -v : v;
+}
+
+// Fill the real P x P matrix (row-major, T[row * P + col]) of the real-linear
+// map out_j^k = sum_{n,m} G(j, k, n, m) in_n^m over the full coefficient
+// set, given inputs and outputs in the packed layout of common.h.
+template <class Gfn>
+static void fill_real(int p, Gfn G, double *T) {
+    const int P = p * p;
+    for (int i = 0; i < P * P; ++i) T[i] = 0.0;
+    for (int j = 0; j < p; ++j) {
+        for (int k = 0; k <= j; ++k) {
+            const int row_re = (k == 0) ? j * j : j * j + 2 * k - 1;
+            const int row_im = j * j + 2 * k;
+            for (int n = 0; n < p; ++n) {
+                for (int m = 0; m <= n; ++m) {
+                    if (m == 0) {
+                        cplx c = G(j, k, n, 0);
+                        T[row_re * P + n * n] = c.real();
+                        if (k > 0) T[row_im * P + n * n] = c.imag();
+                    } else {
+                        const double sgn = (m & 1) ? -1.0 : 1.0;
+                        cplx gp = G(j, k, n, m), gm = G(j, k, n, -m);
+                        cplx cre = gp + sgn * gm;
+                        cplx cim = cplx(0.0, 1.0) * (gp - sgn * gm);
+                        const int col_re = n * n + 2 * m - 1, col_im = n * n + 2 * m;
+                        T[row_re * P + col_re] = cre.real();
+                        T[row_re * P + col_im] = cim.real();
+                        if (k > 0) {
+                            T[row_im * P + col_re] = cre.imag();
+                            T[row_im * P + col_im] = cim.imag();
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+static void octant_offset(int octant, double e[3]) {
+    e[0] = ((octant >> 2) & 1) ? 0.5 : -0.5;
+    e[1] = ((octant >> 1) & 1) ? 0.5 : -0.5;
+    e[2] = (octant & 1) ? 0.5 : -0.5;
+}
+
+void build_m2m(int p, int octant, double *T) {
+    double e[3];
+    octant_offset(octant, e);
+    std::vector<cplx> R;
+    harmonics(false, p, e[0], e[1], e[2], R);
+    auto G = [&](int n, int m, int j, int k) -> cplx {
+        // output (n, m) from input (j, k)
+        const int dn = n - j, dm = m - k;
+        if (dn < 0 || std::abs(dm) > dn) return cplx(0.0, 0.0);
+        return std::ldexp(1.0, -n) * nu(n, m) * std::conj(at(R, dn, dm)) / (nu(j, k) * nu(dn, dm));
+    };
+    fill_real(p, G, T);
+}
+
+void build_l2l(int p, int octant, double *T) {
+    double e[3];
+    octant_offset(octant, e);
+    std::vector<cplx> R;
+    harmonics(false, p, e[0], e[1], e[2], R);
+    auto G = [&](int j, int k, int n, int m) -> cplx {
+        const int dn = n - j, dm = m - k;
+        if (dn < 0 || std::abs(dm) > dn) return cplx(0.0, 0.0);
+        return std::ldexp(1.0, -(n + 1)) * nu(n, m) * at(R, dn, dm) / (nu(dn, dm) * nu(j, k));
+    };
+    fill_real(p, G, T);
+}
+
+int m2l_op_index(int dx, int dy, int dz) {
+    if (dx < -3 || dx > 3 || dy < -3 || dy > 3 || dz < -3 || dz > 3) return -1;
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) return -1;
+    int idx = 0;
+    for (int a = -3; a <= 3; ++a)
+        for (int b = -3; b <= 3; ++b)
+            for (int c = -3; c <= 3; ++c) {
+                if (a >= -1 && a <= 1 && b >= -1 && b <= 1 && c >= -1 && c <= 1) continue;
+                if (a == dx && b == dy && c == dz) return idx;
+                ++idx;
+            }
+    return -1;
+}
+
+void m2l_op_offset(int op, int d[3]) {
+    int idx = 0;
+    for (int a = -3; a <= 3; ++a)
+        for (int b = -3; b <= 3; ++b)
+            for (int c = -3; c <= 3; ++c) {
+                if (a >= -1 && a <= 1 && b >= -1 && b <= 1 && c >= -1 && c <= 1) continue;
+                if (idx == op) {
+                    d[0] = a;
+                    d[1] = b;
+                    d[2] = c;
+                    return;
+                }
+                ++idx;
+            }
+    d[0] = d[1] = d[2] = 0;
+}
+
+void build_m2l(int p, int op, double *T) {
+    int d[3];
+    m2l_op_offset(op, d);
+    std::vector<cplx> I;
+    harmonics(true, 2 * p - 1, (double)d[0], (double)d[1], (double)d[2], I);
+    auto G = [&](int j, int k, int n, int m) -> cplx {
+        const int sgn = ((j + k) & 1) ? -1 : 1;
+        return (double)sgn * at(I, n + j, m - k) * nu(n + j, m - k) / (nu(j, k) * nu(n, m));
+    };
+    fill_real(p, G, T);
+}
+
+}  // namespace bfm
+
+extern "C" int bfm_debug_operator(int p, int kind, int index, double *out, int *d_out) {
+    if (!out || p < 1 || p > bfm::kMaxP) return BFM_EINVAL;
+    if (kind == 0 || kind == 1) {
+        if (index < 0 || index > 7) return BFM_EINVAL;
+        if (kind == 0)
+            bfm::build_m2m(p, index, out);
+        else
+            bfm::build_l2l(p, index, out);
+        return BFM_OK;
+    }
+    if (kind == 2) {
+        if (index < 0 || index >= bfm::kNumM2LOps) return BFM_EINVAL;
+        bfm::build_m2l(p, index, out);
+        if (d_out) bfm::m2l_op_offset(index, d_out);
+        return BFM_OK;
+    }
+    return BFM_EINVAL;
+}

@@ -1,0 +1,535 @@
+// Geometry (ns1), the singular diagonals and right-hand side (s3, s5,
+// eq3_1), the product with L (eq3_27) and restarted GMRES (Section 3.8),
+// all on the handle's stream. Solve vectors live in the octree's sorted
+// point order so that the fast multipole product needs no gather/scatter.
+#include <cmath>
+#include <vector>
+
+#include "ctx.h"
+
+namespace bfm {
+
+static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------
+// Geometry (Section 3.2, ns1): per triangle c = (r2 - r1) x (r3 - r1),
+// A = |c|/2, N A = c/2; per vertex s = sum A/3, n = (sum N A)/|sum N A|.
+
+__global__ void k_tri_geom(const double *xyz, const int *tri, int64_t nt, int64_t nv, double *hc,
+                           double *area, int *flag) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nt) return;
+    const int a = tri[3 * k], b = tri[3 * k + 1], c = tri[3 * k + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) {
+        atomicOr(flag, 2);
+        hc[3 * k] = hc[3 * k + 1] = hc[3 * k + 2] = 0.0;
+        area[k] = 0.0;
+        return;
+    }
+    const double e1x = xyz[3 * b] - xyz[3 * a], e1y = xyz[3 * b + 1] - xyz[3 * a + 1],
+                 e1z = xyz[3 * b + 2] - xyz[3 * a + 2];
+    const double e2x = xyz[3 * c] - xyz[3 * a], e2y = xyz[3 * c + 1] - xyz[3 * a + 1],
+                 e2z = xyz[3 * c + 2] - xyz[3 * a + 2];
+    const double cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
+    const double len = sqrt(cx * cx + cy * cy + cz * cz);
+    if (!(len > 0.0)) atomicOr(flag, 1);
+    hc[3 * k] = 0.5 * cx;
+    hc[3 * k + 1] = 0.5 * cy;
+    hc[3 * k + 2] = 0.5 * cz;
+    area[k] = 0.5 * len;
+}
+
+__global__ void k_vertex_geom(const int *v2t_off, const int *v2t, const double *hc, const double *area,
+                              int64_t nv, double *s, double *nrm, int *flag) {
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    double sa = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    for (int e = v2t_off[j]; e < v2t_off[j + 1]; ++e) {
+        const int k = v2t[e];
+        sa += area[k];
+        mx += hc[3 * (int64_t)k];
+        my += hc[3 * (int64_t)k + 1];
+        mz += hc[3 * (int64_t)k + 2];
+    }
+    const double len = sqrt(mx * mx + my * my + mz * mz);
+    if (!(len > 0.0)) atomicOr(flag, 4);
+    const double il = (len > 0.0) ? 1.0 / len : 0.0;
+    s[j] = sa / 3.0;
+    nrm[j] = mx * il;
+    nrm[nv + j] = my * il;
+    nrm[2 * nv + j] = mz * il;
+}
+
+void ensure_geometry(bfm_ctx *c) {
+    if (c->geom_valid) return;
+    BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+    hipStream_t st = c->stream;
+    c->s.ensure(c->nv);
+    c->nrm.ensure(3 * c->nv);
+    c->tri_hc.ensure(3 * c->nt);
+    c->tri_area.ensure(c->nt);
+    int *flag = c->flag.ensure(1);
+    BFM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    k_tri_geom<<<nblk(c->nt, 256), 256, 0, st>>>(c->xyz.get(), c->tri.get(), c->nt, c->nv,
+                                                 c->tri_hc.get(), c->tri_area.get(), flag);
+    BFM_LAUNCHED();
+    k_vertex_geom<<<nblk(c->nv, 256), 256, 0, st>>>(c->v2t_off.get(), c->v2t.get(), c->tri_hc.get(),
+                                                    c->tri_area.get(), c->nv, c->s.get(), c->nrm.get(),
+                                                    flag);
+    BFM_LAUNCHED();
+    int hf = 0;
+    BFM_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    BFM_CHECK(!(hf & 2), BFM_EMESH, "triangle vertex index out of range");
+    BFM_CHECK(!(hf & 1), BFM_EMESH, "degenerate (zero-area) triangle");
+    BFM_CHECK(!(hf & 4), BFM_EMESH, "vertex with vanishing area-weighted normal");
+    c->geom_valid = true;
+}
+
+void ensure_tree(bfm_ctx *c) {
+    ensure_geometry(c);
+    if (c->tree_valid) return;
+    build_tree(c->tree, c->xyz.get(), c->nv, c->opt.lmax, c->opt.leaf_target, c->stream);
+    sort_geometry(c->tree, c->s.get(), c->nrm.get(), c->stream);
+    c->tree_valid = true;
+    c->diag_valid = false;
+}
+
+void ensure_ops(bfm_ctx *c) {
+    c->fmm.p = c->opt.p;
+    fmm_prepare_ops(c->fmm, c->opt.p, c->stream);
+}
+
+// ---------------------------------------------------------------------------
+// Permutations
+
+__global__ void k_gather(const double *in, const int *perm, int64_t n, double *out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[perm[i]];
+}
+
+__global__ void k_scatter(const double *in, const int *perm, int64_t n, double *out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[perm[i]] = in[i];
+}
+
+void to_sorted(bfm_ctx *c, const double *in, double *out) {
+    k_gather<<<nblk(c->nv, 256), 256, 0, c->stream>>>(in, c->tree.idx_a.get(), c->nv, out);
+    BFM_LAUNCHED();
+}
+
+void to_original(bfm_ctx *c, const double *in, double *out) {
+    k_scatter<<<nblk(c->nv, 256), 256, 0, c->stream>>>(in, c->tree.idx_a.get(), c->nv, out);
+    BFM_LAUNCHED();
+}
+
+// ---------------------------------------------------------------------------
+// Diagonals + right-hand side: five channels over the same points,
+// coordinates taken relative to the cube centre X:
+//   ch0: mu = s n                       -> sum M_ij
+//   ch1..3: q = -s n_a, mu = s n r_a    -> sum M_ij r_ja - sum L_ij n_ja
+//   ch4: mu = s phi n                   -> sum M_ij phi_j
+
+__global__ void k_diag_sources(const double *px, const double *py, const double *pz, const double *ps,
+                               const double *pnx, const double *pny, const double *pnz,
+                               const double *phi, int64_t n, double X, double Y, double Z, double *q,
+                               double *mu) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = ps[i];
+    const double nn[3] = {pnx[i], pny[i], pnz[i]};
+    const double r[3] = {px[i] - X, py[i] - Y, pz[i] - Z};
+    const double f = phi ? phi[i] : 0.0;
+    q[i] = 0.0;
+    q[4 * n + i] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        mu[(0 * 3 + d) * n + i] = s * nn[d];
+        mu[(4 * 3 + d) * n + i] = s * f * nn[d];
+    }
+    for (int a = 0; a < 3; ++a) {
+        q[(1 + a) * n + i] = -s * nn[a];
+        for (int d = 0; d < 3; ++d) mu[((1 + a) * 3 + d) * n + i] = s * nn[d] * r[a];
+    }
+}
+
+__global__ void k_diag_finalize(const double *y, const double *px, const double *py, const double *pz,
+                                const double *pnx, const double *pny, const double *pnz,
+                                const double *phi, int64_t n, double X, double Y, double Z,
+                                double *mii, double *lii, double *b) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double SM = kInv4Pi * y[i];
+    const double r[3] = {px[i] - X, py[i] - Y, pz[i] - Z};
+    const double nn[3] = {pnx[i], pny[i], pnz[i]};
+    double L = 0.0;
+    for (int a = 0; a < 3; ++a) L += nn[a] * (kInv4Pi * y[(1 + a) * n + i] - r[a] * SM);
+    mii[i] = -0.5 - SM;
+    lii[i] = L;
+    if (phi) b[i] = -phi[i] * (1.0 + SM) + kInv4Pi * y[4 * n + i];
+}
+
+void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
+    ensure_tree(c);
+    ensure_ops(c);
+    hipStream_t st = c->stream;
+    Tree &t = c->tree;
+    const int64_t n = c->nv;
+    const double X = t.origin[0] + 0.5 * t.side, Y = t.origin[1] + 0.5 * t.side,
+                 Z = t.origin[2] + 0.5 * t.side;
+    double *phs = nullptr;
+    if (phi_dev) {
+        phs = c->phi_s.ensure(n);
+        to_sorted(c, phi_dev, phs);
+    }
+    double *q = c->src_q.ensure(5 * n);
+    double *mu = c->src_mu.ensure(15 * n);
+    double *y = c->ysum.ensure(5 * n);
+    k_diag_sources<<<nblk(n, 256), 256, 0, st>>>(t.px.get(), t.py.get(), t.pz.get(), t.ps.get(),
+                                                 t.pnx.get(), t.pny.get(), t.pnz.get(), phs, n, X, Y, Z,
+                                                 q, mu);
+    BFM_LAUNCHED();
+    Sources src;
+    src.nch = 5;
+    src.mono = true;
+    src.dip = true;
+    src.q = q;
+    src.mu = mu;
+    fmm_apply(c->fmm, t, src, y, false, st);
+    c->mii_s.ensure(n);
+    c->lii_s.ensure(n);
+    c->b_s.ensure(n);
+    k_diag_finalize<<<nblk(n, 256), 256, 0, st>>>(y, t.px.get(), t.py.get(), t.pz.get(), t.pnx.get(),
+                                                  t.pny.get(), t.pnz.get(), phs, n, X, Y, Z,
+                                                  c->mii_s.get(), c->lii_s.get(), c->b_s.get());
+    BFM_LAUNCHED();
+    c->diag_valid = true;
+}
+
+// ---------------------------------------------------------------------------
+// Product with A = f L + g M (eq3_27), sorted order.
+
+__global__ void k_sources_1ch(const double *ps, const double *pnx, const double *pny, const double *pnz,
+                              int64_t n, double f, const double *x, double g, const double *yv,
+                              double *q, double *mu) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = ps[i];
+    if (x) q[i] = f * s * x[i];
+    if (yv) {
+        const double w = g * s * yv[i];
+        mu[i] = w * pnx[i];
+        mu[n + i] = w * pny[i];
+        mu[2 * n + i] = w * pnz[i];
+    }
+}
+
+__global__ void k_finalize_1ch(const double *y, int64_t n, double f, const double *x, double g,
+                               const double *yv, const double *lii, const double *mii, double *out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = kInv4Pi * y[i];
+    if (lii && x) v += f * lii[i] * x[i];
+    if (mii && yv) v += g * mii[i] * yv[i];
+    out[i] = v;
+}
+
+void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const double *y_s, double *out_s,
+                   bool add_diag, int precision, bool direct) {
+    BFM_CHECK(precision == BFM_PREC_FP64, BFM_EUNSUPPORTED, "only FP64 products are built");
+    ensure_tree(c);
+    if (!direct) ensure_ops(c);
+    if (add_diag && !c->diag_valid) diagonal_pass(c, nullptr);
+    hipStream_t st = c->stream;
+    Tree &t = c->tree;
+    const int64_t n = c->nv;
+    const bool mono = (f != 0.0 && x_s), dip = (g != 0.0 && y_s);
+    double *q = c->src_q.ensure(5 * n);
+    double *mu = c->src_mu.ensure(15 * n);
+    double *y = c->ysum.ensure(5 * n);
+    if (!mono && !dip) {
+        BFM_HIP(hipMemsetAsync(out_s, 0, sizeof(double) * n, st));
+        return;
+    }
+    k_sources_1ch<<<nblk(n, 256), 256, 0, st>>>(t.ps.get(), t.pnx.get(), t.pny.get(), t.pnz.get(), n, f,
+                                                mono ? x_s : nullptr, g, dip ? y_s : nullptr, q, mu);
+    BFM_LAUNCHED();
+    Sources src;
+    src.nch = 1;
+    src.mono = mono;
+    src.dip = dip;
+    src.q = q;
+    src.mu = mu;
+    fmm_apply(c->fmm, t, src, y, direct, st);
+    k_finalize_1ch<<<nblk(n, 256), 256, 0, st>>>(y, n, f, mono ? x_s : nullptr, g, dip ? y_s : nullptr,
+                                                 add_diag ? c->lii_s.get() : nullptr,
+                                                 add_diag ? c->mii_s.get() : nullptr, out_s);
+    BFM_LAUNCHED();
+}
+
+// ---------------------------------------------------------------------------
+// GMRES (restarted, classical Gram-Schmidt with one reorthogonalisation,
+// Givens rotations on the device). Reductions are two-stage with a fixed
+// block count, so sums are bitwise reproducible run to run.
+
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+// part[k * kRedBlocks + blk] = partial of sum_i V[k][i] w[i], k in [0, nv)
+__global__ void __launch_bounds__(kRedThreads) k_mdot(const double *V, int nvec, int64_t ld,
+                                                      const double *w, int64_t n, double *part) {
+    __shared__ double red[8][kRedThreads];
+    for (int k0 = 0; k0 < nvec; k0 += 8) {
+        const int kn = (nvec - k0) < 8 ? (nvec - k0) : 8;
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n;
+             i += (int64_t)kRedBlocks * kRedThreads) {
+            const double wi = w[i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u < kn) acc[u] += V[(k0 + u) * ld + i] * wi;
+        }
+        for (int u = 0; u < 8; ++u) red[u][threadIdx.x] = acc[u];
+        __syncthreads();
+        for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s)
+                for (int u = 0; u < 8; ++u) red[u][threadIdx.x] += red[u][threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x < (unsigned)kn) part[(k0 + threadIdx.x) * kRedBlocks + blockIdx.x] = red[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+// out[k] = sum_b part[k * kRedBlocks + b] (+ out[k] if accumulate)
+__global__ void __launch_bounds__(kRedThreads) k_reduce(const double *part, int nvec, double *out,
+                                                        int accumulate) {
+    __shared__ double red[kRedThreads];
+    const int k = blockIdx.x;
+    if (k >= nvec) return;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < kRedBlocks; b += kRedThreads) a += part[k * kRedBlocks + b];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0] + (accumulate ? out[k] : 0.0);
+}
+
+// w[i] -= sum_k V[k][i] h[k]
+__global__ void k_update(const double *V, int nvec, int64_t ld, const double *h, double *w, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = w[i];
+    for (int k = 0; k < nvec; ++k) v -= V[k * ld + i] * h[k];
+    w[i] = v;
+}
+
+// x[i] += sum_k V[k][i] y[k]
+__global__ void k_combine(const double *V, int nvec, int64_t ld, const double *yv, double *x, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = x[i];
+    for (int k = 0; k < nvec; ++k) v += V[k * ld + i] * yv[k];
+    x[i] = v;
+}
+
+__global__ void k_scale_by(double *v, int64_t n, const double *s) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) v[i] *= s[0];
+}
+
+// v = (b - v) / ||.|| helper pieces
+__global__ void k_sub_from(const double *b, double *v, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) v[i] = b[i] - v[i];
+}
+
+__global__ void k_copy(const double *a, double *b, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// Small-state layout (doubles) for restart m:
+//   H  [(m+1) * m] column-major, cs [m], sn [m], g [m+1], yv [m],
+//   h1 [m+1], h2 [m+1], nrm [1], scal [4]
+struct SmallLayout {
+    int m;
+    int64_t H, cs, sn, g, yv, h1, h2, nrm, scal, total;
+    explicit SmallLayout(int m_) : m(m_) {
+        H = 0;
+        cs = H + (int64_t)(m + 1) * m;
+        sn = cs + m;
+        g = sn + m;
+        yv = g + m + 1;
+        h1 = yv + m;
+        h2 = h1 + m + 1;
+        nrm = h2 + m + 1;
+        scal = nrm + 1;
+        total = scal + 4;
+    }
+};
+
+// Column j of H from the two Gram-Schmidt passes; apply the previous
+// rotations, form rotation j, update g; scal[0] = |g[j+1]| (residual
+// estimate), scal[1] = 1/H[j+1][j] (0 on breakdown).
+__global__ void k_givens(double *sm, SmallLayout L, int j) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int m = L.m;
+    double *H = sm + L.H + (int64_t)(m + 1) * j;
+    double *cs = sm + L.cs, *sn = sm + L.sn, *g = sm + L.g;
+    for (int i = 0; i <= j; ++i) H[i] = sm[L.h1 + i] + sm[L.h2 + i];
+    const double beta = sqrt(fmax(sm[L.nrm], 0.0));
+    H[j + 1] = beta;
+    sm[L.scal + 1] = (beta > 0.0) ? 1.0 / beta : 0.0;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * H[i] + sn[i] * H[i + 1];
+        H[i + 1] = -sn[i] * H[i] + cs[i] * H[i + 1];
+        H[i] = t;
+    }
+    const double den = hypot(H[j], H[j + 1]);
+    const double cj = (den > 0.0) ? H[j] / den : 1.0;
+    const double sj = (den > 0.0) ? H[j + 1] / den : 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    H[j] = den;
+    H[j + 1] = 0.0;
+    g[j + 1] = -sj * g[j];
+    g[j] = cj * g[j];
+    sm[L.scal] = fabs(g[j + 1]);
+}
+
+// Solve the k x k upper triangle H y = g.
+__global__ void k_trisolve(double *sm, SmallLayout L, int k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int m = L.m;
+    double *yv = sm + L.yv;
+    for (int i = k - 1; i >= 0; --i) {
+        double v = sm[L.g + i];
+        for (int c = i + 1; c < k; ++c) v -= sm[L.H + (int64_t)(m + 1) * c + i] * yv[c];
+        const double d = sm[L.H + (int64_t)(m + 1) * i + i];
+        yv[i] = (d != 0.0) ? v / d : 0.0;
+    }
+}
+
+__global__ void k_restart_state(double *sm, SmallLayout L) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // g = [beta, 0, ...], scal[1] = 1/beta; beta from nrm
+    const double beta = sqrt(fmax(sm[L.nrm], 0.0));
+    for (int i = 0; i <= L.m; ++i) sm[L.g + i] = 0.0;
+    sm[L.g] = beta;
+    sm[L.scal + 1] = (beta > 0.0) ? 1.0 / beta : 0.0;
+    sm[L.scal + 2] = beta;
+}
+
+void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nv;
+    const int m = c->opt.gmres_restart;
+    const int maxit = c->opt.gmres_maxit;
+    const double tol = c->opt.gmres_tol;
+    const int prec = c->opt.precision;
+    SmallLayout L(m);
+    double *V = c->V.ensure((size_t)(m + 1) * n);
+    double *w = c->work.ensure(n);
+    double *part = c->part.ensure((size_t)(m + 2) * kRedBlocks);
+    double *sm = c->small.ensure(L.total);
+    if (!c->host_small) BFM_HIP(hipHostMalloc((void **)&c->host_small, 8 * sizeof(double), 0));
+    double *hs = c->host_small;
+    const double *b = c->b_s.get();
+    auto norm2_to = [&](const double *v, int64_t off) {  // sm[off] = ||v||^2
+        k_mdot<<<kRedBlocks, kRedThreads, 0, st>>>(v, 1, n, v, n, part);
+        BFM_LAUNCHED();
+        k_reduce<<<1, kRedThreads, 0, st>>>(part, 1, sm + off, 0);
+        BFM_LAUNCHED();
+    };
+    auto read_scalar = [&](int64_t off) {
+        BFM_HIP(hipMemcpyAsync(hs, sm + off, sizeof(double), hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
+        return hs[0];
+    };
+    int matvecs = 0;
+    // ||b||
+    norm2_to(b, L.nrm);
+    const double nb = std::sqrt(std::max(read_scalar(L.nrm), 0.0));
+    info->iterations = 0;
+    info->restarts = 0;
+    if (!(nb > 0.0)) {
+        BFM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+        info->rel_residual = 0.0;
+        info->converged = 1;
+        info->matvecs = 0;
+        return;
+    }
+    // r0
+    if (use_guess) {
+        matvec_sorted(c, 1.0, x, 0.0, nullptr, V, true, prec, false);
+        ++matvecs;
+        k_sub_from<<<nblk(n, 256), 256, 0, st>>>(b, V, n);
+        BFM_LAUNCHED();
+    } else {
+        BFM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+        k_copy<<<nblk(n, 256), 256, 0, st>>>(b, V, n);
+        BFM_LAUNCHED();
+    }
+    norm2_to(V, L.nrm);
+    double beta = std::sqrt(std::max(read_scalar(L.nrm), 0.0));
+    int it = 0;
+    bool conv = beta <= tol * nb;
+    while (!conv && it < maxit) {
+        k_restart_state<<<1, 1, 0, st>>>(sm, L);
+        BFM_LAUNCHED();
+        k_scale_by<<<nblk(n, 256), 256, 0, st>>>(V, n, sm + L.scal + 1);
+        BFM_LAUNCHED();
+        int k = 0;
+        for (int j = 0; j < m && it < maxit; ++j) {
+            double *vj = V + (int64_t)j * n;
+            double *wj = V + (int64_t)(j + 1) * n;
+            matvec_sorted(c, 1.0, vj, 0.0, nullptr, wj, true, prec, false);
+            ++matvecs;
+            // pass 1
+            k_mdot<<<kRedBlocks, kRedThreads, 0, st>>>(V, j + 1, n, wj, n, part);
+            BFM_LAUNCHED();
+            k_reduce<<<j + 1, kRedThreads, 0, st>>>(part, j + 1, sm + L.h1, 0);
+            BFM_LAUNCHED();
+            k_update<<<nblk(n, 256), 256, 0, st>>>(V, j + 1, n, sm + L.h1, wj, n);
+            BFM_LAUNCHED();
+            // pass 2
+            k_mdot<<<kRedBlocks, kRedThreads, 0, st>>>(V, j + 1, n, wj, n, part);
+            BFM_LAUNCHED();
+            k_reduce<<<j + 1, kRedThreads, 0, st>>>(part, j + 1, sm + L.h2, 0);
+            BFM_LAUNCHED();
+            k_update<<<nblk(n, 256), 256, 0, st>>>(V, j + 1, n, sm + L.h2, wj, n);
+            BFM_LAUNCHED();
+            norm2_to(wj, L.nrm);
+            k_givens<<<1, 1, 0, st>>>(sm, L, j);
+            BFM_LAUNCHED();
+            k_scale_by<<<nblk(n, 256), 256, 0, st>>>(wj, n, sm + L.scal + 1);
+            BFM_LAUNCHED();
+            ++it;
+            k = j + 1;
+            const double res = read_scalar(L.scal);
+            if (res <= tol * nb) break;
+        }
+        k_trisolve<<<1, 1, 0, st>>>(sm, L, k);
+        BFM_LAUNCHED();
+        k_combine<<<nblk(n, 256), 256, 0, st>>>(V, k, n, sm + L.yv, x, n);
+        BFM_LAUNCHED();
+        // true residual
+        matvec_sorted(c, 1.0, x, 0.0, nullptr, V, true, prec, false);
+        ++matvecs;
+        k_sub_from<<<nblk(n, 256), 256, 0, st>>>(b, V, n);
+        BFM_LAUNCHED();
+        norm2_to(V, L.nrm);
+        beta = std::sqrt(std::max(read_scalar(L.nrm), 0.0));
+        info->restarts += 1;
+        conv = beta <= tol * nb;
+    }
+    info->iterations = it;
+    info->matvecs = matvecs;
+    info->rel_residual = beta / nb;
+    info->converged = conv ? 1 : 0;
+}
+
+}  // namespace bfm

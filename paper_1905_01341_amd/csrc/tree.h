@@ -1,0 +1,81 @@
+// Octree over the collocation points (Section 3.9): the bounding cube is
+// split recursively to level lmax, empty boxes are skipped, points are
+// ordered by Morton key (bit interleaving) so that every box owns a
+// contiguous point range at every level.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace bfm {
+
+constexpr int kKeyBits = 15;  // bits per axis of the point keys (levels 0..15)
+
+// Translation tasks grouped by operator: tasks op_off[o]..op_off[o+1] use
+// operator o; task t moves expansion src[t] into expansion dst[t] (global
+// box indices). tile_off[o] counts 16-column wave tiles for a given channel
+// count (see fmm.hip), prepared per channel count on demand.
+struct TaskList {
+    int nops = 0;
+    int64_t ntasks = 0;
+    std::vector<int> op_off_h;  // host copy [nops + 1]
+    DevBuf<int> op_off;         // [nops + 1]
+    DevBuf<int> src, dst;       // [ntasks]
+    // wave-tile prefix per channel count (index = nch), built lazily
+    DevBuf<int> tile_off[8];
+    int ntiles[8] = {0};
+    bool tiles_ready[8] = {false};
+};
+
+struct Tree {
+    bool valid = false;
+    int lmax = 0;
+    double origin[3] = {0, 0, 0};
+    double side = 1.0;
+    int64_t n = 0;       // points
+    int64_t nbox = 0;    // boxes over all levels
+    int64_t nleaf = 0;   // boxes at level lmax
+    int64_t npairs_near = 0;
+    int max_leaf = 0;
+    std::vector<int64_t> lvl_off;  // host [lmax + 2]: boxes of level l are lvl_off[l]..lvl_off[l+1]
+
+    DevBuf<uint64_t> key_a, key_b;  // point keys (sorted result in key_a)
+    DevBuf<int> idx_a, idx_b;       // point permutation (sorted -> original) in idx_a
+    DevBuf<int> iperm;              // original -> sorted
+
+    DevBuf<uint64_t> box_key;   // [nbox] key at the box's own level
+    DevBuf<int> box_level;      // [nbox]
+    DevBuf<int> box_pt0;        // [nbox + 1] first sorted point of each box (per level, + sentinel)
+    DevBuf<int> box_parent;     // [nbox]  (-1 at level 0)
+    DevBuf<double> box_centre;  // [nbox][3]
+    DevBuf<int> nbr;            // [nbox][27] neighbours (incl. self at slot 13), -1 if empty
+    DevBuf<int> leaf_pt;        // [nleaf + 1] point ranges of leaves
+
+    // sorted point data (per tree): positions, weights, normals
+    DevBuf<double> px, py, pz;  // [n]
+    DevBuf<double> ps, pnx, pny, pnz;
+
+    TaskList m2l;                   // all levels 2..lmax
+    std::vector<TaskList *> m2m;    // per level l = 3..lmax: child (level l) -> parent
+    ~Tree() {
+        for (auto *t : m2m) delete t;
+    }
+};
+
+// Build (or rebuild) the tree for the points xyz (device, [n][3] AoS).
+// lmax_req > 0 fixes the depth; otherwise the deepest level whose mean leaf
+// occupancy is >= leaf_target is used (at least 2).
+void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target,
+                hipStream_t st);
+
+// Sorted-order copies of per-vertex geometry (s, n SoA in original order).
+void sort_geometry(Tree &t, const double *s, const double *nrm, hipStream_t st);
+
+// Build the wave-tile prefix of a task list for a channel count.
+void prepare_tiles(TaskList &tl, int nch, hipStream_t st);
+
+// Device-wide exclusive scan of int32 (in place allowed); returns the total.
+int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp);
+
+}  // namespace bfm

@@ -1,0 +1,720 @@
+// Octree construction on the GPU (Section 3.9: cube scaling, level-wise
+// subdivision, empty boxes skipped, bit interleaving + sort, neighbour and
+// interaction lists, built once per mesh).
+//
+// Steps: bounding cube -> 45-bit Morton keys (15 bits per axis) -> stable
+// LSD radix sort of (key, point) in six 8-bit passes -> per-level unique
+// prefixes (boxes) by flag + scan -> parent / child / neighbour tables by
+// binary search in the sorted per-level key arrays -> M2L pairs (children
+// of the parent's neighbours that are not adjacent) and M2M/L2L pairs,
+// grouped by translation operator.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "ops.h"
+#include "tree.h"
+
+namespace bfm {
+
+// ---------------------------------------------------------------------------
+// Morton keys
+
+__host__ __device__ inline uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;  // up to 21 bits
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__host__ __device__ inline uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+// key = ... x_b y_b z_b ... (x in the highest bit of every triple)
+__host__ __device__ inline uint64_t morton(uint32_t ix, uint32_t iy, uint32_t iz) {
+    return (spread3(ix) << 2) | (spread3(iy) << 1) | spread3(iz);
+}
+
+__host__ __device__ inline void demorton(uint64_t k, int &ix, int &iy, int &iz) {
+    ix = (int)compact3(k >> 2);
+    iy = (int)compact3(k >> 1);
+    iz = (int)compact3(k);
+}
+
+// ---------------------------------------------------------------------------
+// Bounding box
+
+__global__ void k_bbox_partial(const double *xyz, int64_t n, double *part) {
+    __shared__ double smin[3][256], smax[3][256];
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int d = 0; d < 3; ++d) {
+            double v = xyz[3 * i + d];
+            mn[d] = fmin(mn[d], v);
+            mx[d] = fmax(mx[d], v);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        smin[d][threadIdx.x] = mn[d];
+        smax[d][threadIdx.x] = mx[d];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int d = 0; d < 3; ++d) {
+                smin[d][threadIdx.x] = fmin(smin[d][threadIdx.x], smin[d][threadIdx.x + s]);
+                smax[d][threadIdx.x] = fmax(smax[d][threadIdx.x], smax[d][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) {
+            part[6 * blockIdx.x + d] = smin[d][0];
+            part[6 * blockIdx.x + 3 + d] = smax[d][0];
+        }
+}
+
+__global__ void k_morton(const double *xyz, int64_t n, double ox, double oy, double oz,
+                         double inv_cell, uint64_t *key, int *idx) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int lim = (1 << kKeyBits) - 1;
+    int c[3];
+    const double o[3] = {ox, oy, oz};
+    for (int d = 0; d < 3; ++d) {
+        double f = floor((xyz[3 * i + d] - o[d]) * inv_cell);
+        int v = (int)fmin(fmax(f, 0.0), (double)lim);
+        c[d] = v;
+    }
+    key[i] = morton(c[0], c[1], c[2]);
+    idx[i] = (int)i;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (uint64 key, int value), 8 bits per pass.
+// Tiles of 4096 items per 256-thread block; each wave ranks its 1024-item
+// segment in order with ballot-based digit matching, so equal digits keep
+// their input order (stability).
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_TILE = 4096;
+constexpr int RS_SEG = 1024;  // per wave
+constexpr int RS_ROUNDS = RS_SEG / 64;
+
+__global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, int64_t n, int shift,
+                                                        int *hist, int nblocks) {
+    __shared__ int cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int k = 0; k < RS_TILE / RS_THREADS; ++k) {
+        int64_t i = base + k * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, const int *vin,
+                                                           int64_t n, int shift, const int *scanned,
+                                                           int nblocks, uint64_t *kout, int *vout) {
+    __shared__ int wcnt[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < 4 * 256; d += RS_THREADS) (&wcnt[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t seg = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_SEG;
+    uint64_t kreg[RS_ROUNDS];
+    int vreg[RS_ROUNDS], pos[RS_ROUNDS];
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int64_t i = seg + r * 64 + lane;
+        const bool ok = i < n;
+        kreg[r] = ok ? kin[i] : 0;
+        vreg[r] = ok ? vin[i] : 0;
+        const int d = ok ? (int)((kreg[r] >> shift) & 255) : 256;
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bal = __ballot(ok && ((d >> b) & 1));
+            peers &= ((d >> b) & 1) ? bal : ~bal;
+        }
+        int base = 0;
+        if (ok) base = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        const int rank = __popcll(peers & lt);
+        pos[r] = base + rank;
+        if (ok && rank == 0) wcnt[w][d] = base + __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {  // exclusive prefix over the 4 waves for digit d = threadIdx.x
+        const int d = threadIdx.x;
+        int run = 0;
+        for (int ww = 0; ww < 4; ++ww) {
+            int t = wcnt[ww][d];
+            wcnt[ww][d] = run + scanned[d * nblocks + blockIdx.x];
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int64_t i = seg + r * 64 + lane;
+        if (i < n) {
+            const int d = (int)((kreg[r] >> shift) & 255);
+            const int p = wcnt[w][d] + pos[r];
+            kout[p] = kreg[r];
+            vout[p] = vreg[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan (int32)
+
+constexpr int SC_THREADS = 1024;
+constexpr int SC_TILE = 4096;
+
+__global__ void __launch_bounds__(SC_THREADS) k_scan_tile(const int *in, int *out, int64_t n,
+                                                          int *sums) {
+    __shared__ int ts[SC_THREADS];
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + threadIdx.x * 4;
+    int v[4], s = 0;
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    ts[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < SC_THREADS; off <<= 1) {
+        int t = (threadIdx.x >= (unsigned)off) ? ts[threadIdx.x - off] : 0;
+        __syncthreads();
+        ts[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = ts[threadIdx.x] - s;  // exclusive prefix of this thread
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == SC_THREADS - 1 && sums) sums[blockIdx.x] = ts[SC_THREADS - 1];
+}
+
+__global__ void k_scan_add(int *out, int64_t n, const int *offs) {
+    int64_t i = (int64_t)blockIdx.x * SC_TILE + threadIdx.x;
+    const int o = offs[blockIdx.x];
+    for (int k = 0; k < SC_TILE; k += blockDim.x)
+        if (i + k < n && i + k < (int64_t)(blockIdx.x + 1) * SC_TILE) out[i + k] += o;
+}
+
+static void scan_rec(const int *in, int *out, int64_t n, hipStream_t st, int *tmp) {
+    const int64_t nb = (n + SC_TILE - 1) / SC_TILE;
+    if (nb <= 1) {
+        k_scan_tile<<<1, SC_THREADS, 0, st>>>(in, out, n, nullptr);
+        BFM_LAUNCHED();
+        return;
+    }
+    int *sums = tmp;
+    k_scan_tile<<<(unsigned)nb, SC_THREADS, 0, st>>>(in, out, n, sums);
+    BFM_LAUNCHED();
+    scan_rec(sums, sums, nb, st, tmp + nb);
+    k_scan_add<<<(unsigned)nb, 256, 0, st>>>(out, n, sums);
+    BFM_LAUNCHED();
+}
+
+int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp) {
+    if (n <= 0) return 0;
+    int64_t need = 2, m = n;
+    while (m > 1) {
+        m = (m + SC_TILE - 1) / SC_TILE;
+        need += m + 1;
+    }
+    int *t = tmp.ensure((size_t)need + 2);
+    int last_in = 0;
+    BFM_HIP(hipMemcpyAsync(&last_in, in + n - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    scan_rec(in, out, n, st, t);
+    int last_out = 0;
+    BFM_HIP(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    return (int64_t)last_out + last_in;
+}
+
+// ---------------------------------------------------------------------------
+// Levels
+
+__global__ void k_level_counts(const uint64_t *key, int64_t n, int lmax, unsigned long long *counts) {
+    __shared__ int c[kKeyBits + 1];
+    if (threadIdx.x <= kKeyBits) c[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        for (int l = 0; l <= lmax; ++l) {
+            const int sh = 3 * (kKeyBits - l);
+            if (i == 0 || (key[i] >> sh) != (key[i - 1] >> sh)) atomicAdd(&c[l], 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= (unsigned)lmax && c[threadIdx.x])
+        atomicAdd(&counts[threadIdx.x], (unsigned long long)c[threadIdx.x]);
+}
+
+__global__ void k_level_flags(const uint64_t *key, int64_t n, int shift, int *flag) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || (key[i] >> shift) != (key[i - 1] >> shift)) ? 1 : 0;
+}
+
+__global__ void k_level_scatter(const uint64_t *key, int64_t n, int shift, const int *flag,
+                                const int *pos, int64_t box0, int level, uint64_t *box_key,
+                                int *box_level, int *box_pt0) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const int64_t b = box0 + pos[i];
+    box_key[b] = key[i] >> shift;
+    box_level[b] = level;
+    box_pt0[b] = (int)i;
+}
+
+__device__ inline int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t v) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+struct LevelInfo {
+    int64_t off[kKeyBits + 2];
+    double h[kKeyBits + 1];
+};
+
+__global__ void k_box_meta(int64_t nbox, int lmax, LevelInfo li, double ox, double oy, double oz,
+                           const uint64_t *box_key, const int *box_level, int64_t npts,
+                           int *box_parent, double *centre, int *nbr, int *box_pt1_unused) {
+    int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const int l = box_level[b];
+    const uint64_t k = box_key[b];
+    int ix, iy, iz;
+    demorton(k, ix, iy, iz);
+    const double h = li.h[l];
+    centre[3 * b] = ox + (ix + 0.5) * h;
+    centre[3 * b + 1] = oy + (iy + 0.5) * h;
+    centre[3 * b + 2] = oz + (iz + 0.5) * h;
+    if (l == 0) {
+        box_parent[b] = -1;
+    } else {
+        int64_t pb = lower_bound_u64(box_key, li.off[l - 1], li.off[l], k >> 3);
+        box_parent[b] = (int)pb;
+    }
+    const int lim = 1 << l;
+    for (int s = 0; s < 27; ++s) {
+        const int dx = s / 9 - 1, dy = (s / 3) % 3 - 1, dz = s % 3 - 1;
+        const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+        int res = -1;
+        if (jx >= 0 && jy >= 0 && jz >= 0 && jx < lim && jy < lim && jz < lim) {
+            const uint64_t nk = morton(jx, jy, jz);
+            int64_t q = lower_bound_u64(box_key, li.off[l], li.off[l + 1], nk);
+            if (q < li.off[l + 1] && box_key[q] == nk) res = (int)q;
+        }
+        nbr[27 * b + s] = res;
+    }
+    (void)npts;
+    (void)box_pt1_unused;
+}
+
+// Number of near-field pairs per leaf, and leaf point ranges.
+__global__ void k_leaf_near(int64_t nleaf, int64_t leaf0, const int *box_pt0, int64_t npts,
+                            const int *nbr, int *leaf_pt, unsigned long long *pairs, int *maxocc) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    const int64_t b = leaf0 + i;
+    const int p0 = box_pt0[b];
+    const int p1 = (i + 1 < nleaf) ? box_pt0[b + 1] : (int)npts;
+    leaf_pt[i] = p0;
+    if (i + 1 == nleaf) leaf_pt[nleaf] = (int)npts;
+    unsigned long long src = 0;
+    for (int s = 0; s < 27; ++s) {
+        const int q = nbr[27 * b + s];
+        if (q < 0) continue;
+        const int64_t qi = q - leaf0;
+        const int q0 = box_pt0[q];
+        const int q1 = (qi + 1 < nleaf) ? box_pt0[q + 1] : (int)npts;
+        src += (unsigned long long)(q1 - q0);
+    }
+    atomicAdd(pairs, src * (unsigned long long)(p1 - p0));
+    atomicMax(maxocc, p1 - p0);
+}
+
+// ---------------------------------------------------------------------------
+// Interaction lists
+
+__constant__ signed short c_m2l_lut[343];
+
+__device__ inline void child_range(const uint64_t *box_key, const LevelInfo &li, int l, uint64_t k,
+                                   int64_t &c0, int64_t &c1) {
+    c0 = lower_bound_u64(box_key, li.off[l + 1], li.off[l + 2], k << 3);
+    c1 = lower_bound_u64(box_key, li.off[l + 1], li.off[l + 2], (k + 1) << 3);
+}
+
+// mode 0: count M2L pairs per target box; mode 1: write them.
+__global__ void k_m2l_pairs(int mode, int64_t b0, int64_t b1, LevelInfo li, const uint64_t *box_key,
+                            const int *box_level, const int *box_parent, const int *nbr, int *count,
+                            const int *offs, int *tsrc, int *tdst, int *top) {
+    int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= b1) return;
+    const int l = box_level[b];
+    int ix, iy, iz;
+    demorton(box_key[b], ix, iy, iz);
+    const int pb = box_parent[b];
+    int c = 0;
+    int64_t w = (mode == 1) ? offs[b - b0] : 0;
+    for (int s = 0; s < 27; ++s) {
+        const int q = nbr[27 * (int64_t)pb + s];
+        if (q < 0) continue;
+        int64_t c0, c1;
+        child_range(box_key, li, l - 1, box_key[q], c0, c1);
+        for (int64_t cc = c0; cc < c1; ++cc) {
+            int jx, jy, jz;
+            demorton(box_key[cc], jx, jy, jz);
+            const int dx = ix - jx, dy = iy - jy, dz = iz - jz;
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+            if (mode == 1) {
+                tsrc[w] = (int)cc;
+                tdst[w] = (int)b;
+                top[w] = c_m2l_lut[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)];
+                ++w;
+            }
+            ++c;
+        }
+    }
+    if (mode == 0) count[b - b0] = c;
+}
+
+// Tasks of one level's M2M/L2L: child box c (level l) <-> parent.
+__global__ void k_tree_pairs(int64_t b0, int64_t b1, const uint64_t *box_key, const int *box_parent,
+                             int *tsrc, int *tdst, int *top) {
+    int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= b1) return;
+    tsrc[b - b0] = (int)b;
+    tdst[b - b0] = box_parent[b];
+    top[b - b0] = (int)(box_key[b] & 7);
+}
+
+__global__ void k_op_hist(const int *top, int64_t n, int *hist) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&hist[top[i]], 1);
+}
+
+// Group by operator keeping the input order within each group: one block
+// per operator scans all tasks in order (operator counts are small).
+__global__ void k_op_group(const int *top, const int *src, const int *dst, int64_t n,
+                           const int *op_off, int *osrc, int *odst) {
+    const int op = blockIdx.x;
+    __shared__ int base;
+    if (threadIdx.x == 0) base = op_off[op];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    // single wave per block keeps the order simple
+    if (threadIdx.x >= 64) return;
+    int run = base;
+    for (int64_t i0 = 0; i0 < n; i0 += 64) {
+        const int64_t i = i0 + lane;
+        const bool hit = (i < n) && top[i] == op;
+        const uint64_t m = __ballot(hit);
+        if (hit) {
+            const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+            const int r = run + __popcll(m & lt);
+            osrc[r] = src[i];
+            odst[r] = dst[i];
+        }
+        run += __popcll(m);
+    }
+}
+
+static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst, const int *top,
+                        int64_t n, hipStream_t st) {
+    tl.nops = nops;
+    tl.ntasks = n;
+    tl.op_off_h.assign(nops + 1, 0);
+    tl.op_off.ensure(nops + 1);
+    for (int c = 0; c < 8; ++c) {
+        tl.ntiles[c] = 0;
+        tl.tiles_ready[c] = false;
+    }
+    DevBuf<int> hist;
+    hist.ensure(nops);
+    BFM_HIP(hipMemsetAsync(hist.get(), 0, sizeof(int) * nops, st));
+    if (n > 0) {
+        k_op_hist<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(top, n, hist.get());
+        BFM_LAUNCHED();
+    }
+    std::vector<int> h(nops);
+    BFM_HIP(hipMemcpyAsync(h.data(), hist.get(), sizeof(int) * nops, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    for (int o = 0; o < nops; ++o) tl.op_off_h[o + 1] = tl.op_off_h[o] + h[o];
+    BFM_HIP(hipMemcpyAsync(tl.op_off.get(), tl.op_off_h.data(), sizeof(int) * (nops + 1),
+                           hipMemcpyHostToDevice, st));
+    tl.src.ensure(n > 0 ? n : 1);
+    tl.dst.ensure(n > 0 ? n : 1);
+    if (n > 0) {
+        k_op_group<<<nops, 64, 0, st>>>(top, tsrc, tdst, n, tl.op_off.get(), tl.src.get(),
+                                        tl.dst.get());
+        BFM_LAUNCHED();
+    }
+    BFM_HIP(hipStreamSynchronize(st));
+}
+
+void prepare_tiles(TaskList &tl, int nch, hipStream_t st) {
+    BFM_CHECK(nch >= 1 && nch < 8, BFM_EINVAL, "channel count out of range");
+    if (tl.tiles_ready[nch]) return;
+    int run = 0;
+    std::vector<int> pre(tl.nops + 1);
+    for (int o = 0; o < tl.nops; ++o) {
+        pre[o] = run;
+        const int cols = (tl.op_off_h[o + 1] - tl.op_off_h[o]) * nch;
+        run += (cols + 15) / 16;
+    }
+    pre[tl.nops] = run;
+    tl.tile_off[nch].ensure(tl.nops + 1);
+    BFM_HIP(hipMemcpyAsync(tl.tile_off[nch].get(), pre.data(), sizeof(int) * (tl.nops + 1),
+                           hipMemcpyHostToDevice, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    tl.ntiles[nch] = run;
+    tl.tiles_ready[nch] = true;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void k_sort_points(const double *xyz, const int *perm, int64_t n, double *px, double *py,
+                              double *pz, int *iperm) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int o = perm[i];
+    px[i] = xyz[3 * (int64_t)o];
+    py[i] = xyz[3 * (int64_t)o + 1];
+    pz[i] = xyz[3 * (int64_t)o + 2];
+    iperm[o] = (int)i;
+}
+
+__global__ void k_sort_geom(const double *s, const double *nrm, const int *perm, int64_t n,
+                            double *ps, double *pnx, double *pny, double *pnz) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int o = perm[i];
+    ps[i] = s[o];
+    pnx[i] = nrm[o];
+    pny[i] = nrm[n + o];
+    pnz[i] = nrm[2 * n + o];
+}
+
+static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target, hipStream_t st) {
+    BFM_CHECK(n >= 1, BFM_EINVAL, "tree of no points");
+    t.valid = false;
+    t.n = n;
+    // bounding cube
+    const int nbb = 256;
+    DevBuf<double> part;
+    part.ensure(6 * nbb);
+    k_bbox_partial<<<nbb, 256, 0, st>>>(xyz, n, part.get());
+    BFM_LAUNCHED();
+    std::vector<double> ph(6 * nbb);
+    BFM_HIP(hipMemcpyAsync(ph.data(), part.get(), sizeof(double) * 6 * nbb, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int b = 0; b < nbb; ++b)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = std::min(mn[d], ph[6 * b + d]);
+            mx[d] = std::max(mx[d], ph[6 * b + 3 + d]);
+        }
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        BFM_CHECK(std::isfinite(mn[d]) && std::isfinite(mx[d]), BFM_EMESH, "non-finite vertex coordinate");
+        ext = std::max(ext, mx[d] - mn[d]);
+    }
+    if (!(ext > 0.0)) ext = 1.0;
+    t.side = ext * (1.0 + 1e-9) + 1e-300;
+    for (int d = 0; d < 3; ++d) t.origin[d] = 0.5 * (mn[d] + mx[d]) - 0.5 * t.side;
+    const double inv_cell = (double)(1 << kKeyBits) / t.side;
+
+    // keys + sort
+    t.key_a.ensure(n);
+    t.key_b.ensure(n);
+    t.idx_a.ensure(n);
+    t.idx_b.ensure(n);
+    k_morton<<<nblk(n, 256), 256, 0, st>>>(xyz, n, t.origin[0], t.origin[1], t.origin[2], inv_cell,
+                                           t.key_a.get(), t.idx_a.get());
+    BFM_LAUNCHED();
+    const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    DevBuf<int> hist, scanned, tmp;
+    hist.ensure((size_t)256 * nblocks);
+    scanned.ensure((size_t)256 * nblocks);
+    uint64_t *kin = t.key_a.get(), *kout = t.key_b.get();
+    int *vin = t.idx_a.get(), *vout = t.idx_b.get();
+    for (int pass = 0; pass < 6; ++pass) {
+        const int shift = 8 * pass;
+        k_rs_hist<<<nblocks, RS_THREADS, 0, st>>>(kin, n, shift, hist.get(), nblocks);
+        BFM_LAUNCHED();
+        exclusive_scan(hist.get(), scanned.get(), (int64_t)256 * nblocks, st, tmp);
+        k_rs_scatter<<<nblocks, RS_THREADS, 0, st>>>(kin, vin, n, shift, scanned.get(), nblocks, kout,
+                                                     vout);
+        BFM_LAUNCHED();
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    // six passes: the result is back in key_a / idx_a
+
+    // boxes per level
+    DevBuf<unsigned long long> cnt;
+    cnt.ensure(kKeyBits + 1);
+    BFM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(unsigned long long) * (kKeyBits + 1), st));
+    k_level_counts<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, kKeyBits, cnt.get());
+    BFM_LAUNCHED();
+    std::vector<unsigned long long> ch(kKeyBits + 1);
+    BFM_HIP(hipMemcpyAsync(ch.data(), cnt.get(), sizeof(unsigned long long) * (kKeyBits + 1),
+                           hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    int lmax = lmax_req;
+    if (lmax <= 0) {
+        lmax = 2;
+        for (int l = 2; l <= kKeyBits; ++l)
+            if ((double)n / (double)ch[l] >= (double)std::max(leaf_target, 1)) lmax = l;
+    }
+    BFM_CHECK(lmax >= 2 && lmax <= kKeyBits, BFM_EINVAL, "octree depth must be in [2, 15]");
+    t.lmax = lmax;
+    t.lvl_off.assign(lmax + 2, 0);
+    for (int l = 0; l <= lmax; ++l) t.lvl_off[l + 1] = t.lvl_off[l] + (int64_t)ch[l];
+    t.nbox = t.lvl_off[lmax + 1];
+    t.nleaf = (int64_t)ch[lmax];
+    LevelInfo li;
+    for (int l = 0; l <= kKeyBits + 1; ++l) li.off[l] = (l <= lmax + 1) ? t.lvl_off[l] : t.nbox;
+    for (int l = 0; l <= kKeyBits; ++l) li.h[l] = t.side / (double)(1 << l);
+
+    t.box_key.ensure(t.nbox);
+    t.box_level.ensure(t.nbox);
+    t.box_pt0.ensure(t.nbox + 1);
+    t.box_parent.ensure(t.nbox);
+    t.box_centre.ensure(3 * t.nbox);
+    t.nbr.ensure(27 * t.nbox);
+    DevBuf<int> flag, pos;
+    flag.ensure(n);
+    pos.ensure(n);
+    for (int l = 0; l <= lmax; ++l) {
+        const int shift = 3 * (kKeyBits - l);
+        k_level_flags<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, shift, flag.get());
+        BFM_LAUNCHED();
+        exclusive_scan(flag.get(), pos.get(), n, st, tmp);
+        k_level_scatter<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, shift, flag.get(), pos.get(),
+                                                      t.lvl_off[l], l, t.box_key.get(),
+                                                      t.box_level.get(), t.box_pt0.get());
+        BFM_LAUNCHED();
+    }
+    k_box_meta<<<nblk(t.nbox, 128), 128, 0, st>>>(t.nbox, lmax, li, t.origin[0], t.origin[1],
+                                                  t.origin[2], t.box_key.get(), t.box_level.get(), n,
+                                                  t.box_parent.get(), t.box_centre.get(), t.nbr.get(),
+                                                  nullptr);
+    BFM_LAUNCHED();
+    // leaves
+    t.leaf_pt.ensure(t.nleaf + 1);
+    DevBuf<unsigned long long> np;
+    np.ensure(1);
+    DevBuf<int> mo;
+    mo.ensure(1);
+    BFM_HIP(hipMemsetAsync(np.get(), 0, sizeof(unsigned long long), st));
+    BFM_HIP(hipMemsetAsync(mo.get(), 0, sizeof(int), st));
+    k_leaf_near<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.box_pt0.get(), n,
+                                                    t.nbr.get(), t.leaf_pt.get(), np.get(), mo.get());
+    BFM_LAUNCHED();
+    unsigned long long npairs = 0;
+    int maxocc = 0;
+    BFM_HIP(hipMemcpyAsync(&npairs, np.get(), sizeof(npairs), hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipMemcpyAsync(&maxocc, mo.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    t.npairs_near = (int64_t)npairs;
+    t.max_leaf = maxocc;
+
+    // M2L lists over levels 2..lmax
+    {
+        {
+            signed short lut[343];
+            for (int a = -3; a <= 3; ++a)
+                for (int b = -3; b <= 3; ++b)
+                    for (int c = -3; c <= 3; ++c)
+                        lut[(a + 3) * 49 + (b + 3) * 7 + (c + 3)] = (signed short)m2l_op_index(a, b, c);
+            BFM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_m2l_lut), lut, sizeof(lut)));
+        }
+        const int64_t b0 = t.lvl_off[2], b1 = t.lvl_off[lmax + 1];
+        const int64_t nb = b1 - b0;
+        DevBuf<int> count, offs;
+        count.ensure(nb);
+        offs.ensure(nb);
+        k_m2l_pairs<<<nblk(nb, 128), 128, 0, st>>>(0, b0, b1, li, t.box_key.get(), t.box_level.get(),
+                                                   t.box_parent.get(), t.nbr.get(), count.get(),
+                                                   nullptr, nullptr, nullptr, nullptr);
+        BFM_LAUNCHED();
+        const int64_t total = exclusive_scan(count.get(), offs.get(), nb, st, tmp);
+        DevBuf<int> ts, td, to;
+        ts.ensure(total + 1);
+        td.ensure(total + 1);
+        to.ensure(total + 1);
+        k_m2l_pairs<<<nblk(nb, 128), 128, 0, st>>>(1, b0, b1, li, t.box_key.get(), t.box_level.get(),
+                                                   t.box_parent.get(), t.nbr.get(), count.get(),
+                                                   offs.get(), ts.get(), td.get(), to.get());
+        BFM_LAUNCHED();
+        group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, st);
+    }
+    // M2M / L2L lists: child levels 3..lmax (index l)
+    for (auto *p : t.m2m) delete p;
+    t.m2m.assign(lmax + 1, nullptr);
+    for (int l = 3; l <= lmax; ++l) {
+        const int64_t b0 = t.lvl_off[l], b1 = t.lvl_off[l + 1];
+        const int64_t nb = b1 - b0;
+        DevBuf<int> ts, td, to;
+        ts.ensure(nb);
+        td.ensure(nb);
+        to.ensure(nb);
+        k_tree_pairs<<<nblk(nb, 128), 128, 0, st>>>(b0, b1, t.box_key.get(), t.box_parent.get(),
+                                                    ts.get(), td.get(), to.get());
+        BFM_LAUNCHED();
+        t.m2m[l] = new TaskList();
+        group_tasks(*t.m2m[l], 8, ts.get(), td.get(), to.get(), nb, st);
+    }
+    // sorted positions
+    t.iperm.ensure(n);
+    t.px.ensure(n);
+    t.py.ensure(n);
+    t.pz.ensure(n);
+    k_sort_points<<<nblk(n, 256), 256, 0, st>>>(xyz, t.idx_a.get(), n, t.px.get(), t.py.get(),
+                                                t.pz.get(), t.iperm.get());
+    BFM_LAUNCHED();
+    BFM_HIP(hipStreamSynchronize(st));
+    t.valid = true;
+}
+
+void sort_geometry(Tree &t, const double *s, const double *nrm, hipStream_t st) {
+    const int64_t n = t.n;
+    t.ps.ensure(n);
+    t.pnx.ensure(n);
+    t.pny.ensure(n);
+    t.pnz.ensure(n);
+    k_sort_geom<<<nblk(n, 256), 256, 0, st>>>(s, nrm, t.idx_a.get(), n, t.ps.get(), t.pnx.get(),
+                                              t.pny.get(), t.pnz.get());
+    BFM_LAUNCHED();
+}
+
+}  // namespace bfm
