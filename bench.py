@@ -1,0 +1,162 @@
+#!/usr/bin/env python
+"""Benchmark: FMM-BEM solve seconds per time step on the 1000-bubble cluster.
+
+One step = one BEM solve as inside a time step of the paper's method: the
+vertices move (device-to-device copy of positions, which invalidates the
+geometry and the octree), then geometry, octree build, the five-channel
+pass for the singular diagonals and b, and GMRES for q = dphi/dn. Inputs
+(mesh, positions, phi) are resident in HBM before the timed region.
+
+Prints one JSON line (see the keys below). Kernel times come from HIP
+events recorded by the library on its stream around every launch inside
+the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FMM-BEM solve s/step at 1.28M tris: tuned vs plain FP64, dphi/dn rel err<=1e-6"
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and FP64 matrix (dense)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1000")
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--p-diag", type=int, default=0)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--lmax", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=3000)
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(cl, phi, matvecs, rows_n):
+    """The oracle (unchanged) on a bounded receiver sample of the same
+    workload, scaled to one solve: one pass of the diagonal/RHS sums plus
+    `matvecs` direct products, each costing N receivers."""
+    import oracle
+    oracle.build(force=False)
+    rows = np.arange(0, cl.nv, max(1, cl.nv // rows_n), dtype=np.int64)[:rows_n]
+    s, n, _ = oracle.geometry(cl.xyz, cl.tri)
+    t0 = time.perf_counter()
+    oracle.sums(cl.xyz, s, n, phi, rows=rows)
+    t1 = time.perf_counter()
+    oracle.offdiag_mvp(cl.xyz, s, n, 1.0, phi, rows=rows)
+    t2 = time.perf_counter()
+    per_row_sums = (t1 - t0) / len(rows)
+    per_row_mvp = (t2 - t1) / len(rows)
+    est = cl.nv * (per_row_sums + matvecs * per_row_mvp)
+    return {
+        "value": est, "unit": "s/step", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": (f"direct sums and one direct product for {len(rows)} evenly spaced receivers x "
+                   f"{cl.nv} sources ({t2 - t0:.1f} s), scaled to {cl.nv} receivers and "
+                   f"{matvecs} products (the GPU solve's count)"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              f"(asked for --gpus {a.gpus})", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1905_01341_amd import bfm
+    from paper_1905_01341_amd import workload as wl
+
+    cl, phi = wl.make(a.workload)
+    dev = torch.device("cuda:0")
+    xyz_t = torch.tensor(cl.xyz, dtype=torch.float64, device=dev).contiguous()
+    phi_t = torch.tensor(phi, dtype=torch.float64, device=dev).contiguous()
+    q_t = torch.zeros_like(phi_t)
+    sv = bfm.Solver(device=0, p=a.p, p_diag=a.p_diag, leaf_target=a.leaf, lmax=a.lmax,
+                    gmres_tol=a.tol, gmres_restart=a.restart, gmres_maxit=1000)
+    sv.set_cluster(cl)
+    torch.cuda.synchronize()
+
+    def step():
+        _check = bfm._check
+        _check(sv.lib.bfm_set_positions_dev(sv.h, bfm.ctypes.c_void_p(xyz_t.data_ptr())))
+        return sv.solve_dev(phi_t, q_t)
+
+    for _ in range(a.warmup):
+        info = step()
+    torch.cuda.synchronize()
+    if not a.no_profile:
+        sv.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(a.steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sv.profile_read() if not a.no_profile else None
+    sv.profile(False)
+    ms = (t1 - t0) * 1e3 / a.steps
+    info = infos[-1]
+    stats = sv.tree_stats()
+
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", f"{a.workload}_q_oracle.npy")
+    if os.path.exists(gold):
+        qo = np.load(gold).astype(np.float64)
+        qg = q_t.cpu().numpy()
+        err = float(np.linalg.norm(qg - qo) / np.linalg.norm(qo))
+
+    roof = None
+    if prof:
+        cand = {k: prof[k] for k in ("p2p", "m2l", "m2m_l2l")}
+        dom = max(cand, key=lambda k: cand[k]["ms"])
+        d = prof[dom]
+        avg_ms = d["ms"] / max(d["launches"], 1)
+        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
+        roof = {"kernel": {"p2p": "k_p2p (near field)", "m2l": "k_translate (M2L)",
+                           "m2m_l2l": "k_translate (M2M/L2L)"}[dom],
+                "bound": "alu" if dom == "p2p" else "mfma",
+                "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
+                "flops_per_launch": d["flops"] / max(d["launches"], 1)}
+    out = {
+        "metric": METRIC, "value": round(ms / 1e3, 6), "unit": "s/step", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{a.workload}: {cl.nb} icosphere bubbles, {cl.nv} nodes, {cl.nt} triangles"),
+            "form": "plain_fp64", "p": a.p, "p_diag": sv.opt.p_diag or min(20, a.p + 4),
+            "lmax": stats["lmax"], "leaves": stats["leaves"], "near_pairs": stats["near_pairs"],
+            "m2l_pairs": stats["m2l_pairs"], "gmres_tol": a.tol, "gmres_restart": a.restart,
+            "iterations": info["iterations"], "matvecs": info["matvecs"],
+            "rel_residual": info["rel_residual"], "err_vs_oracle": err,
+            "phase_ms": {"tree": round(info["t_tree_ms"], 3), "diag": round(info["t_diag_ms"], 3),
+                         "gmres": round(info["t_solve_ms"], 3)},
+        },
+        "roofline": roof,
+    }
+    if prof:
+        out["kernels_ms_per_step"] = {k: round(v["ms"] / a.steps, 3) for k, v in prof.items()}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cl, phi, info["matvecs"], a.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,7 +65,10 @@ typedef struct bfm_options {
     int abi_version;   /* must be BFM_ABI_VERSION */
     int device;        /* HIP device ordinal */
     void *stream;      /* hipStream_t to run on; NULL = the library creates one */
-    int p;             /* expansion degrees 0..p-1 (p^2 coefficients); multiple of 4, 4..20 */
+    int p;             /* expansion degrees 0..p-1 (p^2 coefficients) of the products inside
+                          GMRES; multiple of 4, 4..20 */
+    int p_diag;        /* expansion degrees of the once-per-solve pass for the singular
+                          diagonals and b; 0 = min(20, p + 4) */
     int lmax;          /* octree depth; 0 = choose from leaf_target */
     int leaf_target;   /* mean points per non-empty leaf aimed at when lmax = 0 */
     int precision;     /* BFM_PREC_* for the products inside GMRES */
@@ -87,8 +90,8 @@ typedef struct bfm_solve_info {
 
 typedef struct bfm_ctx bfm_ctx;
 
-/* Fill *opt with defaults: p = 12, lmax = 0, leaf_target = 64, FP64,
- * tol 1e-10, restart 30, maxit 300, device 0, stream NULL. */
+/* Fill *opt with defaults: p = 16, p_diag = 0, lmax = 0, leaf_target = 64,
+ * FP64, tol 1e-10, restart 30, maxit 300, device 0, stream NULL. */
 int bfm_default_options(bfm_options *opt);
 
 /* Create a handle on opt->device. The handle owns every device buffer
@@ -127,7 +130,7 @@ int bfm_geometry(bfm_ctx *ctx, double *s, double *n);
 
 /*
  * Singular diagonals and right-hand side (Section 3.3 s3/s5, eq3_1) by one
- * five-channel fast multipole pass at the handle's p, in FP64:
+ * five-channel fast multipole pass at the handle's p_diag, in FP64:
  *   Mii[i] = -1/2 - sum_{j!=i} M_ij
  *   Lii[i] = n_i . [sum_{j!=i} M_ij (r_j - r_i) - sum_{j!=i} L_ij n_j]
  *   b[i]   = -phi_i/2 + Mii[i] phi_i + sum_{j!=i} M_ij phi_j
@@ -139,8 +142,8 @@ int bfm_diagonals(bfm_ctx *ctx, const double *phi, double *Mii, double *Lii, dou
  * Product with A = f L + g M (eq3_27) by the fast multipole method:
  *   out_i = sum_{j != i} (f L_ij x_j + g M_ij y_j) [+ f L_ii x_i + g M_ii y_i if add_diag]
  * x, y, out host [nv] (x may be NULL if f == 0, y if g == 0). precision
- * selects BFM_PREC_*. add_diag needs the diagonals of the current mesh
- * (computed on demand). direct = 1 replaces the fast multipole method by
+ * selects BFM_PREC_*; the product uses the handle's p. add_diag needs the
+ * diagonals of the current mesh (computed on demand, at p_diag). direct = 1 replaces the fast multipole method by
  * the all-pairs sum on the GPU (FP64), for checking.
  */
 int bfm_matvec(bfm_ctx *ctx, double f, const double *x, double g, const double *y, double *out,
@@ -164,6 +167,21 @@ int bfm_solve_dev(bfm_ctx *ctx, const double *phi_dev, double *q_dev, int use_gu
  * stats[0] = lmax, [1] = leaves, [2] = boxes (all levels), [3] = near-field
  * pairs, [4] = M2L pairs, [5] = M2M+L2L pairs, [6] = max points per leaf. */
 int bfm_tree_stats(bfm_ctx *ctx, int64_t stats[8]);
+
+/*
+ * Kernel timing (measurement support). Classes: 0 near-field P2P, 1 M2L
+ * translations, 2 M2M + L2L translations, 3 P2M, 4 L2P, 5 GMRES vector
+ * kernels, 6 octree build (whole), 7 diagonal/right-hand-side pass (whole).
+ * bfm_profile(ctx, 1) clears and starts recording HIP events around every
+ * launch of these classes on the handle's stream; bfm_profile(ctx, 0) stops.
+ * bfm_profile_read synchronises the stream and returns, per class, the summed
+ * event time in ms, the number of launches, and the summed algorithmic work
+ * of those launches (flops for 0..4: near-field pairs x flops per pair, and
+ * 2 p^4 per translated expansion column; 0 for 5..7). Arrays have 8 entries.
+ */
+#define BFM_KERNEL_CLASSES 8
+int bfm_profile(bfm_ctx *ctx, int enable);
+int bfm_profile_read(bfm_ctx *ctx, double ms[8], int64_t launches[8], double flops[8]);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *bfm_last_error(void);

@@ -33,6 +33,7 @@ class Options(ctypes.Structure):
         ("device", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("p", ctypes.c_int),
+        ("p_diag", ctypes.c_int),
         ("lmax", ctypes.c_int),
         ("leaf_target", ctypes.c_int),
         ("precision", ctypes.c_int),
@@ -91,6 +92,8 @@ def load(path: str = LIB_PATH):
         "bfm_tree_stats": ([P, ctypes.POINTER(I64)], I),
         "bfm_last_error": ([], ctypes.c_char_p),
         "bfm_debug_operator": ([I, I, I, P, P], I),
+        "bfm_profile": ([P, I], I),
+        "bfm_profile_read": ([P, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -218,6 +221,19 @@ class Solver:
                                       ctypes.c_void_p(q_t.data_ptr()), int(use_guess),
                                       ctypes.byref(info)))
         return info.as_dict()
+
+    KERNEL_CLASSES = ["p2p", "m2l", "m2m_l2l", "p2m", "l2p", "gmres", "tree", "diag"]
+
+    def profile(self, enable: bool):
+        _check(self.lib.bfm_profile(self.h, int(enable)))
+
+    def profile_read(self):
+        ms = np.zeros(8)
+        n = np.zeros(8, dtype=np.int64)
+        fl = np.zeros(8)
+        _check(self.lib.bfm_profile_read(self.h, _ptr(ms), _ptr(n), _ptr(fl)))
+        return {k: dict(ms=float(ms[i]), launches=int(n[i]), flops=float(fl[i]))
+                for i, k in enumerate(self.KERNEL_CLASSES)}
 
     def tree_stats(self):
         st = (ctypes.c_int64 * 8)()

@@ -36,6 +36,8 @@ static void check_options(const bfm_options &o) {
     BFM_CHECK(o.abi_version == BFM_ABI_VERSION, BFM_EINVAL, "abi_version mismatch");
     BFM_CHECK(o.p >= 4 && o.p <= kMaxP && o.p % 4 == 0, BFM_EINVAL,
               "p must be a multiple of 4 in [4, 20]");
+    BFM_CHECK(o.p_diag == 0 || (o.p_diag >= 4 && o.p_diag <= kMaxP && o.p_diag % 4 == 0), BFM_EINVAL,
+              "p_diag must be 0 or a multiple of 4 in [4, 20]");
     BFM_CHECK(o.lmax == 0 || (o.lmax >= 2 && o.lmax <= 15), BFM_EINVAL, "lmax must be 0 or in [2, 15]");
     BFM_CHECK(o.leaf_target >= 1, BFM_EINVAL, "leaf_target must be >= 1");
     BFM_CHECK(o.precision == BFM_PREC_FP64 || o.precision == BFM_PREC_FP32, BFM_EINVAL,
@@ -126,7 +128,8 @@ int bfm_default_options(bfm_options *opt) {
     opt->abi_version = BFM_ABI_VERSION;
     opt->device = 0;
     opt->stream = nullptr;
-    opt->p = 12;
+    opt->p = 16;
+    opt->p_diag = 0;
     opt->lmax = 0;
     opt->leaf_target = 64;
     opt->precision = BFM_PREC_FP64;
@@ -145,6 +148,8 @@ int bfm_create(const bfm_options *opt, bfm_ctx **out) {
         BFM_CHECK(opt->device >= 0 && opt->device < ndev, BFM_EINVAL, "device ordinal out of range");
         DeviceScope ds(opt->device);
         auto *c = new bfm_ctx();
+        c->fmm.prof = &c->prof;
+        c->fmm_diag.prof = &c->prof;
         c->opt = *opt;
         c->device = opt->device;
         if (opt->stream) {
@@ -178,7 +183,7 @@ int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
         check_options(*opt);
         BFM_CHECK(opt->device == c->device, BFM_EINVAL, "cannot change the device of a handle");
         const bool tree_change = opt->lmax != c->opt.lmax || opt->leaf_target != c->opt.leaf_target;
-        const bool p_change = opt->p != c->opt.p;
+        const bool p_change = opt->p != c->opt.p || opt->p_diag != c->opt.p_diag;
         void *keep_stream = c->opt.stream;
         c->opt = *opt;
         c->opt.stream = keep_stream;
@@ -388,6 +393,36 @@ int bfm_tree_stats(bfm_ctx *c, int64_t stats[8]) {
         stats[5] = 2 * tr;
         stats[6] = t.max_leaf;
         stats[7] = 0;
+    });
+}
+
+int bfm_profile(bfm_ctx *c, int enable) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        BFM_HIP(hipStreamSynchronize(c->stream));
+        if (enable) c->prof.reset();
+        c->prof.on = enable != 0;
+    });
+}
+
+int bfm_profile_read(bfm_ctx *c, double ms[8], int64_t launches[8], double flops[8]) {
+    return guarded([&] {
+        BFM_CHECK(c && ms && launches && flops, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        BFM_HIP(hipStreamSynchronize(c->stream));
+        for (int k = 0; k < KC_COUNT; ++k) {
+            ms[k] = 0.0;
+            launches[k] = 0;
+            flops[k] = 0.0;
+        }
+        for (const auto &r : c->prof.recs) {
+            float t = 0.f;
+            BFM_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            ms[r.cls] += t;
+            launches[r.cls] += 1;
+            flops[r.cls] += r.flops;
+        }
     });
 }
 

@@ -5,6 +5,7 @@
 
 #include "common.h"
 #include "fmm.h"
+#include "prof.h"
 #include "tree.h"
 
 struct bfm_ctx {
@@ -29,7 +30,9 @@ struct bfm_ctx {
     bfm::Tree tree;
     bool tree_valid = false;
 
-    bfm::FmmWork fmm;
+    bfm::Prof prof;
+    bfm::FmmWork fmm;       // products inside GMRES (order p)
+    bfm::FmmWork fmm_diag;  // diagonal + right-hand-side pass (order p_diag)
 
     // sorted-order solve data
     bfm::DevBuf<double> src_q, src_mu;  // channel strengths
@@ -47,6 +50,7 @@ namespace bfm {
 void ensure_geometry(bfm_ctx *c);
 void ensure_tree(bfm_ctx *c);
 void ensure_ops(bfm_ctx *c);
+int diag_order(const bfm_options &o);
 
 // Five-channel pass: M_ii, L_ii (sorted) and, if phi_dev != null, b (sorted).
 // phi_dev in original order.

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "common.h"
+#include "prof.h"
 #include "tree.h"
 
 namespace bfm {
@@ -23,6 +24,7 @@ struct FmmWork {
     DevBuf<double> mexp, lexp;      // [nbox][nch][P]
     DevBuf<double> ops_m2m, ops_l2l, ops_m2l;  // operators, column-major per op: [op][k][row]
     int ops_p = 0;
+    Prof *prof = nullptr;  // optional kernel timing
 };
 
 // Build translation operators for p (host build + upload); no-op if current.

@@ -105,6 +105,7 @@ __global__ void __launch_bounds__(256) k_p2m(int64_t leaf0, const int *leaf_pt, 
                                              const double *mu, double *mexp) {
     constexpr int NT = P_ * (P_ + 1) / 2;
     constexpr int PP = P_ * P_;
+    static_assert(NT <= 256 && kChunk * NCH <= 256, "phase B assumes one thread per coefficient");
     __shared__ double sre[kChunk][NT], sim[kChunk][NT];
     __shared__ double sq[NCH][kChunk], smu[NCH][3][kChunk];
     const int leaf = blockIdx.x;
@@ -127,8 +128,8 @@ __global__ void __launch_bounds__(256) k_p2m(int64_t leaf0, const int *leaf_pt, 
     for (int c = 0; c < NCH; ++c) ar[c] = ai[c] = 0.0;
     for (int base = r0; base < r1; base += kChunk) {
         __syncthreads();
-        if (tid < kChunk * P_) {
-            const int pt = tid / P_, m = tid % P_;
+        for (int wi = tid; wi < kChunk * P_; wi += blockDim.x) {  // 16 p > 256 when p = 20
+            const int pt = wi / P_, m = wi % P_;
             const int i = base + pt;
             if (i < r1) {
                 regular_column<P_>(m, (px[i] - cx) * ih, (py[i] - cy) * ih, (pz[i] - cz) * ih,
@@ -228,8 +229,8 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t leaf0, const int *leaf_pt, 
     for (int k = tid; k < NCH * PP; k += blockDim.x) (&sl[0][0])[k] = lexp[box * NCH * PP + k];
     for (int base = r0; base < r1; base += kChunk) {
         __syncthreads();
-        if (tid < kChunk * P_) {
-            const int pt = tid / P_, m = tid % P_;
+        for (int wi = tid; wi < kChunk * P_; wi += blockDim.x) {
+            const int pt = wi / P_, m = wi % P_;
             const int i = base + pt;
             if (i < r1)
                 regular_column<P_>(m, (px[i] - cx) * ih, (py[i] - cy) * ih, (pz[i] - cz) * ih,
@@ -308,11 +309,13 @@ __global__ void __launch_bounds__(256) k_translate(int nops, const int *tile_off
         }
     }
     if (!valid) return;
-    double *dcol = out + ((int64_t)db * nch + ch) * PP + 4 * kq;
+    // result layout of v_mfma_f64_16x16x4f64: lane l, element r holds
+    // row (l / 16) + 4 r, column l % 16 of the 16 x 16 block
+    double *dcol = out + ((int64_t)db * nch + ch) * PP + kq;
 #pragma unroll
     for (int rb = 0; rb < PP / 16; ++rb) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) unsafeAtomicAdd(dcol + rb * 16 + r, acc[rb][r]);
+        for (int r = 0; r < 4; ++r) unsafeAtomicAdd(dcol + rb * 16 + 4 * r, acc[rb][r]);
     }
 }
 
@@ -509,16 +512,31 @@ void fmm_prepare_ops(FmmWork &w, int p, hipStream_t st) {
 
 static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Algorithmic flops of one source-receiver pair: shared geometry 3 (d) + 5
+// (r^2) + 1 (1/r) [+ 2 for 1/r^3 with dipoles]; per channel 2 (q/r) and
+// 7 (mu . d / r^3: 5 for the dot product, 2 for the scaled add).
+static double p2p_flops_per_pair(int nch, bool mono, bool dip) {
+    return 9.0 + (dip ? 2.0 : 0.0) + nch * ((mono ? 2.0 : 0.0) + (dip ? 7.0 : 0.0));
+}
+
+static int prof_begin(FmmWork &w, int cls, hipStream_t st) { return w.prof ? w.prof->begin(cls, st) : -1; }
+static void prof_end(FmmWork &w, int idx, hipStream_t st, double flops) {
+    if (w.prof) w.prof->end(idx, st, flops, 0.0);
+}
+
 template <int P_>
-static void translate(TaskList &tl, int nch, bool swap, const double *T, const double *in, double *out,
-                      hipStream_t st) {
+static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, const double *T,
+                      const double *in, double *out, hipStream_t st) {
     prepare_tiles(tl, nch, st);
     const int nt = tl.ntiles[nch];
     if (nt <= 0) return;
+    const int pi = prof_begin(w, cls, st);
     k_translate<P_ * P_><<<nblk(nt, 4), 256, 0, st>>>(tl.nops, tl.tile_off[nch].get(), nt,
                                                        tl.op_off.get(), tl.src.get(), tl.dst.get(),
                                                        nch, swap ? 1 : 0, T, in, out);
     BFM_LAUNCHED();
+    const double PP = (double)P_ * P_;
+    prof_end(w, pi, st, 2.0 * PP * PP * (double)tl.ntasks * nch);
 }
 
 template <int P_, int NCH, bool MONO, bool DIP>
@@ -536,19 +554,27 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     k_zero<<<1024, 256, 0, st>>>(L, (int64_t)ncoef);
     BFM_LAUNCHED();
     // near field first (writes y), far field adds
+    int pi = prof_begin(w, KC_P2P, st);
     k_p2p<NCH, MONO, DIP><<<(unsigned)t.nleaf, kP2PThreads, 0, st>>>(
         leaf0, t.leaf_pt.get(), t.nbr.get(), t.px.get(), t.py.get(), t.pz.get(), t.n, src.q, src.mu, y);
     BFM_LAUNCHED();
+    prof_end(w, pi, st, (double)(t.npairs_near - t.n) * p2p_flops_per_pair(NCH, MONO, DIP));
+    pi = prof_begin(w, KC_P2M, st);
     k_p2m<P_, NCH, MONO, DIP><<<(unsigned)t.nleaf, 256, 0, st>>>(
         leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf, t.px.get(), t.py.get(), t.pz.get(), t.n,
         src.q, src.mu, M);
     BFM_LAUNCHED();
-    for (int l = lmax; l >= 3; --l) translate<P_>(*t.m2m[l], NCH, false, w.ops_m2m.get(), M, M, st);
-    translate<P_>(t.m2l, NCH, false, w.ops_m2l.get(), M, L, st);
-    for (int l = 3; l <= lmax; ++l) translate<P_>(*t.m2m[l], NCH, true, w.ops_l2l.get(), L, L, st);
+    prof_end(w, pi, st, 0.0);
+    for (int l = lmax; l >= 3; --l)
+        translate<P_>(w, KC_M2M_L2L, *t.m2m[l], NCH, false, w.ops_m2m.get(), M, M, st);
+    translate<P_>(w, KC_M2L, t.m2l, NCH, false, w.ops_m2l.get(), M, L, st);
+    for (int l = 3; l <= lmax; ++l)
+        translate<P_>(w, KC_M2M_L2L, *t.m2m[l], NCH, true, w.ops_l2l.get(), L, L, st);
+    pi = prof_begin(w, KC_L2P, st);
     k_l2p<P_, NCH><<<(unsigned)t.nleaf, 256, 0, st>>>(leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf,
                                                       t.px.get(), t.py.get(), t.pz.get(), t.n, L, y);
     BFM_LAUNCHED();
+    prof_end(w, pi, st, 0.0);
 }
 
 template <int NCH, bool MONO, bool DIP>

@@ -32,7 +32,10 @@ __global__ void k_tri_geom(const double *xyz, const int *tri, int64_t nt, int64_
                  e2z = xyz[3 * c + 2] - xyz[3 * a + 2];
     const double cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
     const double len = sqrt(cx * cx + cy * cy + cz * cz);
-    if (!(len > 0.0)) atomicOr(flag, 1);
+    // zero area up to rounding: |e1 x e2| against |e1| |e2| (a repeated vertex
+    // gives a cross product of rounding size, not exactly zero, under FMA)
+    const double scale = sqrt((e1x * e1x + e1y * e1y + e1z * e1z) * (e2x * e2x + e2y * e2y + e2z * e2z));
+    if (!(len > 1e-12 * scale)) atomicOr(flag, 1);
     hc[3 * k] = 0.5 * cx;
     hc[3 * k + 1] = 0.5 * cy;
     hc[3 * k + 2] = 0.5 * cz;
@@ -89,15 +92,24 @@ void ensure_geometry(bfm_ctx *c) {
 void ensure_tree(bfm_ctx *c) {
     ensure_geometry(c);
     if (c->tree_valid) return;
+    const int pi = c->prof.begin(KC_TREE, c->stream);
     build_tree(c->tree, c->xyz.get(), c->nv, c->opt.lmax, c->opt.leaf_target, c->stream);
     sort_geometry(c->tree, c->s.get(), c->nrm.get(), c->stream);
+    c->prof.end(pi, c->stream, 0.0, 0.0);
     c->tree_valid = true;
     c->diag_valid = false;
+}
+
+int diag_order(const bfm_options &o) {
+    if (o.p_diag > 0) return o.p_diag;
+    return o.p + 4 <= kMaxP ? o.p + 4 : kMaxP;
 }
 
 void ensure_ops(bfm_ctx *c) {
     c->fmm.p = c->opt.p;
     fmm_prepare_ops(c->fmm, c->opt.p, c->stream);
+    c->fmm_diag.p = diag_order(c->opt);
+    fmm_prepare_ops(c->fmm_diag, c->fmm_diag.p, c->stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -172,6 +184,7 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
     ensure_tree(c);
     ensure_ops(c);
     hipStream_t st = c->stream;
+    const int pi = c->prof.begin(KC_DIAG, st);
     Tree &t = c->tree;
     const int64_t n = c->nv;
     const double X = t.origin[0] + 0.5 * t.side, Y = t.origin[1] + 0.5 * t.side,
@@ -194,7 +207,7 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
     src.dip = true;
     src.q = q;
     src.mu = mu;
-    fmm_apply(c->fmm, t, src, y, false, st);
+    fmm_apply(c->fmm_diag, t, src, y, false, st);
     c->mii_s.ensure(n);
     c->lii_s.ensure(n);
     c->b_s.ensure(n);
@@ -202,6 +215,7 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
                                                   t.pny.get(), t.pnz.get(), phs, n, X, Y, Z,
                                                   c->mii_s.get(), c->lii_s.get(), c->b_s.get());
     BFM_LAUNCHED();
+    c->prof.end(pi, st, 0.0, 0.0);
     c->diag_valid = true;
 }
 
@@ -489,6 +503,7 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
             matvec_sorted(c, 1.0, vj, 0.0, nullptr, wj, true, prec, false);
             ++matvecs;
             // pass 1
+            const int pg = c->prof.begin(KC_GMRES, st);
             k_mdot<<<kRedBlocks, kRedThreads, 0, st>>>(V, j + 1, n, wj, n, part);
             BFM_LAUNCHED();
             k_reduce<<<j + 1, kRedThreads, 0, st>>>(part, j + 1, sm + L.h1, 0);
@@ -507,6 +522,7 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
             BFM_LAUNCHED();
             k_scale_by<<<nblk(n, 256), 256, 0, st>>>(wj, n, sm + L.scal + 1);
             BFM_LAUNCHED();
+            c->prof.end(pg, st, 0.0, 0.0);
             ++it;
             k = j + 1;
             const double res = read_scalar(L.scal);
