@@ -127,8 +127,10 @@ def main():
         d = prof[dom]
         avg_ms = d["ms"] / max(d["launches"], 1)
         ach = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
-        roof = {"kernel": {"p2p": "k_p2p (near field)", "m2l": "k_translate (M2L)",
-                           "m2m_l2l": "k_translate (M2M/L2L)"}[dom],
+        pp = a.p * a.p
+        roof = {"kernel": {"p2p": "bfm::k_p2p<1, true, false> (near field, GMRES products)",
+                           "m2l": f"bfm::k_translate<{pp}, 0> (M2L, GMRES products)",
+                           "m2m_l2l": f"bfm::k_translate<{pp}, 1> (M2M/L2L, GMRES products)"}[dom],
                 "bound": "alu" if dom == "p2p" else "mfma",
                 "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,

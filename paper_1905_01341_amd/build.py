@@ -15,7 +15,7 @@ ARCH = os.environ.get("BFM_OFFLOAD_ARCH", "gfx950")
 # would otherwise form them from plain float code).
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
+            "-Wall", "-Wno-unused-result", "-Wno-unused-function", "-fopenmp"]
 
 
 def build(verbose: bool = False, jobs: int = 5) -> str:
@@ -35,7 +35,7 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
             _drain(procs)
     _drain(procs)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    cmd = ["hipcc", "-shared", "-fopenmp", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)

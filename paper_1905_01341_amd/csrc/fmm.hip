@@ -268,7 +268,9 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t leaf0, const int *leaf_pt, 
 // ---------------------------------------------------------------------------
 // Grouped translation GEMM (FP64 MFMA). Wave g handles 16 columns of the
 // column space of its operator group: column = task * nch + channel.
-template <int PP>
+// KIND only separates the kernel symbols of M2L (0) and M2M/L2L (1) for
+// profilers; the code is the same.
+template <int PP, int KIND>
 __global__ void __launch_bounds__(256) k_translate(int nops, const int *tile_off, int ntiles,
                                                    const int *op_off, const int *tsrc, const int *tdst,
                                                    int nch, int swap, const double *T,
@@ -495,10 +497,20 @@ void fmm_prepare_ops(FmmWork &w, int p, hipStream_t st) {
         build_l2l(p, o, rm.data());
         to_cm(&h2l[(size_t)o * P * P]);
     }
-    std::vector<double> hl((size_t)kNumM2LOps * P * P);
-    for (int o = 0; o < kNumM2LOps; ++o) {
-        build_m2l(p, o, rm.data());
-        to_cm(&hl[(size_t)o * P * P]);
+    // the 316 multipole-to-local operators are the bulk of the work: build
+    // them once per process and order p
+    static std::vector<double> cache_l[kMaxP + 1];
+    std::vector<double> &hl = cache_l[p];
+    if (hl.empty()) {
+        std::vector<double> tmp((size_t)kNumM2LOps * P * P);
+#pragma omp parallel for schedule(dynamic)
+        for (int o = 0; o < kNumM2LOps; ++o) {
+            std::vector<double> r((size_t)P * P);
+            build_m2l(p, o, r.data());
+            for (int a = 0; a < P; ++a)
+                for (int b = 0; b < P; ++b) tmp[(size_t)o * P * P + (size_t)b * P + a] = r[(size_t)a * P + b];
+        }
+        hl.swap(tmp);
     }
     w.ops_m2m.ensure(h2m.size());
     w.ops_l2l.ensure(h2l.size());
@@ -531,7 +543,8 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
     const int nt = tl.ntiles[nch];
     if (nt <= 0) return;
     const int pi = prof_begin(w, cls, st);
-    k_translate<P_ * P_><<<nblk(nt, 4), 256, 0, st>>>(tl.nops, tl.tile_off[nch].get(), nt,
+    auto kern = (cls == KC_M2L) ? k_translate<P_ * P_, 0> : k_translate<P_ * P_, 1>;
+    kern<<<nblk(nt, 4), 256, 0, st>>>(tl.nops, tl.tile_off[nch].get(), nt,
                                                        tl.op_off.get(), tl.src.get(), tl.dst.get(),
                                                        nch, swap ? 1 : 0, T, in, out);
     BFM_LAUNCHED();

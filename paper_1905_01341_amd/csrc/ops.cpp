@@ -30,15 +30,23 @@ namespace bfm {
 
 using cplx = std::complex<double>;
 
-static long double fact(int n) {
-    long double f = 1.0L;
-    for (int i = 2; i <= n; ++i) f *= (long double)i;
-    return f;
+// nu_n^m = sqrt((n-|m|)! (n+|m|)!) for n < 2 kMaxP, tabulated once.
+static const std::vector<double> &nu_table() {
+    static const std::vector<double> tab = [] {
+        const int N = 2 * kMaxP;
+        std::vector<long double> f(2 * N + 1, 1.0L);
+        for (int i = 2; i <= 2 * N; ++i) f[i] = f[i - 1] * (long double)i;
+        std::vector<double> t((size_t)N * N, 0.0);
+        for (int n = 0; n < N; ++n)
+            for (int m = 0; m <= n; ++m) t[(size_t)n * N + m] = (double)sqrtl(f[n - m] * f[n + m]);
+        return t;
+    }();
+    return tab;
 }
 
 static double nu(int n, int m) {
     if (m < 0) m = -m;
-    return (double)sqrtl(fact(n - m) * fact(n + m));
+    return nu_table()[(size_t)n * (2 * kMaxP) + m];
 }
 
 static inline int tri_index(int n, int m) { return n * (n + 1) / 2 + m; }
