@@ -35,7 +35,7 @@ struct bfm_ctx {
     bfm::FmmWork fmm_diag;  // diagonal + right-hand-side pass (order p_diag)
 
     // sorted-order solve data
-    bfm::DevBuf<double> src_q, src_mu;  // channel strengths
+    bfm::DevBuf<double> src_q, src_w;  // channel monopole strengths, dipole weights
     bfm::DevBuf<double> ysum;           // channel sums
     bfm::DevBuf<double> mii_s, lii_s, b_s, phi_s;
     bool diag_valid = false;            // mii_s / lii_s current for the mesh

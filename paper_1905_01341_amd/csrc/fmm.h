@@ -1,7 +1,9 @@
 // Fast multipole product for the BEM operators (Section 3.9, eq3_27):
-// out_i = sum_{j != i} [ q_j / |r_i - r_j| + mu_j . (r_i - r_j) / |r_i - r_j|^3 ] / (4 pi)
-// for nch independent channels of monopole strengths q and dipole moments mu
-// over the same points. Point data are in the tree's sorted order.
+// out_i = sum_{j != i} [ q_j / |r_i - r_j| + w_j n_j . (r_i - r_j) / |r_i - r_j|^3 ] / (4 pi)
+// for nch independent channels of monopole strengths q and dipole weights w
+// over the same points. Every dipole of the method points along the vertex
+// normal n_j (ns1), so a channel carries only the scalar weight w. Point
+// data are in the tree's sorted order.
 #pragma once
 
 #include "common.h"
@@ -13,8 +15,8 @@ namespace bfm {
 struct Sources {
     int nch = 1;
     bool mono = true, dip = false;
-    const double *q = nullptr;   // [nch][n]
-    const double *mu = nullptr;  // [nch][3][n]
+    const double *q = nullptr;  // [nch][n] monopole strengths
+    const double *w = nullptr;  // [nch][n] dipole weights (moment w_j n_j)
 };
 
 struct FmmWork {

@@ -60,224 +60,207 @@ static void upload_tables(int device) {
 }
 
 // ---------------------------------------------------------------------------
-// Regular harmonics of one order m (column) for n = m..p-1 at v, written to
-// LDS rows re[tri(n, m)], im[tri(n, m)] (see common.h for the recurrence).
-template <int P_>
-__device__ inline void regular_column(int m, double x, double y, double z, double *re, double *im) {
-    const double r2 = x * x + y * y + z * z;
-    double dr = 1.0, di = 0.0;
-    for (int k = 1; k <= m; ++k) {
-        const double f = c_diag[k];
-        const double nr = (dr * x - di * y) * f;
-        const double ni = (dr * y + di * x) * f;
-        dr = nr;
-        di = ni;
-    }
-    double pr = 0.0, pi = 0.0;  // n - 2
-    double cr = dr, ci = di;    // n - 1
-    re[tri(m, m)] = cr;
-    im[tri(m, m)] = ci;
-    for (int n = m + 1; n < P_; ++n) {
-        const int t = tri(n, m);
-        const double a = c_rec_a[t], b = c_rec_b[t] * r2, c = (2.0 * n - 1.0) * z;
-        const double nr = (c * cr - b * pr) * a;
-        const double ni = (c * ci - b * pi) * a;
-        pr = cr;
-        pi = ci;
-        cr = nr;
-        ci = ni;
-        re[t] = cr;
-        im[t] = ci;
-    }
-}
-
-constexpr int kChunk = 16;  // points per harmonic chunk in P2M / L2P
-
-// P2M: Mt_n^m = sum_j q_j conj(Rt_n^m(v_j)) + (1/h) conj(mu_j . grad_v Rt_n^m(v_j)),
-// v_j = (r_j - c)/h. Gradient in the normalised basis:
-//   d/dz Rt_n^m = sqrt((n-m)(n+m)) Rt_{n-1}^m
-//   d/dx Rt_n^m = (1/2)[sqrt((n+m)(n+m-1)) Rt_{n-1}^{m-1} - sqrt((n-m)(n-m-1)) Rt_{n-1}^{m+1}]
-//   d/dy Rt_n^m = (i/2)[sqrt((n+m)(n+m-1)) Rt_{n-1}^{m-1} + sqrt((n-m)(n-m-1)) Rt_{n-1}^{m+1}]
+// P2M. One wave per leaf; lane (m, s) builds the order-m column of the
+// regular harmonics for the leaf's points s, s + S, s + 2S, ... (S = 64/p
+// point subsets) and keeps its p - m coefficients in registers; the S
+// partial sums are added through LDS at the end.
+//   Mt_n^m += q_j conj(Rt_n^m(v_j)) + (w_j / h) conj(n_j . grad_v Rt_n^m(v_j)),
+// v_j = (r_j - c)/h. The directional derivative D = n_j . grad_v follows the
+// same recurrence by forward differentiation:
+//   D Rt_m^m = [D Rt_{m-1}^{m-1} (x+iy) + Rt_{m-1}^{m-1} (n_x+i n_y)] f_m
+//   D Rt_n^m = [(2n-1)(n_z Rt_{n-1} + z D Rt_{n-1}) - b (2 v.n Rt_{n-2} + r^2 D Rt_{n-2})] a
 template <int P_, int NCH, bool MONO, bool DIP>
-__global__ void __launch_bounds__(256) k_p2m(int64_t leaf0, const int *leaf_pt, const double *centre,
-                                             double h, const double *px, const double *py,
-                                             const double *pz, int64_t n, const double *q,
-                                             const double *mu, double *mexp) {
-    constexpr int NT = P_ * (P_ + 1) / 2;
+__global__ void __launch_bounds__(64) k_p2m(int64_t leaf0, const int *leaf_pt, const double *centre,
+                                            double h, const double *px, const double *py,
+                                            const double *pz, const double *pnx, const double *pny,
+                                            const double *pnz, int64_t n, const double *q,
+                                            const double *w, double *mexp) {
+    constexpr int S = 64 / P_;
     constexpr int PP = P_ * P_;
-    static_assert(NT <= 256 && kChunk * NCH <= 256, "phase B assumes one thread per coefficient");
-    __shared__ double sre[kChunk][NT], sim[kChunk][NT];
-    __shared__ double sq[NCH][kChunk], smu[NCH][3][kChunk];
+    constexpr int RW = 2 * P_ + 1;  // padded row: lanes m and m+1 start 2p+1 doubles apart (no bank conflict)
+    __shared__ double red[S][P_][RW];  // [subset][m][2n + re/im]
+    const int lane = threadIdx.x;
+    const int m = lane % P_, s = lane / P_;
+    const bool active = s < S;
     const int leaf = blockIdx.x;
     const int64_t box = leaf0 + leaf;
     const int r0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
     const double cx = centre[3 * box], cy = centre[3 * box + 1], cz = centre[3 * box + 2];
     const double ih = 1.0 / h;
-    const int tid = threadIdx.x;
-    // accumulator ownership for phase B: thread tid < NT owns (n, m)
-    int own_n = 0, own_m = 0;
-    if (tid < NT) {
-        int t = tid;
-        while (t > own_n) {
-            ++own_n;
-            t -= own_n;
-        }
-        own_m = t;
+    double *acc = &red[active ? s : 0][m][0];  // this lane's p x 2 slots
+    // this lane's recurrence coefficients (order m), held in registers
+    double ca[P_], cb[P_];
+#pragma unroll
+    for (int k = 0; k < P_; ++k) {
+        const bool on = k > m;
+        ca[k] = on ? c_rec_a[on ? tri(k, m) : 0] : 0.0;
+        cb[k] = on ? c_rec_b[on ? tri(k, m) : 0] : 0.0;
     }
-    double ar[NCH], ai[NCH];
-    for (int c = 0; c < NCH; ++c) ar[c] = ai[c] = 0.0;
-    for (int base = r0; base < r1; base += kChunk) {
-        __syncthreads();
-        for (int wi = tid; wi < kChunk * P_; wi += blockDim.x) {  // 16 p > 256 when p = 20
-            const int pt = wi / P_, m = wi % P_;
-            const int i = base + pt;
-            if (i < r1) {
-                regular_column<P_>(m, (px[i] - cx) * ih, (py[i] - cy) * ih, (pz[i] - cz) * ih,
-                                   &sre[pt][0], &sim[pt][0]);
-            } else {
-                for (int nn = m; nn < P_; ++nn) sre[pt][tri(nn, m)] = sim[pt][tri(nn, m)] = 0.0;
-            }
-        }
-        if (tid < kChunk * NCH) {
-            const int pt = tid % kChunk, c = tid / kChunk;
-            const int i = base + pt;
-            const bool ok = i < r1;
-            sq[c][pt] = (MONO && ok) ? q[(int64_t)c * n + i] : 0.0;
-            for (int d = 0; d < 3; ++d) smu[c][d][pt] = (DIP && ok) ? mu[((int64_t)c * 3 + d) * n + i] : 0.0;
-        }
-        __syncthreads();
-        if (tid < NT) {
-            const int nn = own_n, m = own_m, t = tid;
-            const int cnt = (r1 - base) < kChunk ? (r1 - base) : kChunk;
-            for (int pt = 0; pt < cnt; ++pt) {
-                const double rr = sre[pt][t], ri = sim[pt][t];
-                double gxr = 0, gxi = 0, gyr = 0, gyi = 0, gzr = 0, gzi = 0;
-                if (DIP && nn > 0) {
-                    // R_{n-1}^m, R_{n-1}^{m-1}, R_{n-1}^{m+1}
-                    double r0r = 0, r0i = 0, rmr = 0, rmi = 0, rpr = 0, rpi = 0;
-                    if (m <= nn - 1) {
-                        r0r = sre[pt][tri(nn - 1, m)];
-                        r0i = sim[pt][tri(nn - 1, m)];
-                    }
-                    if (m >= 1) {
-                        rmr = sre[pt][tri(nn - 1, m - 1)];
-                        rmi = sim[pt][tri(nn - 1, m - 1)];
-                    } else if (nn - 1 >= 1) {  // R^{-1} = -conj(R^{1})
-                        rmr = -sre[pt][tri(nn - 1, 1)];
-                        rmi = sim[pt][tri(nn - 1, 1)];
-                    }
-                    if (m + 1 <= nn - 1) {
-                        rpr = sre[pt][tri(nn - 1, m + 1)];
-                        rpi = sim[pt][tri(nn - 1, m + 1)];
-                    }
-                    const double fz = c_dz[t], fp = 0.5 * c_dp[t], fm = 0.5 * c_dm[t];
-                    gzr = fz * r0r;
-                    gzi = fz * r0i;
-                    gxr = fp * rmr - fm * rpr;
-                    gxi = fp * rmi - fm * rpi;
-                    // i * (fp * Rm + fm * Rp)
-                    gyr = -(fp * rmi + fm * rpi);
-                    gyi = fp * rmr + fm * rpr;
+    for (int c = 0; c < NCH; ++c) {
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < 2 * P_; ++k) acc[k] = 0.0;
+            for (int j = r0 + s; j < r1; j += S) {
+                const double x = (px[j] - cx) * ih, y = (py[j] - cy) * ih, z = (pz[j] - cz) * ih;
+                const double r2 = x * x + y * y + z * z;
+                const double qq = MONO ? q[(int64_t)c * n + j] : 0.0;
+                double ux = 0.0, uy = 0.0, uz = 0.0, ww = 0.0, vu = 0.0;
+                if (DIP) {
+                    ux = pnx[j];
+                    uy = pny[j];
+                    uz = pnz[j];
+                    ww = w[(int64_t)c * n + j] * ih;
+                    vu = x * ux + y * uy + z * uz;
                 }
-                for (int c = 0; c < NCH; ++c) {
-                    if (MONO) {
-                        const double qq = sq[c][pt];
-                        ar[c] += qq * rr;
-                        ai[c] -= qq * ri;  // conj
+                // diagonal Rt_m^m (and its derivative): steps k = 1..m, predicated
+                double dr = 1.0, di = 0.0, Ddr = 0.0, Ddi = 0.0;
+#pragma unroll
+                for (int k = 1; k < P_; ++k) {
+                    if (k <= m) {
+                        const double f = c_diag[k];
+                        const double nr = (dr * x - di * y) * f, ni = (dr * y + di * x) * f;
+                        if (DIP) {
+                            const double nDr = (Ddr * x - Ddi * y + dr * ux - di * uy) * f;
+                            const double nDi = (Ddr * y + Ddi * x + dr * uy + di * ux) * f;
+                            Ddr = nDr;
+                            Ddi = nDi;
+                        }
+                        dr = nr;
+                        di = ni;
                     }
-                    if (DIP) {
-                        const double mx = smu[c][0][pt], my = smu[c][1][pt], mz = smu[c][2][pt];
-                        const double dr = mx * gxr + my * gyr + mz * gzr;
-                        const double di = mx * gxi + my * gyi + mz * gzi;
-                        ar[c] += dr * ih;
-                        ai[c] -= di * ih;
+                }
+                double cr = dr, ci = di, Dcr = Ddr, Dci = Ddi;  // degree k
+                double pr = 0.0, pi = 0.0, Dpr = 0.0, Dpi = 0.0;  // degree k - 1
+#pragma unroll
+                for (int k = 0; k < P_; ++k) {
+                    if (k > m) {
+                        const double a = ca[k], b = cb[k], e = (2.0 * k - 1.0);
+                        const double nr = (e * z * cr - b * r2 * pr) * a;
+                        const double ni = (e * z * ci - b * r2 * pi) * a;
+                        if (DIP) {
+                            const double nDr = (e * (uz * cr + z * Dcr) - b * (2.0 * vu * pr + r2 * Dpr)) * a;
+                            const double nDi = (e * (uz * ci + z * Dci) - b * (2.0 * vu * pi + r2 * Dpi)) * a;
+                            Dpr = Dcr;
+                            Dpi = Dci;
+                            Dcr = nDr;
+                            Dci = nDi;
+                        }
+                        pr = cr;
+                        pi = ci;
+                        cr = nr;
+                        ci = ni;
+                    }
+                    if (k >= m) {
+                        acc[2 * k] += qq * cr + ww * Dcr;
+                        acc[2 * k + 1] -= qq * ci + ww * Dci;  // conjugate
                     }
                 }
             }
         }
-    }
-    if (tid < NT) {
-        for (int c = 0; c < NCH; ++c) {
+        __syncthreads();
+        if (active && s == 0) {
             double *out = mexp + (box * NCH + c) * PP;
-            if (own_m == 0) {
-                out[own_n * own_n] = ar[c];
-            } else {
-                out[own_n * own_n + 2 * own_m - 1] = ar[c];
-                out[own_n * own_n + 2 * own_m] = ai[c];
+            for (int k = m; k < P_; ++k) {
+                double vr = 0.0, vi = 0.0;
+#pragma unroll
+                for (int ss = 0; ss < S; ++ss) {
+                    vr += red[ss][m][2 * k];
+                    vi += red[ss][m][2 * k + 1];
+                }
+                if (m == 0) {
+                    out[k * k] = vr;
+                } else {
+                    out[k * k + 2 * m - 1] = vr;
+                    out[k * k + 2 * m] = vi;
+                }
             }
         }
+        __syncthreads();
     }
 }
 
-// L2P: y_i += (1/h) sum_n [Lt_n^0 Rt_n^0 + 2 sum_{m>0} Re(Lt_n^m Rt_n^m)]
+// L2P, one thread per point: y_i += (1/h) sum_n [Lt_n^0 Rt_n^0 + 2 sum_{m>0}
+// Re(Lt_n^m Rt_n^m)], the harmonics built in registers order by order (the
+// order and degree are the same for every lane, so the loop is uniform).
 template <int P_, int NCH>
-__global__ void __launch_bounds__(256) k_l2p(int64_t leaf0, const int *leaf_pt, const double *centre,
+__global__ void __launch_bounds__(256) k_l2p(int64_t leaf0, const int *pt_leaf, const double *centre,
                                              double h, const double *px, const double *py,
                                              const double *pz, int64_t n, const double *lexp,
                                              double *y) {
-    constexpr int NT = P_ * (P_ + 1) / 2;
     constexpr int PP = P_ * P_;
-    constexpr int NTP = NT + 1;  // padded row
-    __shared__ double sre[kChunk][NTP], sim[kChunk][NTP];
-    __shared__ double sl[NCH][PP];
-    const int leaf = blockIdx.x;
-    const int64_t box = leaf0 + leaf;
-    const int r0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
-    const double cx = centre[3 * box], cy = centre[3 * box + 1], cz = centre[3 * box + 2];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t box = leaf0 + pt_leaf[i];
     const double ih = 1.0 / h;
-    const int tid = threadIdx.x;
-    for (int k = tid; k < NCH * PP; k += blockDim.x) (&sl[0][0])[k] = lexp[box * NCH * PP + k];
-    for (int base = r0; base < r1; base += kChunk) {
-        __syncthreads();
-        for (int wi = tid; wi < kChunk * P_; wi += blockDim.x) {
-            const int pt = wi / P_, m = wi % P_;
-            const int i = base + pt;
-            if (i < r1)
-                regular_column<P_>(m, (px[i] - cx) * ih, (py[i] - cy) * ih, (pz[i] - cz) * ih,
-                                   &sre[pt][0], &sim[pt][0]);
+    const double x = (px[i] - centre[3 * box]) * ih, yy = (py[i] - centre[3 * box + 1]) * ih,
+                 z = (pz[i] - centre[3 * box + 2]) * ih;
+    const double r2 = x * x + yy * yy + z * z;
+    const double *L = lexp + box * NCH * PP;
+    double acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+    double dr = 1.0, di = 0.0;
+#pragma unroll 1
+    for (int m = 0; m < P_; ++m) {
+        if (m > 0) {
+            const double f = c_diag[m];
+            const double nr = (dr * x - di * yy) * f, ni = (dr * yy + di * x) * f;
+            dr = nr;
+            di = ni;
         }
-        __syncthreads();
-        // 16 points x 16 partial sums per channel
-        const int pt = tid >> 4, part = tid & 15;
-        const int i = base + pt;
-        for (int c = 0; c < NCH; ++c) {
-            double acc = 0.0;
-            if (i < r1) {
-                for (int t = part; t < NT; t += 16) {
-                    // decode (n, m) of t
-                    int nn = 0, tt = t;
-                    while (tt > nn) {
-                        ++nn;
-                        tt -= nn;
-                    }
-                    const int m = tt;
-                    const double rr = sre[pt][t], ri = sim[pt][t];
-                    if (m == 0) {
-                        acc += sl[c][nn * nn] * rr;
-                    } else {
-                        acc += 2.0 * (sl[c][nn * nn + 2 * m - 1] * rr - sl[c][nn * nn + 2 * m] * ri);
-                    }
-                }
+        double cr = dr, ci = di, pr = 0.0, pi = 0.0;
+        const double wgt = (m == 0) ? 1.0 : 2.0;
+        const int im = (m == 0) ? 0 : 2 * m - 1;  // offset of the real part within degree k
+#pragma unroll 2
+        for (int k = m; k < P_; ++k) {
+            if (k > m) {
+                const int t = tri(k, m);
+                const double a = c_rec_a[t], b = c_rec_b[t], e = (2.0 * k - 1.0);
+                const double nr = (e * z * cr - b * r2 * pr) * a;
+                const double ni = (e * z * ci - b * r2 * pi) * a;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
             }
-            for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-            if (part == 0 && i < r1) y[(int64_t)c * n + i] += acc * ih;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const double *Lc = L + c * PP + k * k + im;
+                const double lim = (m == 0) ? 0.0 : Lc[1];
+                acc[c] += wgt * (Lc[0] * cr - lim * ci);
+            }
         }
     }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] += acc[c] * ih;
 }
 
 // ---------------------------------------------------------------------------
-// Grouped translation GEMM (FP64 MFMA). Wave g handles 16 columns of the
-// column space of its operator group: column = task * nch + channel.
-// KIND only separates the kernel symbols of M2L (0) and M2M/L2L (1) for
-// profilers; the code is the same.
-template <int PP, int KIND>
-__global__ void __launch_bounds__(256) k_translate(int nops, const int *tile_off, int ntiles,
-                                                   const int *op_off, const int *tsrc, const int *tdst,
-                                                   int nch, int swap, const double *T,
-                                                   const double *in, double *out) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = blockIdx.x * 4 + wave;
+// Grouped translation GEMM (FP64 MFMA). A workgroup of WAVES waves owns
+// WAVES x 16 columns (task x channel) of one operator's group and a slab of
+// ROWS output rows; the operator slab is streamed through LDS in chunks of 16
+// input coefficients and shared by all waves; each wave multiplies it by its
+// 16 gathered expansion columns. The operands are passed transposed
+// (D = in^T T^T), so lane l, element r of a result block holds column
+// l/16 + 4r and row l%16: each quarter-wave adds 16 contiguous coefficients
+// of one target expansion. Wide tiles (many waves, all rows) cut operator
+// re-reads when groups are large; row slabs give parallelism when groups are
+// small (coarse octree levels). KIND only separates the kernel symbols of
+// M2L (0) and M2M/L2L (1) for profilers.
+constexpr int kTKC = 16;
+
+template <int PP, int ROWS, int WAVES, int KIND>
+__global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *tile_off, int ntiles,
+                                                          const int *op_off, const int *tsrc,
+                                                          const int *tdst, int nch, int swap,
+                                                          const double *T, const double *in,
+                                                          double *out) {
+    static_assert(PP % ROWS == 0 && ROWS % 16 == 0, "row slab");
+    constexpr int NSLAB = PP / ROWS;
+    __shared__ double As[kTKC * ROWS];  // [k][row within slab]
+    const int g = blockIdx.x / NSLAB, slab = blockIdx.x % NSLAB;
     if (g >= ntiles) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int lo = 0, hi = nops;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -289,185 +272,192 @@ __global__ void __launch_bounds__(256) k_translate(int nops, const int *tile_off
     const int op = lo;
     const int t0 = op_off[op];
     const int ncols = (op_off[op + 1] - t0) * nch;
-    const int col = (g - tile_off[op]) * 16 + (lane & 15);
-    const bool valid = col < ncols;
-    const int task = t0 + (valid ? col / nch : 0);
-    const int ch = valid ? col % nch : 0;
-    const int sb = valid ? (swap ? tdst[task] : tsrc[task]) : 0;
-    const int db = valid ? (swap ? tsrc[task] : tdst[task]) : 0;
-    const double *bcol = in + ((int64_t)sb * nch + ch) * PP;
-    const double *A = T + (int64_t)op * PP * PP + (lane & 15);
-    const int kq = lane >> 4;
-    dbl4 acc[PP / 16];
+    const int colbase = (g - tile_off[op]) * (16 * WAVES) + wave * 16;
+    const int bcolid = colbase + (lane & 15);
+    const bool bok = bcolid < ncols;
+    const int btask = t0 + (bok ? bcolid / nch : 0);
+    const int bch = bok ? bcolid % nch : 0;
+    const int sb = bok ? (swap ? tdst[btask] : tsrc[btask]) : 0;
+    const double *bcol = in + ((int64_t)sb * nch + bch) * PP;
+    const double *Top = T + (int64_t)op * PP * PP + slab * ROWS;
+    const int kq = lane >> 4, rl = lane & 15;
+    dbl4 acc[ROWS / 16];
 #pragma unroll
-    for (int rb = 0; rb < PP / 16; ++rb) acc[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < PP; k0 += 4) {
-        const double b = valid ? bcol[k0 + kq] : 0.0;
-        const double *Ak = A + (int64_t)(k0 + kq) * PP;
+    for (int rb = 0; rb < ROWS / 16; ++rb) acc[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < PP; k0 += kTKC) {
+        __syncthreads();
+        for (int e = tid; e < kTKC * ROWS; e += 64 * WAVES) {
+            const int kk = e / ROWS, rr = e % ROWS;
+            As[e] = Top[(int64_t)(k0 + kk) * PP + rr];
+        }
+        __syncthreads();
 #pragma unroll
-        for (int rb = 0; rb < PP / 16; ++rb) {
-            const double a = Ak[rb * 16];
-            acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[rb], 0, 0, 0);
+        for (int kk = 0; kk < kTKC / 4; ++kk) {
+            const double b = bok ? bcol[k0 + 4 * kk + kq] : 0.0;
+            const double *Ak = As + (4 * kk + kq) * ROWS + rl;
+#pragma unroll
+            for (int rb = 0; rb < ROWS / 16; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, Ak[rb * 16], acc[rb], 0, 0, 0);
         }
     }
-    if (!valid) return;
-    // result layout of v_mfma_f64_16x16x4f64: lane l, element r holds
-    // row (l / 16) + 4 r, column l % 16 of the 16 x 16 block
-    double *dcol = out + ((int64_t)db * nch + ch) * PP + kq;
 #pragma unroll
-    for (int rb = 0; rb < PP / 16; ++rb) {
+    for (int r = 0; r < 4; ++r) {
+        const int col = colbase + kq + 4 * r;
+        if (col >= ncols) continue;
+        const int task = t0 + col / nch, ch = col % nch;
+        const int db = swap ? tsrc[task] : tdst[task];
+        double *dcol = out + ((int64_t)db * nch + ch) * PP + slab * ROWS + rl;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) unsafeAtomicAdd(dcol + rb * 16 + 4 * r, acc[rb][r]);
+        for (int rb = 0; rb < ROWS / 16; ++rb) unsafeAtomicAdd(dcol + rb * 16, acc[rb][r]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Near field. 1/sqrt in FP64: hardware estimate refined by two Newton steps
-// y <- y (3 - x y^2) / 2 (each step squares the relative error).
+// Near field. 1/sqrt in FP64: the hardware estimate (relative error about
+// 5e-8) refined by one Newton step with an FMA-formed residual.
 __device__ inline double rsqrt_f64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
-constexpr int kP2PThreads = 128;
+constexpr int kP2PThreads = 64;
 
 template <int NCH, bool MONO, bool DIP>
 struct SrcTile {
     double x[kP2PThreads], y[kP2PThreads], z[kP2PThreads];
     double q[MONO ? NCH : 1][kP2PThreads];
-    double mx[DIP ? NCH : 1][kP2PThreads], my[DIP ? NCH : 1][kP2PThreads],
-        mz[DIP ? NCH : 1][kP2PThreads];
+    double w[DIP ? NCH : 1][kP2PThreads];
+    double nx[DIP ? kP2PThreads : 1], ny[DIP ? kP2PThreads : 1], nz[DIP ? kP2PThreads : 1];
 };
 
 template <int NCH, bool MONO, bool DIP>
 __device__ inline void load_source(SrcTile<NCH, MONO, DIP> &s, int slot, int64_t j, const double *px,
-                                   const double *py, const double *pz, int64_t n, const double *q,
-                                   const double *mu) {
+                                   const double *py, const double *pz, const double *pnx,
+                                   const double *pny, const double *pnz, int64_t n, const double *q,
+                                   const double *w) {
     s.x[slot] = px[j];
     s.y[slot] = py[j];
     s.z[slot] = pz[j];
+    if (DIP) {
+        s.nx[slot] = pnx[j];
+        s.ny[slot] = pny[j];
+        s.nz[slot] = pnz[j];
+    }
+#pragma unroll
     for (int c = 0; c < NCH; ++c) {
         if (MONO) s.q[c][slot] = q[(int64_t)c * n + j];
-        if (DIP) {
-            s.mx[c][slot] = mu[((int64_t)c * 3 + 0) * n + j];
-            s.my[c][slot] = mu[((int64_t)c * 3 + 1) * n + j];
-            s.mz[c][slot] = mu[((int64_t)c * 3 + 2) * n + j];
-        }
+        if (DIP) s.w[c][slot] = w[(int64_t)c * n + j];
     }
 }
 
-template <int NCH, bool MONO, bool DIP>
-__device__ inline void interact(const SrcTile<NCH, MONO, DIP> &s, int cnt, double xi, double yi,
-                                double zi, double *acc) {
+// Receivers (R per thread) against the cnt sources of a tile.
+template <int NCH, bool MONO, bool DIP, int R>
+__device__ inline void interact(const SrcTile<NCH, MONO, DIP> &s, int cnt, const double *xi,
+                                const double *yi, const double *zi, double (*acc)[NCH]) {
     for (int jj = 0; jj < cnt; ++jj) {
-        const double dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double inv = (r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
-        const double inv3 = inv * inv * inv;
+        const double sx = s.x[jj], sy = s.y[jj], sz = s.z[jj];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            if (MONO) acc[c] += s.q[c][jj] * inv;
-            if (DIP) acc[c] += (s.mx[c][jj] * dx + s.my[c][jj] * dy + s.mz[c][jj] * dz) * inv3;
+        for (int k = 0; k < R; ++k) {
+            const double dx = xi[k] - sx, dy = yi[k] - sy, dz = zi[k] - sz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double inv = (r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
+            if (MONO) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) acc[k][c] += s.q[c][jj] * inv;
+            }
+            if (DIP) {
+                const double t = (s.nx[jj] * dx + s.ny[jj] * dy + s.nz[jj] * dz) * (inv * inv * inv);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) acc[k][c] += s.w[c][jj] * t;
+            }
         }
     }
 }
 
-// One block per target leaf; sources = points of the (up to 27) existing
-// neighbour leaves, merged into contiguous ranges and streamed through LDS.
-template <int NCH, bool MONO, bool DIP>
-__global__ void __launch_bounds__(kP2PThreads) k_p2p(int64_t leaf0, const int *leaf_pt, const int *nbr,
-                                                     const double *px, const double *py,
-                                                     const double *pz, int64_t n, const double *q,
-                                                     const double *mu, double *y) {
+// One block (one wave) per target leaf; sources = points of the existing
+// neighbour leaves (up to 27), merged into contiguous ranges and streamed
+// through LDS; each thread keeps R receivers so every LDS read serves R pairs.
+template <int NCH, bool MONO, bool DIP, int R>
+__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int *leaf_pt, const int2 *near_rng,
+                                                     const int *near_cnt, const double *px,
+                                                     const double *py, const double *pz,
+                                                     const double *pnx, const double *pny,
+                                                     const double *pnz, int64_t n, const double *q,
+                                                     const double *w, double *y) {
     __shared__ SrcTile<NCH, MONO, DIP> s;
-    __shared__ int rs[28], re[28], roff[29], nr;
+    __shared__ int rs[27], roff[28];
     const int leaf = blockIdx.x;
-    const int64_t box = leaf0 + leaf;
     const int tid = threadIdx.x;
+    const int nr = near_cnt[leaf];
+    if (tid < nr) rs[tid] = near_rng[27 * leaf + tid].x;
     if (tid == 0) {
-        // gather ranges, sort by start, merge contiguous ones
-        int a[27], b[27], k = 0;
-        for (int sl = 0; sl < 27; ++sl) {
-            const int qb = nbr[27 * box + sl];
-            if (qb < 0) continue;
-            const int64_t li = qb - leaf0;
-            a[k] = leaf_pt[li];
-            b[k] = leaf_pt[li + 1];
-            ++k;
-        }
-        for (int i = 1; i < k; ++i) {
-            int va = a[i], vb = b[i], j = i - 1;
-            while (j >= 0 && a[j] > va) {
-                a[j + 1] = a[j];
-                b[j + 1] = b[j];
-                --j;
-            }
-            a[j + 1] = va;
-            b[j + 1] = vb;
-        }
-        int m = 0;
-        for (int i = 0; i < k; ++i) {
-            if (m > 0 && re[m - 1] == a[i]) {
-                re[m - 1] = b[i];
-            } else {
-                rs[m] = a[i];
-                re[m] = b[i];
-                ++m;
-            }
-        }
+        int run = 0;
         roff[0] = 0;
-        for (int i = 0; i < m; ++i) roff[i + 1] = roff[i] + (re[i] - rs[i]);
-        nr = m;
+        for (int k = 0; k < nr; ++k) {
+            const int2 g = near_rng[27 * leaf + k];
+            run += g.y - g.x;
+            roff[k + 1] = run;
+        }
     }
     __syncthreads();
     const int total = roff[nr];
     const int r0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
-    for (int rc = r0; rc < r1; rc += kP2PThreads) {
-        const int i = rc + tid;
-        const bool ok = i < r1;
-        const double xi = ok ? px[i] : 0.0, yi = ok ? py[i] : 0.0, zi = ok ? pz[i] : 0.0;
-        double acc[NCH];
-        for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+    for (int rc = r0; rc < r1; rc += kP2PThreads * R) {
+        double xi[R], yi[R], zi[R], acc[R][NCH];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = rc + tid + k * kP2PThreads;
+            const bool ok = i < r1;
+            xi[k] = ok ? px[i] : 0.0;
+            yi[k] = ok ? py[i] : 0.0;
+            zi[k] = ok ? pz[i] : 0.0;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) acc[k][c] = 0.0;
+        }
         for (int t0 = 0; t0 < total; t0 += kP2PThreads) {
             __syncthreads();
             const int f = t0 + tid;
             if (f < total) {
                 int r = 0;
                 while (roff[r + 1] <= f) ++r;
-                load_source(s, tid, (int64_t)rs[r] + (f - roff[r]), px, py, pz, n, q, mu);
+                load_source(s, tid, (int64_t)rs[r] + (f - roff[r]), px, py, pz, pnx, pny, pnz, n, q, w);
             }
             __syncthreads();
             const int cnt = (total - t0) < kP2PThreads ? (total - t0) : kP2PThreads;
-            interact(s, cnt, xi, yi, zi, acc);
+            interact<NCH, MONO, DIP, R>(s, cnt, xi, yi, zi, acc);
         }
-        if (ok)
-            for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[c];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int i = rc + tid + k * kP2PThreads;
+            if (i < r1)
+                for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[k][c];
+        }
     }
 }
 
-// All-pairs sum (checking path): block of receivers x every source.
+// All-pairs sum (checking path): 64 receivers per block x every source.
 template <int NCH, bool MONO, bool DIP>
 __global__ void __launch_bounds__(kP2PThreads) k_direct(const double *px, const double *py,
-                                                        const double *pz, int64_t n, const double *q,
-                                                        const double *mu, double *y) {
+                                                        const double *pz, const double *pnx,
+                                                        const double *pny, const double *pnz, int64_t n,
+                                                        const double *q, const double *w, double *y) {
     __shared__ SrcTile<NCH, MONO, DIP> s;
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kP2PThreads + tid;
     const bool ok = i < n;
-    const double xi = ok ? px[i] : 0.0, yi = ok ? py[i] : 0.0, zi = ok ? pz[i] : 0.0;
-    double acc[NCH];
-    for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+    double xi[1] = {ok ? px[i] : 0.0}, yi[1] = {ok ? py[i] : 0.0}, zi[1] = {ok ? pz[i] : 0.0};
+    double acc[1][NCH];
+    for (int c = 0; c < NCH; ++c) acc[0][c] = 0.0;
     for (int64_t t0 = 0; t0 < n; t0 += kP2PThreads) {
         __syncthreads();
-        if (t0 + tid < n) load_source(s, tid, t0 + tid, px, py, pz, n, q, mu);
+        if (t0 + tid < n) load_source(s, tid, t0 + tid, px, py, pz, pnx, pny, pnz, n, q, w);
         __syncthreads();
         const int cnt = (n - t0) < kP2PThreads ? (int)(n - t0) : kP2PThreads;
-        interact(s, cnt, xi, yi, zi, acc);
+        interact<NCH, MONO, DIP, 1>(s, cnt, xi, yi, zi, acc);
     }
     if (ok)
-        for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[c];
+        for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[0][c];
 }
 
 __global__ void k_zero(double *p, int64_t n) {
@@ -525,10 +515,10 @@ void fmm_prepare_ops(FmmWork &w, int p, hipStream_t st) {
 static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // Algorithmic flops of one source-receiver pair: shared geometry 3 (d) + 5
-// (r^2) + 1 (1/r) [+ 2 for 1/r^3 with dipoles]; per channel 2 (q/r) and
-// 7 (mu . d / r^3: 5 for the dot product, 2 for the scaled add).
+// (r^2) + 1 (1/r) [+ 5 for n.d and 3 for n.d / r^3 with dipoles]; per channel
+// 2 (q/r) and 2 (w n.d / r^3).
 static double p2p_flops_per_pair(int nch, bool mono, bool dip) {
-    return 9.0 + (dip ? 2.0 : 0.0) + nch * ((mono ? 2.0 : 0.0) + (dip ? 7.0 : 0.0));
+    return 9.0 + (dip ? 8.0 : 0.0) + nch * ((mono ? 2.0 : 0.0) + (dip ? 2.0 : 0.0));
 }
 
 static int prof_begin(FmmWork &w, int cls, hipStream_t st) { return w.prof ? w.prof->begin(cls, st) : -1; }
@@ -536,20 +526,43 @@ static void prof_end(FmmWork &w, int idx, hipStream_t st, double flops) {
     if (w.prof) w.prof->end(idx, st, flops, 0.0);
 }
 
+// Middle row-slab height: a multiple of 16 dividing p^2, at most 80.
+constexpr int mid_rows(int PP) { return PP == 144 ? 48 : (PP == 400 ? 80 : (PP >= 64 ? 64 : PP)); }
+
 template <int P_>
 static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, const double *T,
                       const double *in, double *out, hipStream_t st) {
-    prepare_tiles(tl, nch, st);
-    const int nt = tl.ntiles[nch];
+    constexpr int PP = P_ * P_;
+    const int64_t cols = tl.ntasks * nch;
+    // Enough waves for the whole chip: all rows per wave (wide 128-column
+    // tiles, fewest operator re-reads) when there are many columns, row slabs
+    // (more waves, columns re-read per slab) when there are few.
+    const int64_t wave_tiles = (cols + 15) / 16;
+    const int shape = (wave_tiles >= 8192) ? 0 : (wave_tiles * (PP / mid_rows(PP)) >= 8192 ? 1 : 2);
+    const int width = (shape == 0) ? 128 : 64;
+    prepare_tiles(tl, nch, width, st);
+    const int nt = tl.ntiles_for(nch, width);
     if (nt <= 0) return;
     const int pi = prof_begin(w, cls, st);
-    auto kern = (cls == KC_M2L) ? k_translate<P_ * P_, 0> : k_translate<P_ * P_, 1>;
-    kern<<<nblk(nt, 4), 256, 0, st>>>(tl.nops, tl.tile_off[nch].get(), nt,
-                                                       tl.op_off.get(), tl.src.get(), tl.dst.get(),
-                                                       nch, swap ? 1 : 0, T, in, out);
+    const int *to = tl.tile_for(nch, width);
+    const int sw = swap ? 1 : 0;
+    if (shape == 0) {
+        auto kern = (cls == KC_M2L) ? k_translate<PP, PP, 8, 0> : k_translate<PP, PP, 8, 1>;
+        kern<<<(unsigned)nt, 512, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(), tl.dst.get(), nch,
+                                           sw, T, in, out);
+    } else if (shape == 1) {
+        constexpr int R = mid_rows(PP);
+        auto kern = (cls == KC_M2L) ? k_translate<PP, R, 4, 0> : k_translate<PP, R, 4, 1>;
+        kern<<<(unsigned)(nt * (PP / R)), 256, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(),
+                                                         tl.dst.get(), nch, sw, T, in, out);
+    } else {
+        constexpr int R = 16;
+        auto kern = (cls == KC_M2L) ? k_translate<PP, R, 4, 0> : k_translate<PP, R, 4, 1>;
+        kern<<<(unsigned)(nt * (PP / R)), 256, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(),
+                                                         tl.dst.get(), nch, sw, T, in, out);
+    }
     BFM_LAUNCHED();
-    const double PP = (double)P_ * P_;
-    prof_end(w, pi, st, 2.0 * PP * PP * (double)tl.ntasks * nch);
+    prof_end(w, pi, st, 2.0 * (double)PP * PP * (double)tl.ntasks * nch);
 }
 
 template <int P_, int NCH, bool MONO, bool DIP>
@@ -568,14 +581,15 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     BFM_LAUNCHED();
     // near field first (writes y), far field adds
     int pi = prof_begin(w, KC_P2P, st);
-    k_p2p<NCH, MONO, DIP><<<(unsigned)t.nleaf, kP2PThreads, 0, st>>>(
-        leaf0, t.leaf_pt.get(), t.nbr.get(), t.px.get(), t.py.get(), t.pz.get(), t.n, src.q, src.mu, y);
+    k_p2p<NCH, MONO, DIP, 2><<<(unsigned)t.nleaf, kP2PThreads, 0, st>>>(
+        t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
+        t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, y);
     BFM_LAUNCHED();
     prof_end(w, pi, st, (double)(t.npairs_near - t.n) * p2p_flops_per_pair(NCH, MONO, DIP));
     pi = prof_begin(w, KC_P2M, st);
-    k_p2m<P_, NCH, MONO, DIP><<<(unsigned)t.nleaf, 256, 0, st>>>(
-        leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf, t.px.get(), t.py.get(), t.pz.get(), t.n,
-        src.q, src.mu, M);
+    k_p2m<P_, NCH, MONO, DIP><<<(unsigned)t.nleaf, 64, 0, st>>>(
+        leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf, t.px.get(), t.py.get(), t.pz.get(),
+        t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, M);
     BFM_LAUNCHED();
     prof_end(w, pi, st, 0.0);
     for (int l = lmax; l >= 3; --l)
@@ -584,8 +598,8 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     for (int l = 3; l <= lmax; ++l)
         translate<P_>(w, KC_M2M_L2L, *t.m2m[l], NCH, true, w.ops_l2l.get(), L, L, st);
     pi = prof_begin(w, KC_L2P, st);
-    k_l2p<P_, NCH><<<(unsigned)t.nleaf, 256, 0, st>>>(leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf,
-                                                      t.px.get(), t.py.get(), t.pz.get(), t.n, L, y);
+    k_l2p<P_, NCH><<<nblk(t.n, 256), 256, 0, st>>>(leaf0, t.pt_leaf.get(), t.box_centre.get(), hleaf,
+                                                   t.px.get(), t.py.get(), t.pz.get(), t.n, L, y);
     BFM_LAUNCHED();
     prof_end(w, pi, st, 0.0);
 }
@@ -593,7 +607,7 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
 template <int NCH, bool MONO, bool DIP>
 static void run_direct(const Tree &t, const Sources &src, double *y, hipStream_t st) {
     k_direct<NCH, MONO, DIP><<<nblk(t.n, kP2PThreads), kP2PThreads, 0, st>>>(
-        t.px.get(), t.py.get(), t.pz.get(), t.n, src.q, src.mu, y);
+        t.px.get(), t.py.get(), t.pz.get(), t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, y);
     BFM_LAUNCHED();
 }
 

@@ -137,30 +137,28 @@ void to_original(bfm_ctx *c, const double *in, double *out) {
 
 // ---------------------------------------------------------------------------
 // Diagonals + right-hand side: five channels over the same points,
-// coordinates taken relative to the cube centre X:
-//   ch0: mu = s n                       -> sum M_ij
-//   ch1..3: q = -s n_a, mu = s n r_a    -> sum M_ij r_ja - sum L_ij n_ja
-//   ch4: mu = s phi n                   -> sum M_ij phi_j
+// coordinates taken relative to the cube centre X; every dipole points along
+// the vertex normal, so a channel stores its scalar weight w (moment w n_j):
+//   ch0: w = s                          -> sum M_ij
+//   ch1..3: q = -s n_a, w = s r_a       -> sum M_ij r_ja - sum L_ij n_ja
+//   ch4: w = s phi                      -> sum M_ij phi_j
 
 __global__ void k_diag_sources(const double *px, const double *py, const double *pz, const double *ps,
                                const double *pnx, const double *pny, const double *pnz,
                                const double *phi, int64_t n, double X, double Y, double Z, double *q,
-                               double *mu) {
+                               double *w) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double s = ps[i];
     const double nn[3] = {pnx[i], pny[i], pnz[i]};
     const double r[3] = {px[i] - X, py[i] - Y, pz[i] - Z};
-    const double f = phi ? phi[i] : 0.0;
     q[i] = 0.0;
     q[4 * n + i] = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        mu[(0 * 3 + d) * n + i] = s * nn[d];
-        mu[(4 * 3 + d) * n + i] = s * f * nn[d];
-    }
+    w[i] = s;
+    w[4 * n + i] = s * (phi ? phi[i] : 0.0);
     for (int a = 0; a < 3; ++a) {
         q[(1 + a) * n + i] = -s * nn[a];
-        for (int d = 0; d < 3; ++d) mu[((1 + a) * 3 + d) * n + i] = s * nn[d] * r[a];
+        w[(1 + a) * n + i] = s * r[a];
     }
 }
 
@@ -195,18 +193,18 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
         to_sorted(c, phi_dev, phs);
     }
     double *q = c->src_q.ensure(5 * n);
-    double *mu = c->src_mu.ensure(15 * n);
+    double *wd = c->src_w.ensure(5 * n);
     double *y = c->ysum.ensure(5 * n);
     k_diag_sources<<<nblk(n, 256), 256, 0, st>>>(t.px.get(), t.py.get(), t.pz.get(), t.ps.get(),
                                                  t.pnx.get(), t.pny.get(), t.pnz.get(), phs, n, X, Y, Z,
-                                                 q, mu);
+                                                 q, wd);
     BFM_LAUNCHED();
     Sources src;
     src.nch = 5;
     src.mono = true;
     src.dip = true;
     src.q = q;
-    src.mu = mu;
+    src.w = wd;
     fmm_apply(c->fmm_diag, t, src, y, false, st);
     c->mii_s.ensure(n);
     c->lii_s.ensure(n);
@@ -222,19 +220,13 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
 // ---------------------------------------------------------------------------
 // Product with A = f L + g M (eq3_27), sorted order.
 
-__global__ void k_sources_1ch(const double *ps, const double *pnx, const double *pny, const double *pnz,
-                              int64_t n, double f, const double *x, double g, const double *yv,
-                              double *q, double *mu) {
+__global__ void k_sources_1ch(const double *ps, int64_t n, double f, const double *x, double g,
+                              const double *yv, double *q, double *w) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double s = ps[i];
     if (x) q[i] = f * s * x[i];
-    if (yv) {
-        const double w = g * s * yv[i];
-        mu[i] = w * pnx[i];
-        mu[n + i] = w * pny[i];
-        mu[2 * n + i] = w * pnz[i];
-    }
+    if (yv) w[i] = g * s * yv[i];
 }
 
 __global__ void k_finalize_1ch(const double *y, int64_t n, double f, const double *x, double g,
@@ -258,21 +250,21 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
     const int64_t n = c->nv;
     const bool mono = (f != 0.0 && x_s), dip = (g != 0.0 && y_s);
     double *q = c->src_q.ensure(5 * n);
-    double *mu = c->src_mu.ensure(15 * n);
+    double *wd = c->src_w.ensure(5 * n);
     double *y = c->ysum.ensure(5 * n);
     if (!mono && !dip) {
         BFM_HIP(hipMemsetAsync(out_s, 0, sizeof(double) * n, st));
         return;
     }
-    k_sources_1ch<<<nblk(n, 256), 256, 0, st>>>(t.ps.get(), t.pnx.get(), t.pny.get(), t.pnz.get(), n, f,
-                                                mono ? x_s : nullptr, g, dip ? y_s : nullptr, q, mu);
+    k_sources_1ch<<<nblk(n, 256), 256, 0, st>>>(t.ps.get(), n, f, mono ? x_s : nullptr, g,
+                                                dip ? y_s : nullptr, q, wd);
     BFM_LAUNCHED();
     Sources src;
     src.nch = 1;
     src.mono = mono;
     src.dip = dip;
     src.q = q;
-    src.mu = mu;
+    src.w = wd;
     fmm_apply(c->fmm, t, src, y, direct, st);
     k_finalize_1ch<<<nblk(n, 256), 256, 0, st>>>(y, n, f, mono ? x_s : nullptr, g, dip ? y_s : nullptr,
                                                  add_diag ? c->lii_s.get() : nullptr,

@@ -14,7 +14,7 @@ constexpr int kKeyBits = 15;  // bits per axis of the point keys (levels 0..15)
 
 // Translation tasks grouped by operator: tasks op_off[o]..op_off[o+1] use
 // operator o; task t moves expansion src[t] into expansion dst[t] (global
-// box indices). tile_off[o] counts 16-column wave tiles for a given channel
+// box indices). tile_off counts workgroup tiles of a given column width per
 // count (see fmm.hip), prepared per channel count on demand.
 struct TaskList {
     int nops = 0;
@@ -22,10 +22,14 @@ struct TaskList {
     std::vector<int> op_off_h;  // host copy [nops + 1]
     DevBuf<int> op_off;         // [nops + 1]
     DevBuf<int> src, dst;       // [ntasks]
-    // wave-tile prefix per channel count (index = nch), built lazily
-    DevBuf<int> tile_off[8];
-    int ntiles[8] = {0};
-    bool tiles_ready[8] = {false};
+    // workgroup-tile prefix per (channel count, tile width), built lazily:
+    // slot = nch * 2 + (width == 128)
+    DevBuf<int> tile_off[16];
+    int ntiles[16] = {0};
+    bool tiles_ready[16] = {false};
+    static int slot(int nch, int width) { return nch * 2 + (width == 128 ? 1 : 0); }
+    int ntiles_for(int nch, int width) const { return ntiles[slot(nch, width)]; }
+    const int *tile_for(int nch, int width) const { return tile_off[slot(nch, width)].get(); }
 };
 
 struct Tree {
@@ -51,6 +55,11 @@ struct Tree {
     DevBuf<double> box_centre;  // [nbox][3]
     DevBuf<int> nbr;            // [nbox][27] neighbours (incl. self at slot 13), -1 if empty
     DevBuf<int> leaf_pt;        // [nleaf + 1] point ranges of leaves
+    DevBuf<int> pt_leaf;        // [n] leaf index of every sorted point
+    // near-field sources of every leaf as merged contiguous point ranges:
+    // near_rng[leaf][k] = (start, end) for k < near_cnt[leaf] (at most 27)
+    DevBuf<int2> near_rng;      // [nleaf][27]
+    DevBuf<int> near_cnt;       // [nleaf]
 
     // sorted point data (per tree): positions, weights, normals
     DevBuf<double> px, py, pz;  // [n]
@@ -73,7 +82,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
 void sort_geometry(Tree &t, const double *s, const double *nrm, hipStream_t st);
 
 // Build the wave-tile prefix of a task list for a channel count.
-void prepare_tiles(TaskList &tl, int nch, hipStream_t st);
+void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st);
 
 // Device-wide exclusive scan of int32 (in place allowed); returns the total.
 int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp);

@@ -285,6 +285,11 @@ __global__ void k_level_scatter(const uint64_t *key, int64_t n, int shift, const
     box_pt0[b] = (int)i;
 }
 
+__global__ void k_pt_leaf(const int *flag, const int *pos, int64_t n, int *pt_leaf) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) pt_leaf[i] = pos[i] + flag[i] - 1;  // inclusive prefix - 1
+}
+
 __device__ inline int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t v) {
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
@@ -357,6 +362,47 @@ __global__ void k_leaf_near(int64_t nleaf, int64_t leaf0, const int *box_pt0, in
     }
     atomicAdd(pairs, src * (unsigned long long)(p1 - p0));
     atomicMax(maxocc, p1 - p0);
+}
+
+// Merged near-field source ranges per leaf: the existing neighbours' point
+// ranges sorted by start, touching ranges joined (Morton order makes many
+// neighbours adjacent in the sorted point array).
+__global__ void k_leaf_ranges(int64_t nleaf, int64_t leaf0, const int *leaf_pt, const int *nbr,
+                              int2 *rng, int *cnt) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    const int64_t b = leaf0 + i;
+    int a[27], e[27], k = 0;
+    for (int s = 0; s < 27; ++s) {
+        const int q = nbr[27 * b + s];
+        if (q < 0) continue;
+        const int64_t qi = q - leaf0;
+        a[k] = leaf_pt[qi];
+        e[k] = leaf_pt[qi + 1];
+        ++k;
+    }
+    for (int x = 1; x < k; ++x) {
+        const int va = a[x], ve = e[x];
+        int y = x - 1;
+        while (y >= 0 && a[y] > va) {
+            a[y + 1] = a[y];
+            e[y + 1] = e[y];
+            --y;
+        }
+        a[y + 1] = va;
+        e[y + 1] = ve;
+    }
+    int m = 0;
+    int2 *out = rng + 27 * i;
+    for (int x = 0; x < k; ++x) {
+        if (m > 0 && out[m - 1].y == a[x]) {
+            out[m - 1].y = e[x];
+        } else {
+            out[m] = make_int2(a[x], e[x]);
+            ++m;
+        }
+    }
+    cnt[i] = m;
 }
 
 // ---------------------------------------------------------------------------
@@ -451,7 +497,7 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
     tl.ntasks = n;
     tl.op_off_h.assign(nops + 1, 0);
     tl.op_off.ensure(nops + 1);
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < 16; ++c) {
         tl.ntiles[c] = 0;
         tl.tiles_ready[c] = false;
     }
@@ -478,23 +524,24 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
     BFM_HIP(hipStreamSynchronize(st));
 }
 
-void prepare_tiles(TaskList &tl, int nch, hipStream_t st) {
-    BFM_CHECK(nch >= 1 && nch < 8, BFM_EINVAL, "channel count out of range");
-    if (tl.tiles_ready[nch]) return;
+void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st) {
+    BFM_CHECK(nch >= 1 && nch < 8 && (width == 64 || width == 128), BFM_EINVAL, "tile shape out of range");
+    const int sl = TaskList::slot(nch, width);
+    if (tl.tiles_ready[sl]) return;
     int run = 0;
     std::vector<int> pre(tl.nops + 1);
     for (int o = 0; o < tl.nops; ++o) {
         pre[o] = run;
         const int cols = (tl.op_off_h[o + 1] - tl.op_off_h[o]) * nch;
-        run += (cols + 15) / 16;
+        run += (cols + width - 1) / width;
     }
     pre[tl.nops] = run;
-    tl.tile_off[nch].ensure(tl.nops + 1);
-    BFM_HIP(hipMemcpyAsync(tl.tile_off[nch].get(), pre.data(), sizeof(int) * (tl.nops + 1),
+    tl.tile_off[sl].ensure(tl.nops + 1);
+    BFM_HIP(hipMemcpyAsync(tl.tile_off[sl].get(), pre.data(), sizeof(int) * (tl.nops + 1),
                            hipMemcpyHostToDevice, st));
     BFM_HIP(hipStreamSynchronize(st));
-    tl.ntiles[nch] = run;
-    tl.tiles_ready[nch] = true;
+    tl.ntiles[sl] = run;
+    tl.tiles_ready[sl] = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -623,6 +670,11 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                       t.lvl_off[l], l, t.box_key.get(),
                                                       t.box_level.get(), t.box_pt0.get());
         BFM_LAUNCHED();
+        if (l == lmax) {
+            t.pt_leaf.ensure(n);
+            k_pt_leaf<<<nblk(n, 256), 256, 0, st>>>(flag.get(), pos.get(), n, t.pt_leaf.get());
+            BFM_LAUNCHED();
+        }
     }
     k_box_meta<<<nblk(t.nbox, 128), 128, 0, st>>>(t.nbox, lmax, li, t.origin[0], t.origin[1],
                                                   t.origin[2], t.box_key.get(), t.box_level.get(), n,
@@ -647,6 +699,11 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     BFM_HIP(hipStreamSynchronize(st));
     t.npairs_near = (int64_t)npairs;
     t.max_leaf = maxocc;
+    t.near_rng.ensure(27 * t.nleaf);
+    t.near_cnt.ensure(t.nleaf);
+    k_leaf_ranges<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.leaf_pt.get(), t.nbr.get(),
+                                                      t.near_rng.get(), t.near_cnt.get());
+    BFM_LAUNCHED();
 
     // M2L lists over levels 2..lmax
     {
