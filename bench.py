@@ -43,13 +43,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=3000)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--form", choices=["tuned", "plain"], default="tuned")
+    ap.add_argument("--precond-degree", type=int, default=12)
+    ap.add_argument("--plain-steps", type=int, default=2)
     return ap.parse_args()
 
 
 def cpu_baseline(cl, phi, matvecs, rows_n):
     """The oracle (unchanged) on a bounded receiver sample of the same
     workload, scaled to one solve: one pass of the diagonal/RHS sums plus
-    `matvecs` direct products, each costing N receivers."""
+    `matvecs` direct products (the plain solve's count; the oracle's GMRES is
+    unpreconditioned), each costing N receivers."""
     import oracle
     oracle.build(force=False)
     rows = np.arange(0, cl.nv, max(1, cl.nv // rows_n), dtype=np.int64)[:rows_n]
@@ -85,40 +89,49 @@ def main():
     xyz_t = torch.tensor(cl.xyz, dtype=torch.float64, device=dev).contiguous()
     phi_t = torch.tensor(phi, dtype=torch.float64, device=dev).contiguous()
     q_t = torch.zeros_like(phi_t)
-    sv = bfm.Solver(device=0, p=a.p, p_diag=a.p_diag, leaf_target=a.leaf, lmax=a.lmax,
-                    gmres_tol=a.tol, gmres_restart=a.restart, gmres_maxit=1000)
-    sv.set_cluster(cl)
-    torch.cuda.synchronize()
+    def make_solver(precond):
+        sv = bfm.Solver(device=0, p=a.p, p_diag=a.p_diag, leaf_target=a.leaf, lmax=a.lmax,
+                        gmres_tol=a.tol, gmres_restart=a.restart, gmres_maxit=1000,
+                        precond=precond, precond_degree=a.precond_degree)
+        sv.set_cluster(cl)
+        return sv
 
-    def step():
-        _check = bfm._check
-        _check(sv.lib.bfm_set_positions_dev(sv.h, bfm.ctypes.c_void_p(xyz_t.data_ptr())))
-        return sv.solve_dev(phi_t, q_t)
+    def run(sv, steps, warmup, profile):
+        def step():
+            bfm._check(sv.lib.bfm_set_positions_dev(sv.h, bfm.ctypes.c_void_p(xyz_t.data_ptr())))
+            return sv.solve_dev(phi_t, q_t)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if profile:
+            sv.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = sv.profile_read() if profile else None
+        sv.profile(False)
+        return (t1 - t0) * 1e3 / steps, infos[-1], prof
 
-    for _ in range(a.warmup):
-        info = step()
-    torch.cuda.synchronize()
-    if not a.no_profile:
-        sv.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(a.steps):
-        infos.append(step())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = sv.profile_read() if not a.no_profile else None
-    sv.profile(False)
-    ms = (t1 - t0) * 1e3 / a.steps
-    info = infos[-1]
-    stats = sv.tree_stats()
-
-    err = None
-    gold = os.path.join(ROOT, "tests", "golden", f"{a.workload}_q_oracle.npy")
-    if os.path.exists(gold):
+    def error_vs_oracle():
+        gold = os.path.join(ROOT, "tests", "golden", f"{a.workload}_q_oracle.npy")
+        if not os.path.exists(gold):
+            return None
         qo = np.load(gold).astype(np.float64)
-        qg = q_t.cpu().numpy()
-        err = float(np.linalg.norm(qg - qo) / np.linalg.norm(qo))
+        return float(np.linalg.norm(q_t.cpu().numpy() - qo) / np.linalg.norm(qo))
+
+    # plain FP64 (the paper's unpreconditioned GMRES from a zero guess)
+    sv_plain = make_solver(bfm.PRECOND_NONE)
+    ms_plain, info_plain, _ = run(sv_plain, a.plain_steps, a.warmup, False)
+    err_plain = error_vs_oracle()
+    sv_plain.close()
+    # tuned form: timed for the reported value
+    tuned = a.form == "tuned"
+    sv = make_solver(bfm.PRECOND_SH if tuned else bfm.PRECOND_NONE)
+    ms, info, prof = run(sv, a.steps, a.warmup, not a.no_profile)
+    stats = sv.tree_stats()
+    err = error_vs_oracle()
 
     roof = None
     if prof:
@@ -143,20 +156,26 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{a.workload}: {cl.nb} icosphere bubbles, {cl.nv} nodes, {cl.nt} triangles"),
-            "form": "plain_fp64", "p": a.p, "p_diag": sv.opt.p_diag or min(20, a.p + 4),
+            "form": ("tuned: FP64 FMM products, GMRES right-preconditioned per bubble in spherical "
+                     f"harmonics (degree {a.precond_degree})") if tuned else "plain FP64",
+            "p": a.p, "p_diag": sv.opt.p_diag or min(20, a.p + 4),
             "lmax": stats["lmax"], "leaves": stats["leaves"], "near_pairs": stats["near_pairs"],
             "m2l_pairs": stats["m2l_pairs"], "gmres_tol": a.tol, "gmres_restart": a.restart,
             "iterations": info["iterations"], "matvecs": info["matvecs"],
             "rel_residual": info["rel_residual"], "err_vs_oracle": err,
             "phase_ms": {"tree": round(info["t_tree_ms"], 3), "diag": round(info["t_diag_ms"], 3),
                          "gmres": round(info["t_solve_ms"], 3)},
+            "plain_fp64": {"s_per_step": round(ms_plain / 1e3, 6), "iterations": info_plain["iterations"],
+                           "matvecs": info_plain["matvecs"], "err_vs_oracle": err_plain,
+                           "steps": a.plain_steps},
+            "speedup_vs_plain": round(ms_plain / ms, 3),
         },
         "roofline": roof,
     }
     if prof:
         out["kernels_ms_per_step"] = {k: round(v["ms"] / a.steps, 3) for k, v in prof.items()}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cl, phi, info["matvecs"], a.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(cl, phi, info_plain["matvecs"], a.cpu_rows)
     print(json.dumps(out), flush=True)
 
 

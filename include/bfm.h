@@ -55,6 +55,13 @@ enum {
     BFM_EUNSUPPORTED = -6 /* option combination not built */
 };
 
+/* Preconditioner of the GMRES iteration. */
+enum {
+    BFM_PRECOND_NONE = 0, /* unpreconditioned GMRES, as in the paper (Section 3.8) */
+    BFM_PRECOND_SH = 1    /* per-bubble spherical-harmonic approximate inverse (needs
+                             bfm_set_sphere_template), applied from the right */
+};
+
 /* Arithmetic of the fast multipole product. */
 enum {
     BFM_PREC_FP64 = 0, /* FP64 near field and FP64 translations */
@@ -75,6 +82,8 @@ typedef struct bfm_options {
     double gmres_tol;  /* stop when ||b - L q||_2 <= gmres_tol ||b||_2 */
     int gmres_restart; /* Krylov dimension before restart (1..128) */
     int gmres_maxit;   /* total iteration limit */
+    int precond;       /* BFM_PRECOND_* */
+    int precond_degree; /* highest harmonic degree resolved by BFM_PRECOND_SH, (d+1)^2 <= nd */
 } bfm_options;
 
 typedef struct bfm_solve_info {
@@ -91,7 +100,8 @@ typedef struct bfm_solve_info {
 typedef struct bfm_ctx bfm_ctx;
 
 /* Fill *opt with defaults: p = 16, p_diag = 0, lmax = 0, leaf_target = 64,
- * FP64, tol 1e-10, restart 30, maxit 300, device 0, stream NULL. */
+ * FP64, tol 1e-10, restart 30, maxit 300, device 0, stream NULL, no
+ * preconditioner (precond_degree 12). */
 int bfm_default_options(bfm_options *opt);
 
 /* Create a handle on opt->device. The handle owns every device buffer
@@ -117,6 +127,20 @@ int bfm_set_options(bfm_ctx *ctx, const bfm_options *opt);
  */
 int bfm_set_mesh(bfm_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, const int32_t *tri,
                  int32_t nb, const int64_t *vtx_off, const int64_t *tri_off);
+
+/*
+ * Spherical-harmonic template for BFM_PRECOND_SH: every bubble has nd
+ * vertices numbered like a template unit sphere whose vertex directions are
+ * dirs (host, [nd][3], unit vectors) - the parametrisation by the initial
+ * spherical angles that the paper's shape filter uses (Section 3.7). The
+ * first bubble's triangles give the template's connectivity. The
+ * preconditioner scales harmonics of degree n on bubble b by (2n+1)/R_b, the
+ * inverse of the single layer's eigenvalue R/(2n+1) on a sphere (R_b from
+ * the bubble's area), and degrees above precond_degree by the first
+ * unresolved one. Errors: BFM_EINVAL when a bubble range does not hold nd
+ * vertices or the mesh has not been set.
+ */
+int bfm_set_sphere_template(bfm_ctx *ctx, int32_t nd, const double *dirs);
 
 /* Move the vertices (same connectivity): xyz host [nv][3] or device
  * (_dev, FP64 [nv][3]). Geometry and octree are rebuilt at the next use. */

@@ -18,6 +18,8 @@ BFM_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "EMESH", -6: "EUNSUPPORTED"}
 PREC_FP64 = 0
 PREC_FP32 = 1
+PRECOND_NONE = 0
+PRECOND_SH = 1
 ABI_VERSION = 1
 
 
@@ -40,6 +42,8 @@ class Options(ctypes.Structure):
         ("gmres_tol", ctypes.c_double),
         ("gmres_restart", ctypes.c_int),
         ("gmres_maxit", ctypes.c_int),
+        ("precond", ctypes.c_int),
+        ("precond_degree", ctypes.c_int),
     ]
 
 
@@ -83,6 +87,7 @@ def load(path: str = LIB_PATH):
         "bfm_set_options": ([P, ctypes.POINTER(Options)], I),
         "bfm_set_mesh": ([P, I64, P, I64, P, ctypes.c_int32, P, P], I),
         "bfm_set_positions": ([P, P], I),
+        "bfm_set_sphere_template": ([P, ctypes.c_int32, P], I),
         "bfm_set_positions_dev": ([P, P], I),
         "bfm_geometry": ([P, P, P], I),
         "bfm_diagonals": ([P, P, P, P, P], I),
@@ -172,8 +177,15 @@ class Solver:
                                      _ptr(vo), _ptr(to)))
         self.nv = xyz.shape[0]
 
-    def set_cluster(self, cl):
+    def set_cluster(self, cl, template=True):
         self.set_mesh(cl.xyz, cl.tri, cl.vtx_off, cl.tri_off)
+        nd = int(cl.vtx_off[1] - cl.vtx_off[0])
+        if template and cl.nb * nd == cl.nv:
+            self.set_sphere_template(cl.dirs[:nd])
+
+    def set_sphere_template(self, dirs):
+        d = np.ascontiguousarray(dirs, dtype=np.float64)
+        _check(self.lib.bfm_set_sphere_template(self.h, d.shape[0], _ptr(d)))
 
     def set_positions(self, xyz):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)

@@ -2,6 +2,7 @@
 // internal errors and turns them into a return code plus a thread-local
 // message; nothing throws across the boundary.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -46,6 +47,8 @@ static void check_options(const bfm_options &o) {
     BFM_CHECK(o.gmres_restart >= 1 && o.gmres_restart <= 128, BFM_EINVAL,
               "gmres_restart must be in [1, 128]");
     BFM_CHECK(o.gmres_maxit >= 1, BFM_EINVAL, "gmres_maxit must be >= 1");
+    BFM_CHECK(o.precond == BFM_PRECOND_NONE || o.precond == BFM_PRECOND_SH, BFM_EINVAL, "unknown precond");
+    BFM_CHECK(o.precond_degree >= 1 && o.precond_degree <= 40, BFM_EINVAL, "precond_degree must be in [1, 40]");
 }
 
 struct DeviceScope {
@@ -136,6 +139,8 @@ int bfm_default_options(bfm_options *opt) {
     opt->gmres_tol = 1e-10;
     opt->gmres_restart = 30;
     opt->gmres_maxit = 300;
+    opt->precond = BFM_PRECOND_NONE;
+    opt->precond_degree = 12;
     return BFM_OK;
 }
 
@@ -191,6 +196,7 @@ int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
             c->diag_valid = false;
         }
         if (p_change) c->diag_valid = false;
+        if (opt->precond_degree != c->pre.nmax) c->pre.ready = false;
     });
 }
 
@@ -228,7 +234,15 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
             for (int e = 0; e < 3; ++e) adj[cur[tri[3 * k + e]]++] = (int)k;
         c->nv = nv;
         c->nt = nt;
-        c->nb = nb;
+        c->nb = nb >= 1 ? nb : 1;
+        if (vo.empty()) {
+            vo = {0, nv};
+            to = {0, nt};
+        }
+        c->tri0_h.clear();
+        for (int64_t k = 3 * to[0]; k < 3 * to[1]; ++k) c->tri0_h.push_back(tri[k] - (int)vo[0]);
+        c->pre.nd = 0;
+        c->pre.ready = false;
         c->vtx_off = vo;
         c->tri_off = to;
         c->xyz.ensure(3 * nv);
@@ -242,6 +256,27 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
         BFM_HIP(hipMemcpyAsync(c->v2t.get(), adj.data(), sizeof(int) * 3 * nt, hipMemcpyHostToDevice, st));
         BFM_HIP(hipStreamSynchronize(st));
         invalidate_positions(c);
+    });
+}
+
+int bfm_set_sphere_template(bfm_ctx *c, int32_t nd, const double *dirs) {
+    return guarded([&] {
+        BFM_CHECK(c && dirs, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        BFM_CHECK(nd >= 4 && (int64_t)nd * c->nb == c->nv, BFM_EINVAL,
+                  "every bubble must hold nd vertices (nv = nb * nd)");
+        for (int b = 0; b <= c->nb; ++b)
+            BFM_CHECK(c->vtx_off[b] == (int64_t)b * nd, BFM_EINVAL, "bubble vertex ranges must be b * nd");
+        for (int v : c->tri0_h) BFM_CHECK(v >= 0 && v < nd, BFM_EINVAL, "first bubble's triangles leave its range");
+        for (int v = 0; v < nd; ++v) {
+            const double r = std::sqrt(dirs[3 * v] * dirs[3 * v] + dirs[3 * v + 1] * dirs[3 * v + 1] +
+                                       dirs[3 * v + 2] * dirs[3 * v + 2]);
+            BFM_CHECK(std::fabs(r - 1.0) < 1e-6, BFM_EINVAL, "template directions must be unit vectors");
+        }
+        c->pre.dirs_h.assign(dirs, dirs + 3 * (size_t)nd);
+        c->pre.tri_h = c->tri0_h;
+        c->pre.nd = nd;
+        c->pre.ready = false;
     });
 }
 

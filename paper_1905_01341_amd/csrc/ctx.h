@@ -8,6 +8,17 @@
 #include "prof.h"
 #include "tree.h"
 
+namespace bfm {
+struct Precond {
+    int nd = 0, nc = 0, nmax = -1;
+    double cc = 0.0;
+    bool ready = false;
+    std::vector<double> dirs_h;  // template directions [nd][3]
+    std::vector<int> tri_h;      // template triangles (first bubble, local indices)
+    DevBuf<double> G, Gp, fac, R, X, C, Y;
+};
+}  // namespace bfm
+
 struct bfm_ctx {
     bfm_options opt{};
     int device = 0;
@@ -40,8 +51,11 @@ struct bfm_ctx {
     bfm::DevBuf<double> mii_s, lii_s, b_s, phi_s;
     bool diag_valid = false;            // mii_s / lii_s current for the mesh
 
+    bfm::Precond pre;
+    std::vector<int> tri0_h;  // first bubble's triangles (local indices), kept for templates
+
     // GMRES workspace (sorted order)
-    bfm::DevBuf<double> V, work, x_s, part, small;
+    bfm::DevBuf<double> V, work, x_s, part, small, zbuf, tbuf;
     double *host_small = nullptr;       // pinned
 };
 
@@ -62,6 +76,11 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
 
 // GMRES in sorted order: solves L x = b_s, x_s in/out.
 void gmres_sorted(bfm_ctx *c, double *x_s, bool use_guess, bfm_solve_info *info);
+
+// Spherical-harmonic preconditioner (precond.hip)
+void precond_build(bfm_ctx *c);
+void precond_radii(bfm_ctx *c);
+void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);
 
 // gather (original -> sorted) and scatter (sorted -> original)
 void to_sorted(bfm_ctx *c, const double *in_orig, double *out_s);

@@ -323,139 +323,156 @@ __device__ inline double rsqrt_f64(double x) {
 
 constexpr int kP2PThreads = 64;
 
-template <int NCH, bool MONO, bool DIP>
-struct SrcTile {
-    double x[kP2PThreads], y[kP2PThreads], z[kP2PThreads];
-    double q[MONO ? NCH : 1][kP2PThreads];
-    double w[DIP ? NCH : 1][kP2PThreads];
-    double nx[DIP ? kP2PThreads : 1], ny[DIP ? kP2PThreads : 1], nz[DIP ? kP2PThreads : 1];
-};
-
-template <int NCH, bool MONO, bool DIP>
-__device__ inline void load_source(SrcTile<NCH, MONO, DIP> &s, int slot, int64_t j, const double *px,
-                                   const double *py, const double *pz, const double *pnx,
-                                   const double *pny, const double *pnz, int64_t n, const double *q,
-                                   const double *w) {
-    s.x[slot] = px[j];
-    s.y[slot] = py[j];
-    s.z[slot] = pz[j];
-    if (DIP) {
-        s.nx[slot] = pnx[j];
-        s.ny[slot] = pny[j];
-        s.nz[slot] = pnz[j];
-    }
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        if (MONO) s.q[c][slot] = q[(int64_t)c * n + j];
-        if (DIP) s.w[c][slot] = w[(int64_t)c * n + j];
-    }
-}
-
-// Receivers (R per thread) against the cnt sources of a tile.
+// Receivers xi..zi (R per lane) against sources [j0, j1): every lane reads
+// the same source at the same time, so the loads are wave-uniform (scalar
+// loads of read-only data) and no LDS staging is needed.
 template <int NCH, bool MONO, bool DIP, int R>
-__device__ inline void interact(const SrcTile<NCH, MONO, DIP> &s, int cnt, const double *xi,
-                                const double *yi, const double *zi, double (*acc)[NCH]) {
-    for (int jj = 0; jj < cnt; ++jj) {
-        const double sx = s.x[jj], sy = s.y[jj], sz = s.z[jj];
+__device__ inline void p2p_pair(double sx, double sy, double sz, const double *sq, const double *sw,
+                                double nx, double ny, double nz, const double *xi, const double *yi,
+                                const double *zi, double (*acc)[NCH]) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const double dx = xi[k] - sx, dy = yi[k] - sy, dz = zi[k] - sz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double inv = (r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
-            if (MONO) {
+    for (int k = 0; k < R; ++k) {
+        const double dx = xi[k] - sx, dy = yi[k] - sy, dz = zi[k] - sz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double inv = (r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
+        if (MONO) {
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) acc[k][c] += s.q[c][jj] * inv;
-            }
-            if (DIP) {
-                const double t = (s.nx[jj] * dx + s.ny[jj] * dy + s.nz[jj] * dz) * (inv * inv * inv);
+            for (int c = 0; c < NCH; ++c) acc[k][c] += sq[c] * inv;
+        }
+        if (DIP) {
+            const double tt = (nx * dx + ny * dy + nz * dz) * (inv * inv * inv);
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) acc[k][c] += s.w[c][jj] * t;
-            }
+            for (int c = 0; c < NCH; ++c) acc[k][c] += sw[c] * tt;
         }
     }
 }
 
-// One block (one wave) per target leaf; sources = points of the existing
-// neighbour leaves (up to 27), merged into contiguous ranges and streamed
-// through LDS; each thread keeps R receivers so every LDS read serves R pairs.
+// Receivers xi..zi (R per lane) against sources [j0, j1): every lane reads
+// the same source at the same time, so the loads are wave-uniform (scalar
+// loads of read-only data); sources are fetched in batches of B so one wait
+// covers B sources.
 template <int NCH, bool MONO, bool DIP, int R>
-__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int *leaf_pt, const int2 *near_rng,
-                                                     const int *near_cnt, const double *px,
-                                                     const double *py, const double *pz,
-                                                     const double *pnx, const double *pny,
-                                                     const double *pnz, int64_t n, const double *q,
-                                                     const double *w, double *y) {
-    __shared__ SrcTile<NCH, MONO, DIP> s;
-    __shared__ int rs[27], roff[28];
-    const int leaf = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int nr = near_cnt[leaf];
-    if (tid < nr) rs[tid] = near_rng[27 * leaf + tid].x;
-    if (tid == 0) {
-        int run = 0;
-        roff[0] = 0;
-        for (int k = 0; k < nr; ++k) {
-            const int2 g = near_rng[27 * leaf + k];
-            run += g.y - g.x;
-            roff[k + 1] = run;
-        }
-    }
-    __syncthreads();
-    const int total = roff[nr];
-    const int r0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
-    for (int rc = r0; rc < r1; rc += kP2PThreads * R) {
-        double xi[R], yi[R], zi[R], acc[R][NCH];
+__device__ inline void p2p_range(int j0, int j1, const double *__restrict__ px,
+                                 const double *__restrict__ py, const double *__restrict__ pz,
+                                 const double *__restrict__ pnx, const double *__restrict__ pny,
+                                 const double *__restrict__ pnz, int64_t n,
+                                 const double *__restrict__ q, const double *__restrict__ w,
+                                 const double *xi, const double *yi, const double *zi,
+                                 double (*acc)[NCH]) {
+    constexpr int B = (NCH == 1 && !DIP) ? 8 : (NCH == 1 ? 4 : 2);
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        double bx[B], by[B], bz[B], bq[B][NCH], bw[B][NCH], bnx[B], bny[B], bnz[B];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = rc + tid + k * kP2PThreads;
-            const bool ok = i < r1;
-            xi[k] = ok ? px[i] : 0.0;
-            yi[k] = ok ? py[i] : 0.0;
-            zi[k] = ok ? pz[i] : 0.0;
+        for (int u = 0; u < B; ++u) {
+            bx[u] = px[j + u];
+            by[u] = py[j + u];
+            bz[u] = pz[j + u];
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) acc[k][c] = 0.0;
-        }
-        for (int t0 = 0; t0 < total; t0 += kP2PThreads) {
-            __syncthreads();
-            const int f = t0 + tid;
-            if (f < total) {
-                int r = 0;
-                while (roff[r + 1] <= f) ++r;
-                load_source(s, tid, (int64_t)rs[r] + (f - roff[r]), px, py, pz, pnx, pny, pnz, n, q, w);
+            for (int c = 0; c < NCH; ++c) {
+                bq[u][c] = MONO ? q[(int64_t)c * n + j + u] : 0.0;
+                bw[u][c] = DIP ? w[(int64_t)c * n + j + u] : 0.0;
             }
-            __syncthreads();
-            const int cnt = (total - t0) < kP2PThreads ? (total - t0) : kP2PThreads;
-            interact<NCH, MONO, DIP, R>(s, cnt, xi, yi, zi, acc);
+            bnx[u] = DIP ? pnx[j + u] : 0.0;
+            bny[u] = DIP ? pny[j + u] : 0.0;
+            bnz[u] = DIP ? pnz[j + u] : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int i = rc + tid + k * kP2PThreads;
-            if (i < r1)
-                for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[k][c];
+        for (int u = 0; u < B; ++u)
+            p2p_pair<NCH, MONO, DIP, R>(bx[u], by[u], bz[u], bq[u], bw[u], bnx[u], bny[u], bnz[u], xi, yi, zi,
+                                        acc);
+    }
+    for (; j < j1; ++j) {
+        double sq[NCH], sw[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            sq[c] = MONO ? q[(int64_t)c * n + j] : 0.0;
+            sw[c] = DIP ? w[(int64_t)c * n + j] : 0.0;
         }
+        p2p_pair<NCH, MONO, DIP, R>(px[j], py[j], pz[j], sq, sw, DIP ? pnx[j] : 0.0, DIP ? pny[j] : 0.0,
+                                    DIP ? pnz[j] : 0.0, xi, yi, zi, acc);
     }
 }
 
-// All-pairs sum (checking path): 64 receivers per block x every source.
+template <int NCH, bool MONO, bool DIP, int R>
+__device__ inline void p2p_pass(int rc, int r1, int nr, const int2 *__restrict__ rng,
+                                const double *__restrict__ px, const double *__restrict__ py,
+                                const double *__restrict__ pz, const double *__restrict__ pnx,
+                                const double *__restrict__ pny, const double *__restrict__ pnz,
+                                int64_t n, const double *__restrict__ q, const double *__restrict__ w,
+                                double *__restrict__ y) {
+    const int lane = threadIdx.x;
+    double xi[R], yi[R], zi[R], acc[R][NCH];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        const bool ok = i < r1;
+        // idle lanes sit far away: their sums are never stored
+        xi[k] = ok ? px[i] : 1e100;
+        yi[k] = ok ? py[i] : 0.0;
+        zi[k] = ok ? pz[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) acc[k][c] = 0.0;
+    }
+    for (int g = 0; g < nr; ++g) {
+        const int2 r = rng[g];
+        p2p_range<NCH, MONO, DIP, R>(r.x, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        if (i < r1)
+            for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[k][c];
+    }
+}
+
+// One wave per near-field work item (a leaf and up to 64 of its receivers,
+// items ordered by decreasing pair count); sources = the leaf's merged
+// near-field ranges (the points of up to 27 neighbour leaves).
 template <int NCH, bool MONO, bool DIP>
-__global__ void __launch_bounds__(kP2PThreads) k_direct(const double *px, const double *py,
-                                                        const double *pz, const double *pnx,
-                                                        const double *pny, const double *pnz, int64_t n,
-                                                        const double *q, const double *w, double *y) {
-    __shared__ SrcTile<NCH, MONO, DIP> s;
-    const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * kP2PThreads + tid;
-    const bool ok = i < n;
-    double xi[1] = {ok ? px[i] : 0.0}, yi[1] = {ok ? py[i] : 0.0}, zi[1] = {ok ? pz[i] : 0.0};
-    double acc[1][NCH];
+__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int2 *__restrict__ items,
+                                                     const int *__restrict__ leaf_pt,
+                                                     const int2 *__restrict__ near_rng,
+                                                     const int *__restrict__ near_cnt,
+                                                     const double *__restrict__ px,
+                                                     const double *__restrict__ py,
+                                                     const double *__restrict__ pz,
+                                                     const double *__restrict__ pnx,
+                                                     const double *__restrict__ pny,
+                                                     const double *__restrict__ pnz, int64_t n,
+                                                     const double *__restrict__ q,
+                                                     const double *__restrict__ w, double *__restrict__ y) {
+    static_assert(kP2PChunk == kP2PThreads, "one receiver per lane");
+    const int2 it = items[blockIdx.x];
+    const int leaf = it.x, rc = it.y;
+    const int r1 = leaf_pt[leaf + 1];
+    p2p_pass<NCH, MONO, DIP, 1>(rc, r1, near_cnt[leaf], near_rng + 27 * (int64_t)leaf, px, py, pz, pnx,
+                                pny, pnz, n, q, w, y);
+}
+
+// All-pairs sum (checking path): 64 receivers per wave x every source.
+template <int NCH, bool MONO, bool DIP>
+__global__ void __launch_bounds__(kP2PThreads) k_direct(const double *__restrict__ px,
+                                                        const double *__restrict__ py,
+                                                        const double *__restrict__ pz,
+                                                        const double *__restrict__ pnx,
+                                                        const double *__restrict__ pny,
+                                                        const double *__restrict__ pnz, int64_t n,
+                                                        const double *__restrict__ q,
+                                                        const double *__restrict__ w,
+                                                        double *__restrict__ y) {
+    const int64_t base = (int64_t)blockIdx.x * kP2PThreads;
+    const int r1 = (int)((n - base) < kP2PThreads ? (n - base) : kP2PThreads);
+    const int2 all = make_int2(0, (int)n);
+    // receivers base + lane (pass of one receiver per lane), sources all points
+    double xi[1], yi[1], zi[1], acc[1][NCH];
+    const int i = (int)base + threadIdx.x;
+    const bool ok = threadIdx.x < (unsigned)r1;
+    xi[0] = ok ? px[i] : 1e100;
+    yi[0] = ok ? py[i] : 0.0;
+    zi[0] = ok ? pz[i] : 0.0;
     for (int c = 0; c < NCH; ++c) acc[0][c] = 0.0;
-    for (int64_t t0 = 0; t0 < n; t0 += kP2PThreads) {
-        __syncthreads();
-        if (t0 + tid < n) load_source(s, tid, t0 + tid, px, py, pz, pnx, pny, pnz, n, q, w);
-        __syncthreads();
-        const int cnt = (n - t0) < kP2PThreads ? (int)(n - t0) : kP2PThreads;
-        interact<NCH, MONO, DIP, 1>(s, cnt, xi, yi, zi, acc);
-    }
+    p2p_range<NCH, MONO, DIP, 1>(all.x, all.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
     if (ok)
         for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[0][c];
 }
@@ -581,8 +598,8 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     BFM_LAUNCHED();
     // near field first (writes y), far field adds
     int pi = prof_begin(w, KC_P2P, st);
-    k_p2p<NCH, MONO, DIP, 2><<<(unsigned)t.nleaf, kP2PThreads, 0, st>>>(
-        t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
+    k_p2p<NCH, MONO, DIP><<<(unsigned)t.n_p2p_items, kP2PThreads, 0, st>>>(
+        t.p2p_items.get(), t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
         t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, y);
     BFM_LAUNCHED();
     prof_end(w, pi, st, (double)(t.npairs_near - t.n) * p2p_flops_per_pair(NCH, MONO, DIP));

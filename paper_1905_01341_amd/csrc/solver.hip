@@ -352,6 +352,16 @@ __global__ void k_sub_from(const double *b, double *v, int64_t n) {
     if (i < n) v[i] = b[i] - v[i];
 }
 
+__global__ void k_fill(double *v, int64_t n, double a) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) v[i] = a;
+}
+
+__global__ void k_axpy(double a, const double *x, double *y, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
 __global__ void k_copy(const double *a, double *b, int64_t n) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
@@ -456,6 +466,15 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
         return hs[0];
     };
     int matvecs = 0;
+    const bool pc = c->opt.precond == BFM_PRECOND_SH;
+    double *Z = nullptr, *Tv = nullptr;
+    if (pc) {
+        BFM_CHECK(c->pre.nd > 0, BFM_EINVAL, "BFM_PRECOND_SH needs bfm_set_sphere_template");
+        precond_build(c);
+        precond_radii(c);
+        Z = c->zbuf.ensure(n);
+        Tv = c->tbuf.ensure(n);
+    }
     // ||b||
     norm2_to(b, L.nrm);
     const double nb = std::sqrt(std::max(read_scalar(L.nrm), 0.0));
@@ -492,7 +511,12 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
         for (int j = 0; j < m && it < maxit; ++j) {
             double *vj = V + (int64_t)j * n;
             double *wj = V + (int64_t)(j + 1) * n;
-            matvec_sorted(c, 1.0, vj, 0.0, nullptr, wj, true, prec, false);
+            if (pc) {  // right preconditioning: w = A P^{-1} v_j
+                precond_apply(c, vj, Z);
+                matvec_sorted(c, 1.0, Z, 0.0, nullptr, wj, true, prec, false);
+            } else {
+                matvec_sorted(c, 1.0, vj, 0.0, nullptr, wj, true, prec, false);
+            }
             ++matvecs;
             // pass 1
             const int pg = c->prof.begin(KC_GMRES, st);
@@ -522,8 +546,18 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
         }
         k_trisolve<<<1, 1, 0, st>>>(sm, L, k);
         BFM_LAUNCHED();
-        k_combine<<<nblk(n, 256), 256, 0, st>>>(V, k, n, sm + L.yv, x, n);
-        BFM_LAUNCHED();
+        if (pc) {  // x += P^{-1} V y
+            k_fill<<<nblk(n, 256), 256, 0, st>>>(Tv, n, 0.0);
+            BFM_LAUNCHED();
+            k_combine<<<nblk(n, 256), 256, 0, st>>>(V, k, n, sm + L.yv, Tv, n);
+            BFM_LAUNCHED();
+            precond_apply(c, Tv, Z);
+            k_axpy<<<nblk(n, 256), 256, 0, st>>>(1.0, Z, x, n);
+            BFM_LAUNCHED();
+        } else {
+            k_combine<<<nblk(n, 256), 256, 0, st>>>(V, k, n, sm + L.yv, x, n);
+            BFM_LAUNCHED();
+        }
         // true residual
         matvec_sorted(c, 1.0, x, 0.0, nullptr, V, true, prec, false);
         ++matvecs;

@@ -11,6 +11,7 @@
 namespace bfm {
 
 constexpr int kKeyBits = 15;  // bits per axis of the point keys (levels 0..15)
+constexpr int kP2PChunk = 64;  // receivers per near-field work item
 
 // Translation tasks grouped by operator: tasks op_off[o]..op_off[o+1] use
 // operator o; task t moves expansion src[t] into expansion dst[t] (global
@@ -60,6 +61,10 @@ struct Tree {
     // near_rng[leaf][k] = (start, end) for k < near_cnt[leaf] (at most 27)
     DevBuf<int2> near_rng;      // [nleaf][27]
     DevBuf<int> near_cnt;       // [nleaf]
+    // near-field work items: (leaf, first receiver) of chunks of at most
+    // kP2PChunk receivers, ordered by decreasing pair count
+    DevBuf<int2> p2p_items;
+    int64_t n_p2p_items = 0;
 
     // sorted point data (per tree): positions, weights, normals
     DevBuf<double> px, py, pz;  // [n]
@@ -83,6 +88,11 @@ void sort_geometry(Tree &t, const double *s, const double *nrm, hipStream_t st);
 
 // Build the wave-tile prefix of a task list for a channel count.
 void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st);
+
+// Stable LSD radix sort of (u64 key, int value) on the low `bits` bits of the
+// key; results end in (keys, vals) (the *_tmp buffers are scratch of size n).
+void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits,
+                hipStream_t st);
 
 // Device-wide exclusive scan of int32 (in place allowed); returns the total.
 int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp);

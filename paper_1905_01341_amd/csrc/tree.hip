@@ -178,6 +178,29 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, 
     }
 }
 
+void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits,
+                hipStream_t st) {
+    if (n <= 1) return;
+    const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+    DevBuf<int> hist, scanned, tmp;
+    hist.ensure((size_t)256 * nblocks);
+    scanned.ensure((size_t)256 * nblocks);
+    uint64_t *kin = keys, *kout = keys_tmp;
+    int *vin = vals, *vout = vals_tmp;
+    int passes = (bits + 7) / 8;
+    if (passes & 1) ++passes;  // even pass count: the result lands back in keys / vals
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        k_rs_hist<<<nblocks, RS_THREADS, 0, st>>>(kin, n, shift, hist.get(), nblocks);
+        BFM_LAUNCHED();
+        exclusive_scan(hist.get(), scanned.get(), (int64_t)256 * nblocks, st, tmp);
+        k_rs_scatter<<<nblocks, RS_THREADS, 0, st>>>(kin, vin, n, shift, scanned.get(), nblocks, kout, vout);
+        BFM_LAUNCHED();
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Exclusive scan (int32)
 
@@ -405,6 +428,35 @@ __global__ void k_leaf_ranges(int64_t nleaf, int64_t leaf0, const int *leaf_pt, 
     cnt[i] = m;
 }
 
+// Near-field work items: chunks of at most kP2PChunk receivers per leaf,
+// keyed by pair count so the largest run first.
+__global__ void k_item_count(int64_t nleaf, const int *leaf_pt, int *cnt) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    cnt[i] = (leaf_pt[i + 1] - leaf_pt[i] + kP2PChunk - 1) / kP2PChunk;
+}
+
+__global__ void k_item_fill(int64_t nleaf, const int *leaf_pt, const int *off, const int2 *rng,
+                            const int *rcnt, int2 *items, uint64_t *key, int *idx) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    int src = 0;
+    for (int k = 0; k < rcnt[i]; ++k) src += rng[27 * i + k].y - rng[27 * i + k].x;
+    const int r0 = leaf_pt[i], r1 = leaf_pt[i + 1];
+    int o = off[i];
+    for (int r = r0; r < r1; r += kP2PChunk, ++o) {
+        const int nrec = (r1 - r) < kP2PChunk ? (r1 - r) : kP2PChunk;
+        items[o] = make_int2((int)i, r);
+        key[o] = 0xffffffffull - (uint64_t)((unsigned)nrec * (unsigned)src);  // descending cost
+        idx[o] = o;
+    }
+}
+
+__global__ void k_item_permute(const int2 *in, const int *idx, int64_t n, int2 *out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[idx[i]];
+}
+
 // ---------------------------------------------------------------------------
 // Interaction lists
 
@@ -607,24 +659,8 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     k_morton<<<nblk(n, 256), 256, 0, st>>>(xyz, n, t.origin[0], t.origin[1], t.origin[2], inv_cell,
                                            t.key_a.get(), t.idx_a.get());
     BFM_LAUNCHED();
-    const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
-    DevBuf<int> hist, scanned, tmp;
-    hist.ensure((size_t)256 * nblocks);
-    scanned.ensure((size_t)256 * nblocks);
-    uint64_t *kin = t.key_a.get(), *kout = t.key_b.get();
-    int *vin = t.idx_a.get(), *vout = t.idx_b.get();
-    for (int pass = 0; pass < 6; ++pass) {
-        const int shift = 8 * pass;
-        k_rs_hist<<<nblocks, RS_THREADS, 0, st>>>(kin, n, shift, hist.get(), nblocks);
-        BFM_LAUNCHED();
-        exclusive_scan(hist.get(), scanned.get(), (int64_t)256 * nblocks, st, tmp);
-        k_rs_scatter<<<nblocks, RS_THREADS, 0, st>>>(kin, vin, n, shift, scanned.get(), nblocks, kout,
-                                                     vout);
-        BFM_LAUNCHED();
-        std::swap(kin, kout);
-        std::swap(vin, vout);
-    }
-    // six passes: the result is back in key_a / idx_a
+    radix_sort(t.key_a.get(), t.idx_a.get(), t.key_b.get(), t.idx_b.get(), n, 3 * kKeyBits, st);
+    DevBuf<int> tmp;
 
     // boxes per level
     DevBuf<unsigned long long> cnt;
@@ -704,6 +740,29 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     k_leaf_ranges<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.leaf_pt.get(), t.nbr.get(),
                                                       t.near_rng.get(), t.near_cnt.get());
     BFM_LAUNCHED();
+    {
+        DevBuf<int> icnt, ioff, iidx, iidx2;
+        DevBuf<uint64_t> ikey, ikey2;
+        DevBuf<int2> raw;
+        icnt.ensure(t.nleaf);
+        ioff.ensure(t.nleaf);
+        k_item_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), icnt.get());
+        BFM_LAUNCHED();
+        const int64_t ni = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);
+        raw.ensure(ni);
+        ikey.ensure(ni);
+        ikey2.ensure(ni);
+        iidx.ensure(ni);
+        iidx2.ensure(ni);
+        k_item_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.near_rng.get(),
+                                                        t.near_cnt.get(), raw.get(), ikey.get(), iidx.get());
+        BFM_LAUNCHED();
+        radix_sort(ikey.get(), iidx.get(), ikey2.get(), iidx2.get(), ni, 32, st);
+        t.p2p_items.ensure(ni);
+        k_item_permute<<<nblk(ni, 256), 256, 0, st>>>(raw.get(), iidx.get(), ni, t.p2p_items.get());
+        BFM_LAUNCHED();
+        t.n_p2p_items = ni;
+    }
 
     // M2L lists over levels 2..lmax
     {

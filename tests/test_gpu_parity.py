@@ -165,3 +165,43 @@ def test_degenerate_mesh_is_rejected():
     with pytest.raises(bfm.BfmError) as e:
         sv.solve(phi)
     assert e.value.code == -5
+
+
+def test_sh_preconditioned_solve_single_bubble(single):
+    """Right preconditioning leaves the solution unchanged and cuts the
+    iteration count (the single layer is nearly diagonal in harmonics)."""
+    cl, phi, s, n = single
+    q_ref, _ = oracle.solve(cl.xyz, cl.tri, phi, method="lu")
+    plain = _solver(cl, p=16, leaf_target=16, gmres_tol=1e-12)
+    q0, i0 = plain.solve(phi)
+    pre = _solver(cl, p=16, leaf_target=16, gmres_tol=1e-12, precond=bfm.PRECOND_SH, precond_degree=12)
+    q1, i1 = pre.solve(phi)
+    print(f"plain {i0['iterations']} it, preconditioned {i1['iterations']} it")
+    assert i1["converged"] and rel(q1, q_ref) < 1e-6, (rel(q1, q_ref), i1)
+    assert i1["iterations"] < i0["iterations"] / 2
+
+
+def test_sh_preconditioned_solve_cluster(c100):
+    cl, phi, s, n, rows = c100
+    sv = _solver(cl, p=16, gmres_tol=1e-10, precond=bfm.PRECOND_SH, precond_degree=12)
+    q, info = sv.solve(phi)
+    assert info["converged"], info
+    d = oracle.sums(cl.xyz, s, n, phi, rows=rows)
+    _, Lii, _ = oracle.diagonals(cl.xyz, s, n, rows=rows, sm=d)
+    b = oracle.rhs(phi, d["B"], rows=rows)
+    Lq = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, q, rows=rows) + Lii * q[rows]
+    print(f"preconditioned: {info['iterations']} it, oracle-system residual {rel(Lq, b):.3e}")
+    assert rel(Lq, b) < 1e-6 and info["iterations"] < 60
+
+
+def test_sphere_template_validation():
+    cl, phi = wl.make("single")
+    sv = bfm.Solver()
+    sv.set_mesh(cl.xyz, cl.tri)
+    with pytest.raises(bfm.BfmError):
+        sv.set_sphere_template(cl.dirs[:100])  # wrong vertex count
+    with pytest.raises(bfm.BfmError):
+        sv.set_sphere_template(cl.dirs * 2.0)  # not unit vectors
+    sv.set_options(precond=bfm.PRECOND_SH)
+    with pytest.raises(bfm.BfmError):
+        sv.solve(phi)  # no template set
