@@ -18,5 +18,5 @@ GMRES, and hand-computed geometry of a regular octahedron.
 """
 from .core import (  # noqa: F401
     build, geometry, sums, diagonals, rhs, offdiag_mvp, dense_offdiag,
-    system_dense, matvec_L, gmres, solve, num_threads,
+    system_dense, matvec_L, gmres, bubble_block_inverse, solve, num_threads,
 )

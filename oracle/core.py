@@ -173,9 +173,12 @@ def matvec_L(xyz, s, n, Lii):
     return mv
 
 
-def gmres(matvec, b, x0=None, tol=1e-12, restart=50, maxit=2000):
+def gmres(matvec, b, x0=None, tol=1e-12, restart=50, maxit=2000, prec=None):
     """Restarted GMRES(m) (Saad and Schultz 1986), modified Gram-Schmidt
-    Arnoldi, Givens rotations; stops when ||b - A x|| <= tol ||b||.
+    Arnoldi, Givens rotations; stops when ||b - A x|| <= tol ||b|| (the true
+    residual of the unpreconditioned system). prec, if given, is applied from
+    the right (Arnoldi on A prec; x = x0 + prec(V y)), which changes the
+    iterates but not the solution.
 
     Returns (x, info) with info = dict(iterations, restarts, rel_residual,
     converged)."""
@@ -184,6 +187,7 @@ def gmres(matvec, b, x0=None, tol=1e-12, restart=50, maxit=2000):
     x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
     if nrm_b == 0.0:
         return np.zeros_like(b), dict(iterations=0, restarts=0, rel_residual=0.0, converged=True)
+    right = (lambda v: v) if prec is None else prec
     it = 0
     restarts = 0
     r = b - matvec(x)
@@ -201,7 +205,7 @@ def gmres(matvec, b, x0=None, tol=1e-12, restart=50, maxit=2000):
         V[0] = r / beta
         k_used = 0
         for k in range(m):
-            w = matvec(V[k])
+            w = matvec(right(V[k]))
             it += 1
             for i in range(k + 1):
                 H[i, k] = np.dot(V[i], w)
@@ -226,7 +230,7 @@ def gmres(matvec, b, x0=None, tol=1e-12, restart=50, maxit=2000):
         y = np.zeros(k_used)
         for i in range(k_used - 1, -1, -1):
             y[i] = (gvec[i] - np.dot(H[i, i + 1:k_used], y[i + 1:k_used])) / H[i, i]
-        x = x + V[:k_used].T @ y
+        x = x + right(V[:k_used].T @ y)
         r = b - matvec(x)
         beta = np.linalg.norm(r)
         restarts += 1
@@ -234,11 +238,36 @@ def gmres(matvec, b, x0=None, tol=1e-12, restart=50, maxit=2000):
     return x, dict(iterations=it, restarts=restarts, rel_residual=rel, converged=rel <= tol)
 
 
-def solve(xyz, tri, phi, method="gmres", tol=1e-12, restart=50, x0=None, maxit=2000):
+def bubble_block_inverse(xyz, s, n, Lii, vtx_off):
+    """Right preconditioner for GMRES: the exact inverse of every bubble's
+    own diagonal block of L (dense LU per bubble, scipy). Bubble b owns
+    vertices vtx_off[b]:vtx_off[b+1]."""
+    import scipy.linalg as sla
+    xyz, s, n = _f64(xyz), _f64(s), _f64(n)
+    facs = []
+    for b in range(len(vtx_off) - 1):
+        o0, o1 = int(vtx_off[b]), int(vtx_off[b + 1])
+        Lb, _ = dense_offdiag(xyz[o0:o1], s[o0:o1], n[o0:o1])
+        Lb[np.diag_indices_from(Lb)] = Lii[o0:o1]
+        facs.append((o0, o1, sla.lu_factor(Lb)))
+
+    def apply(v):
+        out = np.empty_like(v)
+        for o0, o1, f in facs:
+            out[o0:o1] = sla.lu_solve(f, v[o0:o1])
+        return out
+    return apply
+
+
+def solve(xyz, tri, phi, method="gmres", tol=1e-12, restart=50, x0=None, maxit=2000, vtx_off=None,
+          matvec_hook=None):
     """Solve L q = b (eq3_2) for q = dphi/dn at every vertex.
 
     method "gmres": restarted GMRES with direct-sum products (any N);
+    method "gmres_bj": the same, right-preconditioned by the exact inverses
+    of the bubbles' own diagonal blocks (vtx_off gives the bubble ranges);
     method "lu": dense LU of the assembled matrix (small N).
+    matvec_hook(k) is called after every direct product (progress reports).
     Returns (q, info) with info carrying the diagonals and b.
     """
     xyz = _f64(xyz)
@@ -254,6 +283,22 @@ def solve(xyz, tri, phi, method="gmres", tol=1e-12, restart=50, x0=None, maxit=2
         q = np.linalg.solve(L, b)
         info.update(iterations=0, rel_residual=np.linalg.norm(L @ q - b) / np.linalg.norm(b))
         return q, info
-    q, gi = gmres(matvec_L(xyz, s, n, Lii), b, x0=x0, tol=tol, restart=restart, maxit=maxit)
+    base = matvec_L(xyz, s, n, Lii)
+    count = [0]
+
+    def mv(v):
+        y = base(v)
+        count[0] += 1
+        if matvec_hook:
+            matvec_hook(count[0])
+        return y
+    prec = None
+    if method == "gmres_bj":
+        if vtx_off is None:
+            vtx_off = np.array([0, xyz.shape[0]])
+        prec = bubble_block_inverse(xyz, s, n, Lii, vtx_off)
+    elif method != "gmres":
+        raise ValueError(method)
+    q, gi = gmres(mv, b, x0=x0, tol=tol, restart=restart, maxit=maxit, prec=prec)
     info.update(gi)
     return q, info

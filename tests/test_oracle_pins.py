@@ -262,3 +262,17 @@ def test_pins_catch_planted_mistakes():
     assert np.abs((-M).sum(axis=1) + 0.5).max() > 0.9
     # dropped 1/(4 pi)
     assert l1_err(L * 4 * np.pi, Lii * 4 * np.pi) > 1.0
+
+
+def test_block_preconditioned_gmres_same_solution():
+    """Right preconditioning by the bubbles' own block inverses changes the
+    Krylov iterates but not the solution of L q = b (pinned to dense LU)."""
+    cl = wl.cluster(4, 2, 7.0, 0.5, 1.0, 0.5, seed=21, perturb=0.05)
+    phi = wl.smooth_phi(cl, 4)
+    q_lu, _ = oracle.solve(cl.xyz, cl.tri, phi, method="lu")
+    q_pl, i_pl = oracle.solve(cl.xyz, cl.tri, phi, tol=1e-13)
+    q_bj, i_bj = oracle.solve(cl.xyz, cl.tri, phi, method="gmres_bj", tol=1e-13, vtx_off=cl.vtx_off)
+    assert i_bj["converged"] and i_pl["converged"]
+    assert np.linalg.norm(q_bj - q_lu) / np.linalg.norm(q_lu) < 1e-11
+    assert np.linalg.norm(q_pl - q_lu) / np.linalg.norm(q_lu) < 1e-11
+    assert i_bj["iterations"] < i_pl["iterations"] / 2
