@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BFM_ABI_VERSION 1
+#define BFM_ABI_VERSION 2
 
 enum {
     BFM_OK = 0,
@@ -60,6 +60,14 @@ enum {
     BFM_PRECOND_NONE = 0, /* unpreconditioned GMRES, as in the paper (Section 3.8) */
     BFM_PRECOND_SH = 1    /* per-bubble spherical-harmonic approximate inverse (needs
                              bfm_set_sphere_template), applied from the right */
+};
+
+/* Initial guess of bfm_solve / bfm_solve_dev (argument use_guess). */
+enum {
+    BFM_GUESS_ZERO = 0,    /* q = 0 */
+    BFM_GUESS_GIVEN = 1,   /* q as passed in (e.g. the previous time step's, Section 3.6) */
+    BFM_GUESS_LEARNED = 2  /* predicted by the trained network of bfm_mlp.h from the current
+                              surface and phi; needs bfm_set_sphere_template */
 };
 
 /* Arithmetic of the fast multipole product. */
@@ -95,6 +103,7 @@ typedef struct bfm_solve_info {
     double t_tree_ms;    /* geometry + octree build */
     double t_diag_ms;    /* singular diagonals + right-hand side pass */
     double t_solve_ms;   /* GMRES */
+    double t_guess_ms;   /* learned initial guess (BFM_GUESS_LEARNED), else 0 */
 } bfm_solve_info;
 
 typedef struct bfm_ctx bfm_ctx;
@@ -177,7 +186,8 @@ int bfm_matvec(bfm_ctx *ctx, double f, const double *x, double g, const double *
  * Solve L q = b for q = dphi/dn (eq3_2): geometry, octree, diagonals and
  * right-hand side, then restarted GMRES from the initial guess.
  *   phi  host [nv] (bfm_solve) or device FP64 [nv] (bfm_solve_dev)
- *   q    in: initial guess if use_guess != 0, else ignored (zero guess);
+ *   q    in: the initial guess if use_guess == BFM_GUESS_GIVEN, else ignored
+ *        (BFM_GUESS_ZERO: zero; BFM_GUESS_LEARNED: the network's prediction);
  *        out: the solution. Host [nv] or device [nv] respectively.
  *   info may be NULL.
  * Returns BFM_ENOCONV (q = last iterate, info filled) when gmres_maxit is

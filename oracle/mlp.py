@@ -10,6 +10,12 @@ checked against: a fully connected network
 
 the mean-squared loss over a batch, its gradients by the chain rule, and one
 Adam step (Kingma and Ba 2015, bias-corrected moments).
+
+``rnd`` (optional, default the identity) is applied to both operands of
+every matrix product, forward and backward; passing a BF16 rounding gives
+the arithmetic of kernels that store those operands in BF16 and accumulate
+in higher precision. Biases, pre-activations and the bias gradients are
+never rounded.
 """
 from __future__ import annotations
 
@@ -34,12 +40,17 @@ def init(sizes, seed=0):
     return params
 
 
-def forward(params, x):
+def _ident(a):
+    return a
+
+
+def forward(params, x, rnd=None):
     """Returns (y, cache) where cache holds the pre-activations."""
+    rnd = rnd or _ident
     h = np.asarray(x, dtype=np.float64)
     cache = [h]
     for k, (W, b) in enumerate(params):
-        z = h @ W + b
+        z = rnd(h) @ rnd(W) + b
         if k < len(params) - 1:
             cache.append(z)
             h = silu(z)
@@ -48,15 +59,16 @@ def forward(params, x):
     return h, cache
 
 
-def loss(params, x, t):
+def loss(params, x, t, rnd=None):
     """0.5 * mean over the batch of ||y - t||^2."""
-    y, _ = forward(params, x)
+    y, _ = forward(params, x, rnd)
     return 0.5 * np.sum((y - t) ** 2) / x.shape[0]
 
 
-def backward(params, x, t):
+def backward(params, x, t, rnd=None):
     """Gradients of `loss` with respect to every W_k, b_k (chain rule)."""
-    y, cache = forward(params, x)
+    rnd = rnd or _ident
+    y, cache = forward(params, x, rnd)
     B = x.shape[0]
     g = (y - t) / B  # dL/dy
     grads = [None] * len(params)
@@ -64,9 +76,9 @@ def backward(params, x, t):
     for k in range(len(params) - 1, -1, -1):
         W, _ = params[k]
         h_in = hs[k]
-        grads[k] = (h_in.T @ g, g.sum(axis=0))
+        grads[k] = (rnd(h_in).T @ rnd(g), g.sum(axis=0))
         if k > 0:
-            g = (g @ W.T) * silu_grad(cache[k])
+            g = (rnd(g) @ rnd(W).T) * silu_grad(cache[k])
     return grads
 
 

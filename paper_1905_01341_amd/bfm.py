@@ -20,7 +20,14 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 PRECOND_NONE = 0
 PRECOND_SH = 1
-ABI_VERSION = 1
+GUESS_ZERO = 0
+GUESS_GIVEN = 1
+GUESS_LEARNED = 2
+ABI_VERSION = 2
+MLP_INPUTS = 174
+MLP_OUTPUTS = 81
+MLP_NUM_PARAMS = 656465
+MLP_NORM_SIZE = 510
 
 
 class BfmError(RuntimeError):
@@ -57,6 +64,7 @@ class SolveInfo(ctypes.Structure):
         ("t_tree_ms", ctypes.c_double),
         ("t_diag_ms", ctypes.c_double),
         ("t_solve_ms", ctypes.c_double),
+        ("t_guess_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -75,6 +83,14 @@ def load(path: str = LIB_PATH):
         raise FileNotFoundError(
             f"{path} is missing: build it with paper_1905_01341_amd.build.build() "
             "(there is no fallback implementation)")
+    # torch ships its own copy of the HIP runtime under the same soname. If
+    # torch is installed, load it first so that libbfm binds to that copy:
+    # one runtime per process, and device pointers of torch tensors are valid
+    # in the library (a second runtime started later finds no GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     I = ctypes.c_int
@@ -99,6 +115,20 @@ def load(path: str = LIB_PATH):
         "bfm_debug_operator": ([I, I, I, P, P], I),
         "bfm_profile": ([P, I], I),
         "bfm_profile_read": ([P, P, P, P], I),
+        "bfm_mlp_init": ([P, ctypes.c_uint64], I),
+        "bfm_mlp_set_params": ([P, P], I),
+        "bfm_mlp_get_params": ([P, P], I),
+        "bfm_mlp_set_norm": ([P, P], I),
+        "bfm_mlp_get_norm": ([P, P], I),
+        "bfm_mlp_forward": ([P, I64, P, P], I),
+        "bfm_mlp_gradient": ([P, I64, P, P, P, ctypes.POINTER(D)], I),
+        "bfm_mlp_adam_step": ([P, ctypes.c_float], I),
+        "bfm_mlp_features": ([P, P, P, P, P], I),
+        "bfm_mlp_collect_dev": ([P, P, P], I),
+        "bfm_mlp_dataset": ([P, I, ctypes.POINTER(I64)], I),
+        "bfm_mlp_fit": ([P, I, I, ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(D)], I),
+        "bfm_mlp_guess_dev": ([P, P, P], I),
+        "bfm_mlp_guess": ([P, P, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -147,6 +177,7 @@ class Solver:
         _check(self.lib.bfm_create(ctypes.byref(self.opt), ctypes.byref(h)))
         self.h = h
         self.nv = 0
+        self.nb = 0
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -176,6 +207,7 @@ class Solver:
         _check(self.lib.bfm_set_mesh(self.h, xyz.shape[0], _ptr(xyz), tri.shape[0], _ptr(tri), nb,
                                      _ptr(vo), _ptr(to)))
         self.nv = xyz.shape[0]
+        self.nb = max(nb, 1)
 
     def set_cluster(self, cl, template=True):
         self.set_mesh(cl.xyz, cl.tri, cl.vtx_off, cl.tri_off)
@@ -211,18 +243,21 @@ class Solver:
                                    int(add_diag), int(precision), int(direct)))
         return out
 
-    def solve(self, phi, q0=None, check=True):
-        """Host arrays in, (q, info dict) out."""
+    def solve(self, phi, q0=None, check=True, learned=False):
+        """Host arrays in, (q, info dict) out. The initial guess is q0 if
+        given, the trained network's prediction if learned, else zero."""
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         q = np.zeros(self.nv) if q0 is None else np.array(q0, dtype=np.float64)
+        guess = GUESS_LEARNED if learned else (GUESS_GIVEN if q0 is not None else GUESS_ZERO)
         info = SolveInfo()
-        rc = self.lib.bfm_solve(self.h, _ptr(phi), _ptr(q), int(q0 is not None), ctypes.byref(info))
+        rc = self.lib.bfm_solve(self.h, _ptr(phi), _ptr(q), guess, ctypes.byref(info))
         if check or rc not in (BFM_OK, -4):
             _check(rc)
         return q, info.as_dict()
 
     def solve_dev(self, phi_t, q_t, use_guess=False):
-        """torch float64 device tensors (contiguous); q_t is overwritten."""
+        """torch float64 device tensors (contiguous); q_t is overwritten.
+        use_guess: False/True (zero or q_t as given) or one of GUESS_*."""
         import torch
         assert phi_t.dtype == torch.float64 and q_t.dtype == torch.float64
         assert phi_t.is_contiguous() and q_t.is_contiguous()
@@ -252,3 +287,80 @@ class Solver:
         _check(self.lib.bfm_tree_stats(self.h, st))
         keys = ["lmax", "leaves", "boxes", "near_pairs", "m2l_pairs", "tree_pairs", "max_leaf"]
         return {k: int(st[i]) for i, k in enumerate(keys)}
+
+    # -- learned initial guess (include/bfm_mlp.h) ---------------------------
+
+    def mlp_init(self, seed=0):
+        _check(self.lib.bfm_mlp_init(self.h, int(seed)))
+
+    def mlp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_NUM_PARAMS
+        _check(self.lib.bfm_mlp_set_params(self.h, _ptr(p)))
+
+    def mlp_get_params(self):
+        p = np.empty(MLP_NUM_PARAMS, dtype=np.float32)
+        _check(self.lib.bfm_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def mlp_set_norm(self, norm):
+        n = np.ascontiguousarray(norm, dtype=np.float32)
+        assert n.size == MLP_NORM_SIZE
+        _check(self.lib.bfm_mlp_set_norm(self.h, _ptr(n)))
+
+    def mlp_get_norm(self):
+        n = np.empty(MLP_NORM_SIZE, dtype=np.float32)
+        _check(self.lib.bfm_mlp_get_norm(self.h, _ptr(n)))
+        return n
+
+    def mlp_forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        assert x.ndim == 2 and x.shape[1] == MLP_INPUTS
+        y = np.empty((x.shape[0], MLP_OUTPUTS), dtype=np.float32)
+        _check(self.lib.bfm_mlp_forward(self.h, x.shape[0], _ptr(x), _ptr(y)))
+        return y
+
+    def mlp_gradient(self, x, t):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        assert x.shape[0] == t.shape[0] and x.shape[1] == MLP_INPUTS and t.shape[1] == MLP_OUTPUTS
+        g = np.empty(MLP_NUM_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(self.lib.bfm_mlp_gradient(self.h, x.shape[0], _ptr(x), _ptr(t), _ptr(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def mlp_adam_step(self, lr):
+        _check(self.lib.bfm_mlp_adam_step(self.h, float(lr)))
+
+    def mlp_features(self, phi, q=None):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        qq = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        nb = self.nb
+        feat = np.empty((nb, MLP_INPUTS), dtype=np.float32)
+        targ = None if q is None else np.empty((nb, MLP_OUTPUTS), dtype=np.float32)
+        _check(self.lib.bfm_mlp_features(self.h, _ptr(phi), _ptr(qq), _ptr(feat), _ptr(targ)))
+        return feat, targ
+
+    def mlp_collect_dev(self, phi_t, q_t):
+        _check(self.lib.bfm_mlp_collect_dev(self.h, ctypes.c_void_p(phi_t.data_ptr()),
+                                            ctypes.c_void_p(q_t.data_ptr())))
+
+    def mlp_dataset(self, clear=False):
+        n = ctypes.c_int64()
+        _check(self.lib.bfm_mlp_dataset(self.h, int(clear), ctypes.byref(n)))
+        return n.value
+
+    def mlp_fit(self, epochs, batch=256, lr=1e-3, seed=0):
+        loss = ctypes.c_double()
+        _check(self.lib.bfm_mlp_fit(self.h, int(epochs), int(batch), float(lr), int(seed), ctypes.byref(loss)))
+        return loss.value
+
+    def mlp_guess(self, phi):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        q = np.empty(self.nv)
+        _check(self.lib.bfm_mlp_guess(self.h, _ptr(phi), _ptr(q)))
+        return q
+
+    def mlp_guess_dev(self, phi_t, q_t):
+        _check(self.lib.bfm_mlp_guess_dev(self.h, ctypes.c_void_p(phi_t.data_ptr()),
+                                          ctypes.c_void_p(q_t.data_ptr())))

@@ -7,7 +7,9 @@
 #include <string>
 #include <vector>
 
+#include "../../include/bfm_mlp.h"
 #include "ctx.h"
+#include "learn.h"
 #include "ops.h"
 
 namespace bfm {
@@ -91,8 +93,9 @@ struct Timer {
     }
 };
 
-static void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, bool use_guess,
-                       bfm_solve_info *info) {
+static void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm_solve_info *info) {
+    BFM_CHECK(guess == BFM_GUESS_ZERO || guess == BFM_GUESS_GIVEN || guess == BFM_GUESS_LEARNED, BFM_EINVAL,
+              "use_guess must be BFM_GUESS_ZERO, BFM_GUESS_GIVEN or BFM_GUESS_LEARNED");
     bfm_solve_info loc{};
     const int64_t n = c->nv;
     {
@@ -100,6 +103,12 @@ static void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, bool us
         ensure_tree(c);
         loc.t_tree_ms = t.stop_ms();
     }
+    if (guess == BFM_GUESS_LEARNED) {
+        Timer t(c->stream);
+        mlp_guess(c, phi_dev, q_dev);
+        loc.t_guess_ms = t.stop_ms();
+    }
+    const bool use_guess = guess != BFM_GUESS_ZERO;
     {
         Timer t(c->stream);
         diagonal_pass(c, phi_dev);
@@ -175,6 +184,7 @@ int bfm_destroy(bfm_ctx *c) {
         if (!c) return;
         DeviceScope ds(c->device);
         (void)hipStreamSynchronize(c->stream);
+        mlp_free(c);
         if (c->host_small) (void)hipHostFree(c->host_small);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
@@ -243,6 +253,7 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
         for (int64_t k = 3 * to[0]; k < 3 * to[1]; ++k) c->tri0_h.push_back(tri[k] - (int)vo[0]);
         c->pre.nd = 0;
         c->pre.ready = false;
+        c->pre.basis.nmax = -1;
         c->vtx_off = vo;
         c->tri_off = to;
         c->xyz.ensure(3 * nv);
@@ -277,6 +288,7 @@ int bfm_set_sphere_template(bfm_ctx *c, int32_t nd, const double *dirs) {
         c->pre.tri_h = c->tri0_h;
         c->pre.nd = nd;
         c->pre.ready = false;
+        c->pre.basis.nmax = -1;  // rebuild harmonics for the new template
     });
 }
 
@@ -379,7 +391,7 @@ int bfm_solve_dev(bfm_ctx *c, const double *phi_dev, double *q_dev, int use_gues
         BFM_CHECK(c && phi_dev && q_dev, BFM_EINVAL, "null argument");
         BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
         DeviceScope ds(c->device);
-        solve_impl(c, phi_dev, q_dev, use_guess != 0, info);
+        solve_impl(c, phi_dev, q_dev, use_guess, info);
         BFM_HIP(hipStreamSynchronize(c->stream));
     });
 }
@@ -395,10 +407,10 @@ int bfm_solve(bfm_ctx *c, const double *phi, double *q, int use_guess, bfm_solve
         buf.ensure(2 * n);
         hipStream_t st = c->stream;
         BFM_HIP(hipMemcpyAsync(buf.get(), phi, sizeof(double) * n, hipMemcpyHostToDevice, st));
-        if (use_guess)
+        if (use_guess == BFM_GUESS_GIVEN)
             BFM_HIP(hipMemcpyAsync(buf.get() + n, q, sizeof(double) * n, hipMemcpyHostToDevice, st));
         try {
-            solve_impl(c, buf.get(), buf.get() + n, use_guess != 0, info);
+            solve_impl(c, buf.get(), buf.get() + n, use_guess, info);
         } catch (const Error &e) {
             if (e.code != BFM_ENOCONV) throw;
             g_last_error = e.msg;
@@ -457,6 +469,170 @@ int bfm_profile_read(bfm_ctx *c, double ms[8], int64_t launches[8], double flops
             launches[r.cls] += 1;
             flops[r.cls] += r.flops;
         }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Learned initial guess (include/bfm_mlp.h)
+
+int bfm_mlp_init(bfm_ctx *c, uint64_t seed) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        mlp_init(mlp_get(c), seed, c->stream);
+    });
+}
+
+int bfm_mlp_set_params(bfm_ctx *c, const float *params) {
+    return guarded([&] {
+        BFM_CHECK(c && params, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        mlp_set_params(mlp_get(c), params, c->stream);
+    });
+}
+
+int bfm_mlp_get_params(bfm_ctx *c, float *params) {
+    return guarded([&] {
+        BFM_CHECK(c && params, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        mlp_get_params(mlp_get(c), params, false, c->stream);
+    });
+}
+
+int bfm_mlp_set_norm(bfm_ctx *c, const float *norm) {
+    return guarded([&] {
+        BFM_CHECK(c && norm, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        mlp_set_norm(mlp_get(c), norm, c->stream);
+    });
+}
+
+int bfm_mlp_get_norm(bfm_ctx *c, float *norm) {
+    return guarded([&] {
+        BFM_CHECK(c && norm, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        mlp_get_norm(mlp_get(c), norm, c->stream);
+    });
+}
+
+int bfm_mlp_forward(bfm_ctx *c, int64_t rows, const float *x, float *y) {
+    return guarded([&] {
+        BFM_CHECK(c && x && y, BFM_EINVAL, "null argument");
+        BFM_CHECK(rows >= 1 && rows <= (1 << 24), BFM_EINVAL, "rows must be in [1, 2^24]");
+        DeviceScope ds(c->device);
+        hipStream_t st = c->stream;
+        DevBuf<float> dx, dy;
+        dx.ensure((size_t)rows * BFM_MLP_INPUTS);
+        dy.ensure((size_t)rows * BFM_MLP_OUTPUTS);
+        BFM_HIP(hipMemcpyAsync(dx.get(), x, sizeof(float) * rows * BFM_MLP_INPUTS, hipMemcpyHostToDevice, st));
+        mlp_forward_rows(mlp_get(c), rows, dx.get(), dy.get(), st);
+        BFM_HIP(hipMemcpyAsync(y, dy.get(), sizeof(float) * rows * BFM_MLP_OUTPUTS, hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
+    });
+}
+
+int bfm_mlp_gradient(bfm_ctx *c, int64_t rows, const float *x, const float *t, float *grad, double *loss) {
+    return guarded([&] {
+        BFM_CHECK(c && x && t, BFM_EINVAL, "null argument");
+        BFM_CHECK(rows >= 1 && rows <= (1 << 24), BFM_EINVAL, "rows must be in [1, 2^24]");
+        DeviceScope ds(c->device);
+        hipStream_t st = c->stream;
+        DevBuf<float> dx, dt;
+        dx.ensure((size_t)rows * BFM_MLP_INPUTS);
+        dt.ensure((size_t)rows * BFM_MLP_OUTPUTS);
+        BFM_HIP(hipMemcpyAsync(dx.get(), x, sizeof(float) * rows * BFM_MLP_INPUTS, hipMemcpyHostToDevice, st));
+        BFM_HIP(hipMemcpyAsync(dt.get(), t, sizeof(float) * rows * BFM_MLP_OUTPUTS, hipMemcpyHostToDevice, st));
+        Mlp &net = mlp_get(c);
+        const double l = mlp_gradient_rows(net, rows, dx.get(), dt.get(), st);
+        if (grad) mlp_get_params(net, grad, true, st);
+        if (loss) *loss = l;
+    });
+}
+
+int bfm_mlp_adam_step(bfm_ctx *c, float lr) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        BFM_CHECK(lr > 0.f, BFM_EINVAL, "lr must be positive");
+        DeviceScope ds(c->device);
+        mlp_adam(mlp_get(c), lr, c->stream);
+        BFM_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int bfm_mlp_features(bfm_ctx *c, const double *phi, const double *q, float *feat, float *targ) {
+    return guarded([&] {
+        BFM_CHECK(c && phi && feat, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        hipStream_t st = c->stream;
+        const int64_t n = c->nv, nb = c->nb;
+        const bool with_t = q && targ;
+        DevBuf<double> dv;
+        DevBuf<float> df;
+        dv.ensure(2 * n);
+        df.ensure((size_t)nb * (BFM_MLP_INPUTS + BFM_MLP_OUTPUTS));
+        BFM_HIP(hipMemcpyAsync(dv.get(), phi, sizeof(double) * n, hipMemcpyHostToDevice, st));
+        if (with_t) BFM_HIP(hipMemcpyAsync(dv.get() + n, q, sizeof(double) * n, hipMemcpyHostToDevice, st));
+        float *ft = df.get() + nb * BFM_MLP_INPUTS;
+        mlp_features(c, dv.get(), with_t ? dv.get() + n : nullptr, df.get(), with_t ? ft : nullptr);
+        BFM_HIP(hipMemcpyAsync(feat, df.get(), sizeof(float) * nb * BFM_MLP_INPUTS, hipMemcpyDeviceToHost, st));
+        if (with_t)
+            BFM_HIP(hipMemcpyAsync(targ, ft, sizeof(float) * nb * BFM_MLP_OUTPUTS, hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
+    });
+}
+
+int bfm_mlp_collect_dev(bfm_ctx *c, const double *phi_dev, const double *q_dev) {
+    return guarded([&] {
+        BFM_CHECK(c && phi_dev && q_dev, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        mlp_collect(c, phi_dev, q_dev);
+    });
+}
+
+int bfm_mlp_dataset(bfm_ctx *c, int clear, int64_t *rows) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        Mlp &net = mlp_get(c);
+        if (clear) net.ds_rows = 0;
+        if (rows) *rows = net.ds_rows;
+    });
+}
+
+int bfm_mlp_fit(bfm_ctx *c, int epochs, int batch, float lr, uint64_t seed, double *loss) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        const double l = mlp_fit(c, epochs, batch, lr, seed);
+        if (loss) *loss = l;
+    });
+}
+
+int bfm_mlp_guess_dev(bfm_ctx *c, const double *phi_dev, double *q_dev) {
+    return guarded([&] {
+        BFM_CHECK(c && phi_dev && q_dev, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        mlp_guess(c, phi_dev, q_dev);
+        BFM_HIP(hipStreamSynchronize(c->stream));
+    });
+}
+
+int bfm_mlp_guess(bfm_ctx *c, const double *phi, double *q) {
+    return guarded([&] {
+        BFM_CHECK(c && phi && q, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        DeviceScope ds(c->device);
+        hipStream_t st = c->stream;
+        const int64_t n = c->nv;
+        DevBuf<double> dv;
+        dv.ensure(2 * n);
+        BFM_HIP(hipMemcpyAsync(dv.get(), phi, sizeof(double) * n, hipMemcpyHostToDevice, st));
+        mlp_guess(c, dv.get(), dv.get() + n);
+        BFM_HIP(hipMemcpyAsync(q, dv.get() + n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
     });
 }
 

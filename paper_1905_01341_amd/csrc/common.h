@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/bfm.h"
@@ -65,6 +66,10 @@ struct DevBuf {
         return ptr;
     }
     T *get() const { return ptr; }
+    void swap(DevBuf &o) {
+        std::swap(ptr, o.ptr);
+        std::swap(cap, o.cap);
+    }
 };
 
 // ---------------------------------------------------------------------------

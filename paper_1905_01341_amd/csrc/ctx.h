@@ -9,14 +9,23 @@
 #include "tree.h"
 
 namespace bfm {
+// Real spherical harmonics of degree <= nmax sampled at the template
+// vertices (G, column-major [nd x nc]) and their weighted least-squares
+// projector (Gp, column-major [nc x nd]).
+struct ShBasis {
+    int nmax = -1, nc = 0, nd = 0;
+    DevBuf<double> G, Gp;
+};
 struct Precond {
     int nd = 0, nc = 0, nmax = -1;
     double cc = 0.0;
     bool ready = false;
     std::vector<double> dirs_h;  // template directions [nd][3]
     std::vector<int> tri_h;      // template triangles (first bubble, local indices)
-    DevBuf<double> G, Gp, fac, R, X, C, Y;
+    ShBasis basis;
+    DevBuf<double> fac, R, X, C, Y;
 };
+struct Mlp;  // learned initial guess (learn.hip)
 }  // namespace bfm
 
 struct bfm_ctx {
@@ -54,6 +63,8 @@ struct bfm_ctx {
     bfm::Precond pre;
     std::vector<int> tri0_h;  // first bubble's triangles (local indices), kept for templates
 
+    bfm::Mlp *mlp = nullptr;  // learned initial guess, created on first use
+
     // GMRES workspace (sorted order)
     bfm::DevBuf<double> V, work, x_s, part, small, zbuf, tbuf;
     double *host_small = nullptr;       // pinned
@@ -78,9 +89,13 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
 void gmres_sorted(bfm_ctx *c, double *x_s, bool use_guess, bfm_solve_info *info);
 
 // Spherical-harmonic preconditioner (precond.hip)
+void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st);
 void precond_build(bfm_ctx *c);
 void precond_radii(bfm_ctx *c);
 void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);
+// C = A B, column-major FP64 (precond.hip)
+void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                 hipStream_t st);
 
 // gather (original -> sorted) and scatter (sorted -> original)
 void to_sorted(bfm_ctx *c, const double *in_orig, double *out_s);

@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
                                                           double *out) {
     static_assert(PP % ROWS == 0 && ROWS % 16 == 0, "row slab");
     constexpr int NSLAB = PP / ROWS;
-    __shared__ double As[kTKC * ROWS];  // [k][row within slab]
+    __shared__ double As[2][kTKC * ROWS];  // two buffers of [k][row within slab]
     const int g = blockIdx.x / NSLAB, slab = blockIdx.x % NSLAB;
     if (g >= ntiles) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -284,20 +284,49 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     dbl4 acc[ROWS / 16];
 #pragma unroll
     for (int rb = 0; rb < ROWS / 16; ++rb) acc[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < PP; k0 += kTKC) {
-        __syncthreads();
-        for (int e = tid; e < kTKC * ROWS; e += 64 * WAVES) {
-            const int kk = e / ROWS, rr = e % ROWS;
-            As[e] = Top[(int64_t)(k0 + kk) * PP + rr];
+    // double-buffered operator slab: the next chunk is fetched into
+    // registers while the current one feeds the MFMAs from LDS
+    constexpr int NT = 64 * WAVES;
+    constexpr int PER = (kTKC * ROWS + NT - 1) / NT;
+    double pre[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * NT;
+            if (e < kTKC * ROWS) {
+                const int kk = e / ROWS, rr = e % ROWS;
+                pre[u] = Top[(int64_t)(k0 + kk) * PP + rr];
+            }
         }
-        __syncthreads();
+    };
+    auto stash = [&](double *dst) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + u * NT;
+            if (e < kTKC * ROWS) dst[e] = pre[u];
+        }
+    };
+    fetch(0);
+    stash(As[0]);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < PP; k0 += kTKC) {
+        const bool more = k0 + kTKC < PP;
+        if (more) fetch(k0 + kTKC);
+        double bv[kTKC / 4];
+#pragma unroll
+        for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bok ? bcol[k0 + 4 * kk + kq] : 0.0;
 #pragma unroll
         for (int kk = 0; kk < kTKC / 4; ++kk) {
-            const double b = bok ? bcol[k0 + 4 * kk + kq] : 0.0;
-            const double *Ak = As + (4 * kk + kq) * ROWS + rl;
+            const double *Ak = As[cur] + (4 * kk + kq) * ROWS + rl;
 #pragma unroll
             for (int rb = 0; rb < ROWS / 16; ++rb)
-                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, Ak[rb * 16], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[kk], Ak[rb * 16], acc[rb], 0, 0, 0);
+        }
+        if (more) {
+            stash(As[cur ^ 1]);
+            __syncthreads();
+            cur ^= 1;
         }
     }
 #pragma unroll
@@ -545,6 +574,8 @@ static void prof_end(FmmWork &w, int idx, hipStream_t st, double flops) {
 
 // Middle row-slab height: a multiple of 16 dividing p^2, at most 80.
 constexpr int mid_rows(int PP) { return PP == 144 ? 48 : (PP == 400 ? 80 : (PP >= 64 ? 64 : PP)); }
+// Wide-tile slab: every row while the accumulators fit in registers.
+constexpr int wide_rows(int PP) { return PP <= 256 ? PP : mid_rows(PP); }
 
 template <int P_>
 static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, const double *T,
@@ -564,9 +595,10 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
     const int *to = tl.tile_for(nch, width);
     const int sw = swap ? 1 : 0;
     if (shape == 0) {
-        auto kern = (cls == KC_M2L) ? k_translate<PP, PP, 8, 0> : k_translate<PP, PP, 8, 1>;
-        kern<<<(unsigned)nt, 512, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(), tl.dst.get(), nch,
-                                           sw, T, in, out);
+        constexpr int R = wide_rows(PP);
+        auto kern = (cls == KC_M2L) ? k_translate<PP, R, 8, 0> : k_translate<PP, R, 8, 1>;
+        kern<<<(unsigned)(nt * (PP / R)), 512, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(),
+                                                         tl.dst.get(), nch, sw, T, in, out);
     } else if (shape == 1) {
         constexpr int R = mid_rows(PP);
         auto kern = (cls == KC_M2L) ? k_translate<PP, R, 4, 0> : k_translate<PP, R, 4, 1>;

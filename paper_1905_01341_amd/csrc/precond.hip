@@ -23,9 +23,11 @@ namespace bfm {
 
 static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// Real harmonics of degree 0..nmax at unit vector d: for each degree n the
-// order-0 value, then real and imaginary parts of orders 1..n (any
-// normalisation serves: the projector is formed from G itself).
+// Real harmonics of degree 0..nmax at unit vector d, orthonormal on the
+// unit sphere and without the Condon-Shortley phase: for each degree n the
+// order-0 value, then the cos(m lon) and sin(m lon) parts of orders 1..n.
+// The recurrence yields sqrt((n-m)!/(n+m)!) P_n^m(cos theta) e^{i m lon};
+// the factor sqrt((2n+1)/4pi) (times sqrt(2) for m > 0) normalises it.
 static void sh_row(int nmax, const double d[3], double *row) {
     using cplx = std::complex<double>;
     const double x = d[0], y = d[1], z = d[2];
@@ -43,11 +45,13 @@ static void sh_row(int nmax, const double d[3], double *row) {
                 pr = cr;
                 cr = nr;
             }
+            const double f = std::sqrt((2.0 * n + 1.0) / (4.0 * 3.14159265358979323846)) *
+                             (m > 0 ? std::sqrt(2.0) : 1.0);
             if (m == 0) {
-                row[n * n] = cr.real();
+                row[n * n] = f * cr.real();
             } else {
-                row[n * n + 2 * m - 1] = cr.real();
-                row[n * n + 2 * m] = cr.imag();
+                row[n * n + 2 * m - 1] = f * cr.real();
+                row[n * n + 2 * m] = f * cr.imag();
             }
         }
     }
@@ -81,14 +85,12 @@ static void cholesky_solve(int n, std::vector<double> &S, std::vector<double> &B
     }
 }
 
-void precond_build(bfm_ctx *c) {
-    Precond &P = c->pre;
-    BFM_CHECK(P.nd > 0 && !P.dirs_h.empty(), BFM_EINVAL, "no sphere template set");
+void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st) {
     const int nd = P.nd;
-    const int nmax = c->opt.precond_degree;
+    BFM_CHECK(nd > 0 && !P.dirs_h.empty(), BFM_EINVAL, "no sphere template set");
     BFM_CHECK(nmax >= 1 && (nmax + 1) * (nmax + 1) <= nd, BFM_EINVAL,
-              "precond_degree must satisfy (degree + 1)^2 <= vertices per bubble");
-    if (P.ready && P.nmax == nmax) return;
+              "harmonic degree must satisfy (degree + 1)^2 <= vertices per bubble");
+    if (B.nmax == nmax && B.nd == nd) return;
     const int nc = (nmax + 1) * (nmax + 1);
     // template vertex areas from the first bubble's triangles on the unit directions
     std::vector<double> wv(nd, 0.0);
@@ -104,34 +106,45 @@ void precond_build(bfm_ctx *c) {
     }
     std::vector<double> G((size_t)nd * nc);  // row-major [nd][nc]
     for (int v = 0; v < nd; ++v) sh_row(nmax, &P.dirs_h[3 * v], &G[(size_t)v * nc]);
-    // S = G^T W G ; B = G^T W  -> G+ = S^{-1} B  ([nc][nd])
-    std::vector<double> S((size_t)nc * nc, 0.0), B((size_t)nc * nd, 0.0);
+    // S = G^T W G ; R = G^T W  -> G+ = S^{-1} R  ([nc][nd])
+    std::vector<double> S((size_t)nc * nc, 0.0), R((size_t)nc * nd, 0.0);
     for (int i = 0; i < nc; ++i)
-        for (int v = 0; v < nd; ++v) B[(size_t)i * nd + v] = G[(size_t)v * nc + i] * wv[v];
+        for (int v = 0; v < nd; ++v) R[(size_t)i * nd + v] = G[(size_t)v * nc + i] * wv[v];
     for (int i = 0; i < nc; ++i)
         for (int j = 0; j <= i; ++j) {
             double s = 0.0;
-            for (int v = 0; v < nd; ++v) s += B[(size_t)i * nd + v] * G[(size_t)v * nc + j];
+            for (int v = 0; v < nd; ++v) s += R[(size_t)i * nd + v] * G[(size_t)v * nc + j];
             S[(size_t)i * nc + j] = S[(size_t)j * nc + i] = s;
         }
-    cholesky_solve(nc, S, B, nd);
+    cholesky_solve(nc, S, R, nd);
     // device layouts (column-major): G [nd x nc], Gp [nc x nd]
     std::vector<double> Gc((size_t)nd * nc), Gpc((size_t)nc * nd);
     for (int v = 0; v < nd; ++v)
         for (int i = 0; i < nc; ++i) {
             Gc[(size_t)i * nd + v] = G[(size_t)v * nc + i];
-            Gpc[(size_t)v * nc + i] = B[(size_t)i * nd + v];
+            Gpc[(size_t)v * nc + i] = R[(size_t)i * nd + v];
         }
+    B.G.ensure(Gc.size());
+    B.Gp.ensure(Gpc.size());
+    BFM_HIP(hipMemcpyAsync(B.G.get(), Gc.data(), sizeof(double) * Gc.size(), hipMemcpyHostToDevice, st));
+    BFM_HIP(hipMemcpyAsync(B.Gp.get(), Gpc.data(), sizeof(double) * Gpc.size(), hipMemcpyHostToDevice, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    B.nmax = nmax;
+    B.nc = nc;
+    B.nd = nd;
+}
+
+void precond_build(bfm_ctx *c) {
+    Precond &P = c->pre;
+    const int nmax = c->opt.precond_degree;
+    if (P.ready && P.nmax == nmax) return;
+    sh_basis_build(P, nmax, P.basis, c->stream);
+    const int nc = P.basis.nc;
     std::vector<double> fac(nc);
     const double cc = 2.0 * (nmax + 1) + 1.0;
     for (int n = 0; n <= nmax; ++n)
         for (int i = n * n; i < (n + 1) * (n + 1); ++i) fac[i] = (2.0 * n + 1.0) - cc;
-    P.G.ensure(Gc.size());
-    P.Gp.ensure(Gpc.size());
     P.fac.ensure(nc);
-    BFM_HIP(hipMemcpyAsync(P.G.get(), Gc.data(), sizeof(double) * Gc.size(), hipMemcpyHostToDevice, c->stream));
-    BFM_HIP(hipMemcpyAsync(P.Gp.get(), Gpc.data(), sizeof(double) * Gpc.size(), hipMemcpyHostToDevice,
-                           c->stream));
     BFM_HIP(hipMemcpyAsync(P.fac.get(), fac.data(), sizeof(double) * nc, hipMemcpyHostToDevice, c->stream));
     BFM_HIP(hipStreamSynchronize(c->stream));
     P.nmax = nmax;
@@ -206,6 +219,14 @@ __global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, const doub
         }
 }
 
+// C = A B, all column-major (the plain product of k_gemm_nn)
+void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                 hipStream_t st) {
+    dim3 g((M + 63) / 64, (N + 63) / 64);
+    k_gemm_nn<<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, nullptr, 0.0, nullptr, 0);
+    BFM_LAUNCHED();
+}
+
 // out_s[i] = Y[perm[i]] / R[bubble of perm[i]]  (sorted order)
 __global__ void k_precond_out(const double *Y, const int *perm, int64_t n, int nd, const double *R,
                               double *out) {
@@ -232,10 +253,10 @@ void precond_apply(bfm_ctx *c, const double *in_s, double *out_s) {
     to_original(c, in_s, X);
     dim3 g1((nc + 63) / 64, (nb + 63) / 64), g2((nd + 63) / 64, (nb + 63) / 64);
     // C = diag(2n+1 - c) G+ X
-    k_gemm_nn<<<g1, 256, 0, st>>>(nc, nb, nd, P.Gp.get(), nc, X, nd, Cm, nc, P.fac.get(), 0.0, nullptr, 0);
+    k_gemm_nn<<<g1, 256, 0, st>>>(nc, nb, nd, P.basis.Gp.get(), nc, X, nd, Cm, nc, P.fac.get(), 0.0, nullptr, 0);
     BFM_LAUNCHED();
     // Y = G C + c X
-    k_gemm_nn<<<g2, 256, 0, st>>>(nd, nb, nc, P.G.get(), nd, Cm, nc, Y, nd, nullptr, P.cc, X, nd);
+    k_gemm_nn<<<g2, 256, 0, st>>>(nd, nb, nc, P.basis.G.get(), nd, Cm, nc, Y, nd, nullptr, P.cc, X, nd);
     BFM_LAUNCHED();
     k_precond_out<<<nblk(c->nv, 256), 256, 0, st>>>(Y, c->tree.idx_a.get(), c->nv, nd, P.R.get(), out_s);
     BFM_LAUNCHED();

@@ -147,7 +147,8 @@ def test_warm_start_and_tetrahedron_edge_cases():
     assert np.all(np.einsum("ij,ij->i", cr, v[f].mean(1)) > 0)
     phi = np.array([1.0, 0.5, -0.25, 2.0])
     q_ref, _ = oracle.solve(v, f, phi, method="lu")
-    sv = _solver(wl.Cluster(v, f, np.array([0, 4]), np.array([0, 4]), np.zeros((1, 3)), np.ones(1), v),
+    dirs = v / np.linalg.norm(v, axis=1, keepdims=True)
+    sv = _solver(wl.Cluster(v, f, np.array([0, 4]), np.array([0, 4]), np.zeros((1, 3)), np.ones(1), dirs),
                  p=16, gmres_tol=1e-13)
     q, info = sv.solve(phi)
     assert rel(q, q_ref) < 1e-6, rel(q, q_ref)
