@@ -58,8 +58,11 @@ enum {
 /* Preconditioner of the GMRES iteration. */
 enum {
     BFM_PRECOND_NONE = 0, /* unpreconditioned GMRES, as in the paper (Section 3.8) */
-    BFM_PRECOND_SH = 1    /* per-bubble spherical-harmonic approximate inverse (needs
+    BFM_PRECOND_SH = 1,   /* per-bubble spherical-harmonic approximate inverse (needs
                              bfm_set_sphere_template), applied from the right */
+    BFM_PRECOND_SH_COARSE = 2 /* two-level: BFM_PRECOND_SH followed by a coarse correction in
+                                 the space of per-bubble constants (one unknown per bubble,
+                                 interactions between bubbles as point monopoles) */
 };
 
 /* Initial guess of bfm_solve / bfm_solve_dev (argument use_guess). */

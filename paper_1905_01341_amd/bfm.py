@@ -20,6 +20,7 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 PRECOND_NONE = 0
 PRECOND_SH = 1
+PRECOND_SH_COARSE = 2
 GUESS_ZERO = 0
 GUESS_GIVEN = 1
 GUESS_LEARNED = 2

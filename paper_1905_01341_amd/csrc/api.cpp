@@ -49,7 +49,8 @@ static void check_options(const bfm_options &o) {
     BFM_CHECK(o.gmres_restart >= 1 && o.gmres_restart <= 128, BFM_EINVAL,
               "gmres_restart must be in [1, 128]");
     BFM_CHECK(o.gmres_maxit >= 1, BFM_EINVAL, "gmres_maxit must be >= 1");
-    BFM_CHECK(o.precond == BFM_PRECOND_NONE || o.precond == BFM_PRECOND_SH, BFM_EINVAL, "unknown precond");
+    BFM_CHECK(o.precond == BFM_PRECOND_NONE || o.precond == BFM_PRECOND_SH || o.precond == BFM_PRECOND_SH_COARSE,
+              BFM_EINVAL, "unknown precond");
     BFM_CHECK(o.precond_degree >= 1 && o.precond_degree <= 40, BFM_EINVAL, "precond_degree must be in [1, 40]");
 }
 

@@ -24,6 +24,11 @@ struct Precond {
     std::vector<int> tri_h;      // template triangles (first bubble, local indices)
     ShBasis basis;
     DevBuf<double> fac, R, X, C, Y;
+    // coarse space of per-bubble constants (two-level form)
+    DevBuf<double> U;                  // own-bubble column sums of s^T L, caller order [nv]
+    DevBuf<double> ccen, carea;        // area-weighted centroids [nb][3], areas [nb]
+    DevBuf<double> Ainv, gj_row, gj_col, gj_piv;  // inverse coarse matrix [nb x nb] and Gauss-Jordan work
+    DevBuf<double> csum, cy;           // per-bubble sums [3][nb], coarse correction [nb]
 };
 struct Mlp;  // learned initial guess (learn.hip)
 }  // namespace bfm
@@ -93,6 +98,8 @@ void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st);
 void precond_build(bfm_ctx *c);
 void precond_radii(bfm_ctx *c);
 void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);
+// coarse correction of the two-level form (needs the diagonals of the current mesh)
+void coarse_build(bfm_ctx *c);
 // C = A B, column-major FP64 (precond.hip)
 void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                  hipStream_t st);

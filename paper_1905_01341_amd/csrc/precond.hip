@@ -227,13 +227,209 @@ void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B,
     BFM_LAUNCHED();
 }
 
-// out_s[i] = Y[perm[i]] / R[bubble of perm[i]]  (sorted order)
+// out_s[i] = Y[perm[i]] / R[b] (+ cy[b]), b the bubble of perm[i]  (sorted order)
 __global__ void k_precond_out(const double *Y, const int *perm, int64_t n, int nd, const double *R,
-                              double *out) {
+                              const double *cy, double *out) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int o = perm[i];
-    out[i] = Y[o] / R[o / nd];
+    const int b = o / nd;
+    out[i] = Y[o] / R[b] + (cy ? cy[b] : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse correction (two-level form). With Z the per-bubble indicator
+// vectors and S = diag(s), the coarse matrix A_c = (S Z)^T L Z couples the
+// bubbles' mean values: A_c[a][a] = sum_{i, j in a} s_i L_ij (exact, from
+// the bubble's own pairs and the singular diagonal), A_c[a][b] =
+// area_a area_b / (4 pi |c_a - c_b|) for a != b (each bubble seen from the
+// other as a point monopole at its area centroid). After the block step
+// x = P_b^{-1} v the correction adds Z A_c^{-1} (S Z)^T (v - L x), with the
+// residual's bubble sums formed from the same model of L:
+//   (S Z)^T L x |_a = U_a . x_a + area_a sum_{b != a} m_b / (4 pi |c_a - c_b|),
+//   U_a = s_a^T L_aa (per vertex), m_b = sum_{j in b} s_j x_j.
+
+// area and area-weighted centroid of every bubble
+__global__ void k_coarse_geom(const double *xyz, const double *s, int nd, double *cen, double *area) {
+    __shared__ double red[4][256];
+    const int b = blockIdx.x;
+    double a[4] = {0, 0, 0, 0};
+    for (int v = threadIdx.x; v < nd; v += 256) {
+        const int64_t o = (int64_t)b * nd + v;
+        const double w = s[o];
+        a[0] += w * xyz[3 * o];
+        a[1] += w * xyz[3 * o + 1];
+        a[2] += w * xyz[3 * o + 2];
+        a[3] += w;
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) cen[3 * b + k] = red[k][0] / red[3][0];
+        area[b] = red[3][0];
+    }
+}
+
+// U_j = s_j (sum_{i in a, i != j} s_i / (4 pi r_ij) + L_jj) for vertex j of
+// bubble a (caller order). Grid (vertex blocks, bubbles); the bubble's
+// points pass through LDS in chunks.
+__global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const double *s, const double *lii, int nd,
+                                                  double *U) {
+    constexpr int CH = 512;
+    __shared__ double sx[CH], sy[CH], sz[CH], ss[CH];
+    const int b = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int64_t base = (int64_t)b * nd;
+    const bool ok = j < nd;
+    const double xj = ok ? xyz[3 * (base + j)] : 0.0, yj = ok ? xyz[3 * (base + j) + 1] : 0.0,
+                 zj = ok ? xyz[3 * (base + j) + 2] : 0.0;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < nd; c0 += CH) {
+        const int cn = min(CH, nd - c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn; t += 256) {
+            const int64_t o = base + c0 + t;
+            sx[t] = xyz[3 * o];
+            sy[t] = xyz[3 * o + 1];
+            sz[t] = xyz[3 * o + 2];
+            ss[t] = s[o];
+        }
+        __syncthreads();
+        if (ok)
+            for (int t = 0; t < cn; ++t) {
+                if (c0 + t == j) continue;
+                const double dx = xj - sx[t], dy = yj - sy[t], dz = zj - sz[t];
+                acc += ss[t] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+    }
+    if (ok) U[base + j] = s[base + j] * (acc * (1.0 / (4.0 * 3.14159265358979323846)) + lii[base + j]);
+}
+
+// A (column-major nb x nb): off-diagonal point-monopole couplings; the
+// diagonal from the bubble sums of U.
+__global__ void k_coarse_matrix(const double *cen, const double *area, const double *U, int nd, int nb,
+                                double *A) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nb * nb) return;
+    const int a = (int)(e % nb), b = (int)(e / nb);
+    if (a != b) {
+        const double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1],
+                     dz = cen[3 * a + 2] - cen[3 * b + 2];
+        A[e] = area[a] * area[b] / (4.0 * 3.14159265358979323846 * sqrt(dx * dx + dy * dy + dz * dz));
+        return;
+    }
+    double t = 0.0;
+    for (int v = 0; v < nd; ++v) t += U[(int64_t)a * nd + v];
+    A[e] = t;
+}
+
+// Gauss-Jordan inverse (no pivoting: the coarse matrix is symmetric positive
+// definite) of the bs x bs diagonal block at (k0, k0) of A (column-major,
+// leading dimension n); writes -inverse to P (column-major bs x bs).
+constexpr int kGjBlock = 64;
+__global__ void __launch_bounds__(256) k_gj_block(const double *A, int n, int k0, int bs, double *P) {
+    __shared__ double T[kGjBlock][kGjBlock + 1];
+    for (int e = threadIdx.x; e < bs * bs; e += 256) {
+        const int r = e % bs, c = e / bs;
+        T[r][c] = A[(int64_t)(k0 + c) * n + k0 + r];
+    }
+    for (int k = 0; k < bs; ++k) {
+        __syncthreads();
+        const double p = 1.0 / T[k][k];
+        __syncthreads();
+        for (int j = threadIdx.x; j < bs; j += 256) T[k][j] = (j == k) ? p : T[k][j] * p;
+        __syncthreads();
+        for (int e = threadIdx.x; e < bs * bs; e += 256) {
+            const int i = e % bs, j = e / bs;
+            if (i != k && j != k) T[i][j] -= T[i][k] * T[k][j];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < bs; i += 256)
+            if (i != k) T[i][k] = -T[i][k] * p;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < bs * bs; e += 256) {
+        const int r = e % bs, c = e / bs;
+        P[(int64_t)c * bs + r] = -T[r][c];
+    }
+}
+
+// row block k0..k0+bs of A := -Rn (Rn = -P^{-1} A_K,:) outside the block
+// columns; column block := Cn (= -A_:,K P^{-1}) outside the block rows, and
+// the diagonal block := P^{-1} = -Pn.
+__global__ void k_gj_fix(double *A, int n, int k0, int bs, const double *Rn, const double *Cn, const double *Pn) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nrow = (int64_t)bs * n;
+    if (e < nrow) {  // row block, all columns j (block columns get -Pn below)
+        const int r = (int)(e % bs), j = (int)(e / bs);
+        if (j < k0 || j >= k0 + bs) A[(int64_t)j * n + k0 + r] = -Rn[(int64_t)j * bs + r];
+        return;
+    }
+    e -= nrow;
+    if (e >= nrow) return;
+    const int i = (int)(e % n), c = (int)(e / n);  // column block, all rows i
+    if (i < k0 || i >= k0 + bs)
+        A[(int64_t)(k0 + c) * n + i] = Cn[(int64_t)c * n + i];
+    else
+        A[(int64_t)(k0 + c) * n + i] = -Pn[(int64_t)c * bs + (i - k0)];
+}
+
+// per bubble: sums[0][b] = sum s x, sums[1][b] = sum U x, sums[2][b] = sum s v,
+// with x = Y / R[b] (caller order), v = X
+__global__ void k_coarse_sums(const double *Y, const double *X, const double *R, const double *s,
+                              const double *U, int nd, int nb, double *sums) {
+    __shared__ double red[3][256];
+    const int b = blockIdx.x;
+    const double ir = 1.0 / R[b];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int v = threadIdx.x; v < nd; v += 256) {
+        const int64_t o = (int64_t)b * nd + v;
+        const double x = Y[o] * ir;
+        a0 += s[o] * x;
+        a1 += U[o] * x;
+        a2 += s[o] * X[o];
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    red[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) sums[(int64_t)k * nb + b] = red[k][0];
+}
+
+// coarse right-hand side rc_a = sum s v - U.x - area_a sum_{b != a} m_b / (4 pi d_ab),
+// written over sums[2]
+__global__ void k_coarse_rhs(const double *cen, const double *area, int nb, double *sums) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nb) return;
+    const double *m = sums;
+    double far = 0.0;
+    const double ax = cen[3 * a], ay = cen[3 * a + 1], az = cen[3 * a + 2];
+    for (int b = 0; b < nb; ++b) {
+        if (b == a) continue;
+        const double dx = ax - cen[3 * b], dy = ay - cen[3 * b + 1], dz = az - cen[3 * b + 2];
+        far += m[b] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    sums[2 * (int64_t)nb + a] -= sums[(int64_t)nb + a] + area[a] * far * (1.0 / (4.0 * 3.14159265358979323846));
+}
+
+// y = A x (column-major nb x nb), one thread per row
+__global__ void k_dense_mv(const double *A, const double *x, int nb, double *y) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nb) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += A[(int64_t)b * nb + a] * x[b];
+    y[a] = t;
 }
 
 void precond_radii(bfm_ctx *c) {
@@ -258,8 +454,70 @@ void precond_apply(bfm_ctx *c, const double *in_s, double *out_s) {
     // Y = G C + c X
     k_gemm_nn<<<g2, 256, 0, st>>>(nd, nb, nc, P.basis.G.get(), nd, Cm, nc, Y, nd, nullptr, P.cc, X, nd);
     BFM_LAUNCHED();
-    k_precond_out<<<nblk(c->nv, 256), 256, 0, st>>>(Y, c->tree.idx_a.get(), c->nv, nd, P.R.get(), out_s);
+    const double *cy = nullptr;
+    if (c->opt.precond == BFM_PRECOND_SH_COARSE) {
+        double *sums = P.csum.get();
+        k_coarse_sums<<<nb, 256, 0, st>>>(Y, X, P.R.get(), c->s.get(), P.U.get(), nd, nb, sums);
+        BFM_LAUNCHED();
+        k_coarse_rhs<<<nblk(nb, 128), 128, 0, st>>>(P.ccen.get(), P.carea.get(), nb, sums);
+        BFM_LAUNCHED();
+        k_dense_mv<<<nblk(nb, 128), 128, 0, st>>>(P.Ainv.get(), sums + 2 * (int64_t)nb, nb, P.cy.get());
+        BFM_LAUNCHED();
+        cy = P.cy.get();
+    }
+    k_precond_out<<<nblk(c->nv, 256), 256, 0, st>>>(Y, c->tree.idx_a.get(), c->nv, nd, P.R.get(), cy, out_s);
     BFM_LAUNCHED();
+}
+
+void coarse_build(bfm_ctx *c) {
+    Precond &P = c->pre;
+    hipStream_t st = c->stream;
+    const int nd = P.nd, nb = c->nb;
+    BFM_CHECK(c->diag_valid, BFM_EINVAL, "coarse space needs the diagonals of the current mesh");
+    double *cen = P.ccen.ensure(3 * (size_t)nb), *area = P.carea.ensure(nb);
+    k_coarse_geom<<<nb, 256, 0, st>>>(c->xyz.get(), c->s.get(), nd, cen, area);
+    BFM_LAUNCHED();
+    double *lii = P.Y.ensure((size_t)nd * nb);  // work: L_ii in caller order
+    to_original(c, c->lii_s.get(), lii);
+    double *U = P.U.ensure((size_t)nd * nb);
+    k_coarse_u<<<dim3(nblk(nd, 256), nb), 256, 0, st>>>(c->xyz.get(), c->s.get(), lii, nd, U);
+    BFM_LAUNCHED();
+    double *A = P.Ainv.ensure((size_t)nb * nb);
+    k_coarse_matrix<<<nblk((int64_t)nb * nb, 256), 256, 0, st>>>(cen, area, U, nd, nb, A);
+    BFM_LAUNCHED();
+    // blocked Gauss-Jordan inversion in place
+    const int B = kGjBlock;
+    double *Pn = P.gj_piv.ensure((size_t)B * B);
+    double *Rn = P.gj_row.ensure((size_t)B * nb);
+    double *Cn = P.gj_col.ensure((size_t)nb * B);
+    for (int k0 = 0; k0 < nb; k0 += B) {
+        const int bs = std::min(B, nb - k0);
+        k_gj_block<<<1, 256, 0, st>>>(A, nb, k0, bs, Pn);
+        BFM_LAUNCHED();
+        // Rn = Pn A_K,:  (= -P^{-1} A_K,:), bs x nb
+        gemm_nn_f64(bs, nb, bs, Pn, bs, A + k0, nb, Rn, bs, st);
+        // trailing columns outside the block: A += A_:,K Rn
+        dim3 g((nb + 63) / 64, 1);
+        if (k0 > 0) {
+            g.y = (k0 + 63) / 64;
+            k_gemm_nn<<<g, 256, 0, st>>>(nb, k0, bs, A + (int64_t)k0 * nb, nb, Rn, bs, A, nb, nullptr, 1.0, A,
+                                         nb);
+            BFM_LAUNCHED();
+        }
+        const int j1 = k0 + bs;
+        if (j1 < nb) {
+            g.y = (nb - j1 + 63) / 64;
+            k_gemm_nn<<<g, 256, 0, st>>>(nb, nb - j1, bs, A + (int64_t)k0 * nb, nb, Rn + (int64_t)j1 * bs, bs,
+                                         A + (int64_t)j1 * nb, nb, nullptr, 1.0, A + (int64_t)j1 * nb, nb);
+            BFM_LAUNCHED();
+        }
+        // Cn = A_:,K Pn  (= -A_:,K P^{-1}), nb x bs
+        gemm_nn_f64(nb, bs, bs, A + (int64_t)k0 * nb, nb, Pn, bs, Cn, nb, st);
+        k_gj_fix<<<nblk(2 * (int64_t)bs * nb, 256), 256, 0, st>>>(A, nb, k0, bs, Rn, Cn, Pn);
+        BFM_LAUNCHED();
+    }
+    P.csum.ensure(3 * (size_t)nb);
+    P.cy.ensure(nb);
 }
 
 }  // namespace bfm

@@ -466,12 +466,13 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
         return hs[0];
     };
     int matvecs = 0;
-    const bool pc = c->opt.precond == BFM_PRECOND_SH;
+    const bool pc = c->opt.precond != BFM_PRECOND_NONE;
     double *Z = nullptr, *Tv = nullptr;
     if (pc) {
-        BFM_CHECK(c->pre.nd > 0, BFM_EINVAL, "BFM_PRECOND_SH needs bfm_set_sphere_template");
+        BFM_CHECK(c->pre.nd > 0, BFM_EINVAL, "the harmonic preconditioner needs bfm_set_sphere_template");
         precond_build(c);
         precond_radii(c);
+        if (c->opt.precond == BFM_PRECOND_SH_COARSE) coarse_build(c);
         Z = c->zbuf.ensure(n);
         Tv = c->tbuf.ensure(n);
     }
