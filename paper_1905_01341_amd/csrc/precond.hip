@@ -331,31 +331,46 @@ __global__ void k_coarse_matrix(const double *cen, const double *area, const dou
 // Gauss-Jordan inverse (no pivoting: the coarse matrix is symmetric positive
 // definite) of the bs x bs diagonal block at (k0, k0) of A (column-major,
 // leading dimension n); writes -inverse to P (column-major bs x bs).
+// Thread t owns column t % 64 and rows 16 (t / 64) .. +15 in registers; each
+// step publishes the pivot row and column through LDS.
 constexpr int kGjBlock = 64;
 __global__ void __launch_bounds__(256) k_gj_block(const double *A, int n, int k0, int bs, double *P) {
-    __shared__ double T[kGjBlock][kGjBlock + 1];
-    for (int e = threadIdx.x; e < bs * bs; e += 256) {
-        const int r = e % bs, c = e / bs;
-        T[r][c] = A[(int64_t)(k0 + c) * n + k0 + r];
+    __shared__ double prow[kGjBlock], pcol[kGjBlock];
+    const int j = threadIdx.x % kGjBlock, i0 = 16 * (threadIdx.x / kGjBlock);
+    double t[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + r;
+        // identity outside the bs x bs block keeps the padded steps inert
+        t[r] = (i < bs && j < bs) ? A[(int64_t)(k0 + j) * n + k0 + i] : (i == j ? 1.0 : 0.0);
     }
-    for (int k = 0; k < bs; ++k) {
-        __syncthreads();
-        const double p = 1.0 / T[k][k];
-        __syncthreads();
-        for (int j = threadIdx.x; j < bs; j += 256) T[k][j] = (j == k) ? p : T[k][j] * p;
-        __syncthreads();
-        for (int e = threadIdx.x; e < bs * bs; e += 256) {
-            const int i = e % bs, j = e / bs;
-            if (i != k && j != k) T[i][j] -= T[i][k] * T[k][j];
+    for (int k = 0; k < kGjBlock; ++k) {
+        // publish column k (old values) and row k
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (j == k) pcol[i0 + r] = t[r];
+            if (i0 + r == k) prow[j] = t[r];
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < bs; i += 256)
-            if (i != k) T[i][k] = -T[i][k] * p;
+        const double p = 1.0 / prow[k];
+        const double rk = (j == k) ? p : prow[j] * p;  // new row k, column j
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = i0 + r;
+            const double f = pcol[i];
+            if (i == k)
+                t[r] = rk;
+            else if (j == k)
+                t[r] = -f * p;
+            else
+                t[r] -= f * rk;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < bs * bs; e += 256) {
-        const int r = e % bs, c = e / bs;
-        P[(int64_t)c * bs + r] = -T[r][c];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + r;
+        if (i < bs && j < bs) P[(int64_t)j * bs + i] = -t[r];
     }
 }
 
@@ -408,28 +423,43 @@ __global__ void k_coarse_sums(const double *Y, const double *X, const double *R,
 }
 
 // coarse right-hand side rc_a = sum s v - U.x - area_a sum_{b != a} m_b / (4 pi d_ab),
-// written over sums[2]
+// written over sums[2]; one block per bubble a
 __global__ void k_coarse_rhs(const double *cen, const double *area, int nb, double *sums) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= nb) return;
+    __shared__ double red[256];
+    const int a = blockIdx.x;
     const double *m = sums;
-    double far = 0.0;
     const double ax = cen[3 * a], ay = cen[3 * a + 1], az = cen[3 * a + 2];
-    for (int b = 0; b < nb; ++b) {
+    double far = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
         if (b == a) continue;
         const double dx = ax - cen[3 * b], dy = ay - cen[3 * b + 1], dz = az - cen[3 * b + 2];
         far += m[b] / sqrt(dx * dx + dy * dy + dz * dz);
     }
-    sums[2 * (int64_t)nb + a] -= sums[(int64_t)nb + a] + area[a] * far * (1.0 / (4.0 * 3.14159265358979323846));
+    red[threadIdx.x] = far;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        sums[2 * (int64_t)nb + a] -=
+            sums[(int64_t)nb + a] + area[a] * red[0] * (1.0 / (4.0 * 3.14159265358979323846));
 }
 
-// y = A x (column-major nb x nb), one thread per row
+// y = A x for symmetric A (nb x nb): row a read as column a; one block per row
 __global__ void k_dense_mv(const double *A, const double *x, int nb, double *y) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= nb) return;
+    __shared__ double red[256];
+    const int a = blockIdx.x;
+    const double *col = A + (int64_t)a * nb;
     double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += A[(int64_t)b * nb + a] * x[b];
-    y[a] = t;
+    for (int b = threadIdx.x; b < nb; b += 256) t += col[b] * x[b];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) y[a] = red[0];
 }
 
 void precond_radii(bfm_ctx *c) {
@@ -459,9 +489,9 @@ void precond_apply(bfm_ctx *c, const double *in_s, double *out_s) {
         double *sums = P.csum.get();
         k_coarse_sums<<<nb, 256, 0, st>>>(Y, X, P.R.get(), c->s.get(), P.U.get(), nd, nb, sums);
         BFM_LAUNCHED();
-        k_coarse_rhs<<<nblk(nb, 128), 128, 0, st>>>(P.ccen.get(), P.carea.get(), nb, sums);
+        k_coarse_rhs<<<nb, 256, 0, st>>>(P.ccen.get(), P.carea.get(), nb, sums);
         BFM_LAUNCHED();
-        k_dense_mv<<<nblk(nb, 128), 128, 0, st>>>(P.Ainv.get(), sums + 2 * (int64_t)nb, nb, P.cy.get());
+        k_dense_mv<<<nb, 256, 0, st>>>(P.Ainv.get(), sums + 2 * (int64_t)nb, nb, P.cy.get());
         BFM_LAUNCHED();
         cy = P.cy.get();
     }
