@@ -1,5 +1,5 @@
 /*
- * bfm_debug.h - host-only introspection of libbfm for tests (no GPU needed).
+ * bfm_debug.h - introspection of libbfm for tests.
  *
  * The fast multipole translations of the paper's FMM (Section 3.9:
  * multipole and local expansions of degrees 0..p_fmm-1, translated between
@@ -26,6 +26,18 @@ extern "C" {
  * Returns 0, or -1 (BFM_EINVAL) on a bad p, kind or index.
  */
 int bfm_debug_operator(int p, int kind, int index, double *out, int *d_out);
+
+/*
+ * Device dense kernels on host data, for tests (need a GPU):
+ * bfm_debug_dgemm: C = A B with the library's FP64 MFMA GEMM; A [M x K],
+ * B [K x N], C [M x N], all column-major host arrays.
+ * bfm_debug_spd_inverse: the library's in-place blocked Gauss-Jordan inverse
+ * (no pivoting) of a symmetric positive definite n x n column-major matrix,
+ * as used for the coarse correction of BFM_PRECOND_SH_COARSE.
+ * Return BFM_OK or a BFM_E* code (message in bfm_last_error()).
+ */
+int bfm_debug_dgemm(int device, int M, int N, int K, const double *A, const double *B, double *C);
+int bfm_debug_spd_inverse(int device, int n, const double *A, double *Ainv);
 
 #ifdef __cplusplus
 }

@@ -114,6 +114,8 @@ def load(path: str = LIB_PATH):
         "bfm_tree_stats": ([P, ctypes.POINTER(I64)], I),
         "bfm_last_error": ([], ctypes.c_char_p),
         "bfm_debug_operator": ([I, I, I, P, P], I),
+        "bfm_debug_dgemm": ([I, I, I, I, P, P, P], I),
+        "bfm_debug_spd_inverse": ([I, I, P, P], I),
         "bfm_profile": ([P, I], I),
         "bfm_profile_read": ([P, P, P, P], I),
         "bfm_mlp_init": ([P, ctypes.c_uint64], I),
@@ -166,6 +168,27 @@ def debug_operator(p: int, kind: int, index: int):
     d = np.zeros(3, dtype=np.int32)
     _check(load().bfm_debug_operator(p, kind, index, _ptr(out), _ptr(d)))
     return out, d
+
+
+def debug_dgemm(A, B, device=0):
+    """C = A B on the device with the library's FP64 MFMA GEMM (test hook)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    B = np.asfortranarray(B, dtype=np.float64)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    C = np.empty((M, N), dtype=np.float64, order="F")
+    _check(load().bfm_debug_dgemm(device, M, N, K, _ptr(A), _ptr(B), _ptr(C)))
+    return C
+
+
+def debug_spd_inverse(A, device=0):
+    """The library's blocked Gauss-Jordan inverse of an SPD matrix (test hook)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    n = A.shape[0]
+    out = np.empty((n, n), dtype=np.float64, order="F")
+    _check(load().bfm_debug_spd_inverse(device, n, _ptr(A), _ptr(out)))
+    return out
 
 
 class Solver:

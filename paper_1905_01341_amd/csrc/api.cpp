@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/bfm_debug.h"
 #include "../../include/bfm_mlp.h"
 #include "ctx.h"
 #include "learn.h"
@@ -634,6 +635,42 @@ int bfm_mlp_guess(bfm_ctx *c, const double *phi, double *q) {
         mlp_guess(c, dv.get(), dv.get() + n);
         BFM_HIP(hipMemcpyAsync(q, dv.get() + n, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         BFM_HIP(hipStreamSynchronize(st));
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Test hooks (include/bfm_debug.h)
+
+int bfm_debug_dgemm(int device, int M, int N, int K, const double *A, const double *B, double *C) {
+    return guarded([&] {
+        BFM_CHECK(A && B && C, BFM_EINVAL, "null argument");
+        BFM_CHECK(M >= 1 && N >= 1 && K >= 1 && (int64_t)M * N <= (1 << 26) && (int64_t)M * K <= (1 << 26) &&
+                      (int64_t)K * N <= (1 << 26),
+                  BFM_EINVAL, "sizes out of range");
+        DeviceScope ds(device);
+        DevBuf<double> a, b, c;
+        a.ensure((size_t)M * K);
+        b.ensure((size_t)K * N);
+        c.ensure((size_t)M * N);
+        BFM_HIP(hipMemcpy(a.get(), A, sizeof(double) * M * K, hipMemcpyHostToDevice));
+        BFM_HIP(hipMemcpy(b.get(), B, sizeof(double) * K * N, hipMemcpyHostToDevice));
+        gemm_nn_f64(M, N, K, a.get(), M, b.get(), K, c.get(), M, nullptr);
+        BFM_HIP(hipDeviceSynchronize());
+        BFM_HIP(hipMemcpy(C, c.get(), sizeof(double) * M * N, hipMemcpyDeviceToHost));
+    });
+}
+
+int bfm_debug_spd_inverse(int device, int n, const double *A, double *Ainv) {
+    return guarded([&] {
+        BFM_CHECK(A && Ainv, BFM_EINVAL, "null argument");
+        BFM_CHECK(n >= 1 && n <= 8192, BFM_EINVAL, "n out of range");
+        DeviceScope ds(device);
+        DevBuf<double> a, piv, row, col;
+        a.ensure((size_t)n * n);
+        BFM_HIP(hipMemcpy(a.get(), A, sizeof(double) * n * n, hipMemcpyHostToDevice));
+        spd_inverse(a.get(), n, piv, row, col, nullptr);
+        BFM_HIP(hipDeviceSynchronize());
+        BFM_HIP(hipMemcpy(Ainv, a.get(), sizeof(double) * n * n, hipMemcpyDeviceToHost));
     });
 }
 

@@ -100,6 +100,9 @@ void precond_radii(bfm_ctx *c);
 void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);
 // coarse correction of the two-level form (needs the diagonals of the current mesh)
 void coarse_build(bfm_ctx *c);
+// in-place inverse of an SPD n x n column-major device matrix (blocked Gauss-Jordan)
+void spd_inverse(double *A, int n, DevBuf<double> &piv, DevBuf<double> &row, DevBuf<double> &col,
+                 hipStream_t st);
 // C = A B, column-major FP64 (precond.hip)
 void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                  hipStream_t st);

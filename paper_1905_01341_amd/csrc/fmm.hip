@@ -60,81 +60,114 @@ static void upload_tables(int device) {
 }
 
 // ---------------------------------------------------------------------------
-// P2M. One wave per leaf; lane (m, s) builds the order-m column of the
-// regular harmonics for the leaf's points s, s + S, s + 2S, ... (S = 64/p
-// point subsets) and keeps its p - m coefficients in registers; the S
-// partial sums are added through LDS at the end.
+// P2M. One wave per leaf; lane l takes the leaf's points l, l + 64, ... and
+// evaluates the regular harmonics of its point in registers, order by order
+// (the loops over order m and degree k are uniform across the wave and fully
+// unrolled, so every coefficient has a fixed register slot); every kCS slots
+// the wave's 64 values per slot are summed through LDS (transposed: lane t
+// adds up slot t) into the leaf's running totals.
 //   Mt_n^m += q_j conj(Rt_n^m(v_j)) + (w_j / h) conj(n_j . grad_v Rt_n^m(v_j)),
 // v_j = (r_j - c)/h. The directional derivative D = n_j . grad_v follows the
 // same recurrence by forward differentiation:
 //   D Rt_m^m = [D Rt_{m-1}^{m-1} (x+iy) + Rt_{m-1}^{m-1} (n_x+i n_y)] f_m
 //   D Rt_n^m = [(2n-1)(n_z Rt_{n-1} + z D Rt_{n-1}) - b (2 v.n Rt_{n-2} + r^2 D Rt_{n-2})] a
+// Slots run over m, then degree k >= m, then (real, imaginary) for m > 0.
+constexpr int kCS = 32;
+
+__host__ __device__ constexpr int p2m_slot(int P, int m, int k) {
+    return m == 0 ? k : P + (m - 1) * (2 * P - m) + 2 * (k - m);
+}
+
+// slot -> index in the packed expansion layout
+__device__ inline int p2m_slot_out(int P, int s) {
+    if (s < P) return s * s;
+    s -= P;
+    for (int m = 1; m < P; ++m) {
+        const int cnt = 2 * (P - m);
+        if (s < cnt) {
+            const int k = m + s / 2;
+            return k * k + 2 * m - 1 + (s & 1);
+        }
+        s -= cnt;
+    }
+    return 0;
+}
+
+template <int PP>
+__device__ inline void p2m_put(int s, double v, double (&acc)[kCS], double (*red)[65], double *tot, int lane) {
+    acc[s % kCS] = v;
+    if (s % kCS == kCS - 1 || s == PP - 1) {
+        const int base = s - s % kCS, cnt = s % kCS + 1;
+#pragma unroll
+        for (int t = 0; t < kCS; ++t)
+            if (t < cnt) red[t][lane] = acc[t];
+        __syncthreads();
+        if (lane < cnt) {
+            double sum = 0.0;
+#pragma unroll 16
+            for (int l = 0; l < 64; ++l) sum += red[lane][l];
+            tot[base + lane] += sum;
+        }
+        __syncthreads();
+    }
+}
+
 template <int P_, int NCH, bool MONO, bool DIP>
 __global__ void __launch_bounds__(64) k_p2m(int64_t leaf0, const int *leaf_pt, const double *centre,
                                             double h, const double *px, const double *py,
                                             const double *pz, const double *pnx, const double *pny,
                                             const double *pnz, int64_t n, const double *q,
                                             const double *w, double *mexp) {
-    constexpr int S = 64 / P_;
     constexpr int PP = P_ * P_;
-    constexpr int RW = 2 * P_ + 1;  // padded row: lanes m and m+1 start 2p+1 doubles apart (no bank conflict)
-    __shared__ double red[S][P_][RW];  // [subset][m][2n + re/im]
+    __shared__ double red[kCS][65];
+    __shared__ double tot[PP];
     const int lane = threadIdx.x;
-    const int m = lane % P_, s = lane / P_;
-    const bool active = s < S;
     const int leaf = blockIdx.x;
     const int64_t box = leaf0 + leaf;
     const int r0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
     const double cx = centre[3 * box], cy = centre[3 * box + 1], cz = centre[3 * box + 2];
     const double ih = 1.0 / h;
-    double *acc = &red[active ? s : 0][m][0];  // this lane's p x 2 slots
-    // this lane's recurrence coefficients (order m), held in registers
-    double ca[P_], cb[P_];
-#pragma unroll
-    for (int k = 0; k < P_; ++k) {
-        const bool on = k > m;
-        ca[k] = on ? c_rec_a[on ? tri(k, m) : 0] : 0.0;
-        cb[k] = on ? c_rec_b[on ? tri(k, m) : 0] : 0.0;
-    }
     for (int c = 0; c < NCH; ++c) {
-        if (active) {
+        for (int t = lane; t < PP; t += 64) tot[t] = 0.0;
+        for (int j0 = r0; j0 < r1; j0 += 64) {
+            const int j = j0 + lane;
+            const bool ok = j < r1;
+            // idle lanes: a point at the centre with zero strength
+            const double x = ok ? (px[j] - cx) * ih : 0.0, y = ok ? (py[j] - cy) * ih : 0.0,
+                         z = ok ? (pz[j] - cz) * ih : 0.0;
+            const double r2 = x * x + y * y + z * z;
+            const double qq = (MONO && ok) ? q[(int64_t)c * n + j] : 0.0;
+            double ux = 0.0, uy = 0.0, uz = 0.0, ww = 0.0, vu = 0.0;
+            if (DIP && ok) {
+                ux = pnx[j];
+                uy = pny[j];
+                uz = pnz[j];
+                ww = w[(int64_t)c * n + j] * ih;
+                vu = x * ux + y * uy + z * uz;
+            }
+            double acc[kCS];
+            double dr = 1.0, di = 0.0, Ddr = 0.0, Ddi = 0.0;  // Rt_m^m and its derivative
 #pragma unroll
-            for (int k = 0; k < 2 * P_; ++k) acc[k] = 0.0;
-            for (int j = r0 + s; j < r1; j += S) {
-                const double x = (px[j] - cx) * ih, y = (py[j] - cy) * ih, z = (pz[j] - cz) * ih;
-                const double r2 = x * x + y * y + z * z;
-                const double qq = MONO ? q[(int64_t)c * n + j] : 0.0;
-                double ux = 0.0, uy = 0.0, uz = 0.0, ww = 0.0, vu = 0.0;
-                if (DIP) {
-                    ux = pnx[j];
-                    uy = pny[j];
-                    uz = pnz[j];
-                    ww = w[(int64_t)c * n + j] * ih;
-                    vu = x * ux + y * uy + z * uz;
-                }
-                // diagonal Rt_m^m (and its derivative): steps k = 1..m, predicated
-                double dr = 1.0, di = 0.0, Ddr = 0.0, Ddi = 0.0;
-#pragma unroll
-                for (int k = 1; k < P_; ++k) {
-                    if (k <= m) {
-                        const double f = c_diag[k];
-                        const double nr = (dr * x - di * y) * f, ni = (dr * y + di * x) * f;
-                        if (DIP) {
-                            const double nDr = (Ddr * x - Ddi * y + dr * ux - di * uy) * f;
-                            const double nDi = (Ddr * y + Ddi * x + dr * uy + di * ux) * f;
-                            Ddr = nDr;
-                            Ddi = nDi;
-                        }
-                        dr = nr;
-                        di = ni;
+            for (int m = 0; m < P_; ++m) {
+                if (m > 0) {
+                    const double f = c_diag[m];
+                    const double nr = (dr * x - di * y) * f, ni = (dr * y + di * x) * f;
+                    if (DIP) {
+                        const double nDr = (Ddr * x - Ddi * y + dr * ux - di * uy) * f;
+                        const double nDi = (Ddr * y + Ddi * x + dr * uy + di * ux) * f;
+                        Ddr = nDr;
+                        Ddi = nDi;
                     }
+                    dr = nr;
+                    di = ni;
                 }
-                double cr = dr, ci = di, Dcr = Ddr, Dci = Ddi;  // degree k
+                double cr = dr, ci = di, Dcr = Ddr, Dci = Ddi;     // degree k
                 double pr = 0.0, pi = 0.0, Dpr = 0.0, Dpi = 0.0;  // degree k - 1
 #pragma unroll
-                for (int k = 0; k < P_; ++k) {
+                for (int k = m; k < P_; ++k) {
                     if (k > m) {
-                        const double a = ca[k], b = cb[k], e = (2.0 * k - 1.0);
+                        const int t = tri(k, m);
+                        const double a = c_rec_a[t], b = c_rec_b[t], e = (2.0 * k - 1.0);
                         const double nr = (e * z * cr - b * r2 * pr) * a;
                         const double ni = (e * z * ci - b * r2 * pi) * a;
                         if (DIP) {
@@ -150,31 +183,15 @@ __global__ void __launch_bounds__(64) k_p2m(int64_t leaf0, const int *leaf_pt, c
                         cr = nr;
                         ci = ni;
                     }
-                    if (k >= m) {
-                        acc[2 * k] += qq * cr + ww * Dcr;
-                        acc[2 * k + 1] -= qq * ci + ww * Dci;  // conjugate
-                    }
+                    const int s = p2m_slot(P_, m, k);
+                    p2m_put<PP>(s, qq * cr + ww * Dcr, acc, red, tot, lane);
+                    if (m > 0) p2m_put<PP>(s + 1, -(qq * ci + ww * Dci), acc, red, tot, lane);  // conjugate
                 }
             }
         }
         __syncthreads();
-        if (active && s == 0) {
-            double *out = mexp + (box * NCH + c) * PP;
-            for (int k = m; k < P_; ++k) {
-                double vr = 0.0, vi = 0.0;
-#pragma unroll
-                for (int ss = 0; ss < S; ++ss) {
-                    vr += red[ss][m][2 * k];
-                    vi += red[ss][m][2 * k + 1];
-                }
-                if (m == 0) {
-                    out[k * k] = vr;
-                } else {
-                    out[k * k + 2 * m - 1] = vr;
-                    out[k * k + 2 * m] = vi;
-                }
-            }
-        }
+        double *out = mexp + (box * NCH + c) * PP;
+        for (int t = lane; t < PP; t += 64) out[p2m_slot_out(P_, t)] = tot[t];
         __syncthreads();
     }
 }

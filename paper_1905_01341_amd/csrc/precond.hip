@@ -168,55 +168,67 @@ __global__ void k_bubble_radius(const double *s, int nd, double *R) {
     if (threadIdx.x == 0) R[b] = sqrt(red[0] / (4.0 * 3.14159265358979323846));
 }
 
-// C[M x N] = A[M x K] B[K x N] (+ beta D), all column-major; 64 x 64 tiles,
-// 256 threads with 4 x 4 outputs each, K staged through LDS in chunks of 16.
-// rowscale (may be null) multiplies row i of A B by rowscale[i] before beta D
-// is added.
+// C[M x N] = rowscale o (A[M x K] B[K x N]) + beta D, all column-major, FP64
+// MFMA (v_mfma_f64_16x16x4f64). A workgroup of 4 waves owns a 64 x 64 tile
+// of C (each wave a 32 x 32 quarter, 2 x 2 MFMA blocks); K advances in
+// chunks of 16 staged through LDS. rowscale and D may be null. C may alias D
+// (each element is read and written by the same lane) but not A or B.
+// MFMA operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// of a 16 x 4 by 4 x 16 product; element r of the result holds row
+// l / 16 + 4 r, column l % 16.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, const double *A, int lda,
                                                  const double *B, int ldb, double *C, int ldc,
                                                  const double *rowscale, double beta, const double *D,
                                                  int ldd) {
-    __shared__ double As[16][64 + 1], Bs[16][64 + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    __shared__ double As[16][64 + 1], Bs[16][64 + 1];  // [k][row], [k][col]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-    double acc[4][4] = {};
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    dbl4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < K; k0 += 16) {
         for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = e / 64, ii = e % 64;
+            const int ii = e % 64, kk = e / 64;  // A: consecutive rows
             const int gi = i0 + ii, gk = k0 + kk;
             As[kk][ii] = (gi < M && gk < K) ? A[(int64_t)gk * lda + gi] : 0.0;
-            const int jj = e % 64, kb = e / 64;
+            const int kb = e % 16, jj = e / 16;  // B: consecutive k within a column
             const int gj = j0 + jj, gk2 = k0 + kb;
             Bs[kb][jj] = (gj < N && gk2 < K) ? B[(int64_t)gj * ldb + gk2] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], b[4];
+        for (int k4 = 0; k4 < 4; ++k4) {
+            const int kk = 4 * k4 + lane / 16;
+            double af[2], bf[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = As[kk][tx + 16 * u];
-                b[u] = Bs[kk][ty + 16 * u];
-            }
+            for (int a = 0; a < 2; ++a) af[a] = As[kk][wi + 16 * a + lane % 16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[kk][wj + 16 * b + lane % 16];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int gi = i0 + tx + 16 * u, gj = j0 + ty + 16 * v;
-            if (gi < M && gj < N) {
-                double val = acc[u][v];
-                if (rowscale) val *= rowscale[gi];
-                if (D) val += beta * D[(int64_t)gj * ldd + gi];
-                C[(int64_t)gj * ldc + gi] = val;
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = i0 + wi + 16 * a + lane / 16 + 4 * r, gj = j0 + wj + 16 * b + lane % 16;
+                if (gi < M && gj < N) {
+                    double val = acc[a][b][r];
+                    if (rowscale) val *= rowscale[gi];
+                    if (D) val += beta * D[(int64_t)gj * ldd + gi];
+                    C[(int64_t)gj * ldc + gi] = val;
+                }
             }
-        }
 }
 
 // C = A B, all column-major (the plain product of k_gemm_nn)
@@ -499,27 +511,16 @@ void precond_apply(bfm_ctx *c, const double *in_s, double *out_s) {
     BFM_LAUNCHED();
 }
 
-void coarse_build(bfm_ctx *c) {
-    Precond &P = c->pre;
-    hipStream_t st = c->stream;
-    const int nd = P.nd, nb = c->nb;
-    BFM_CHECK(c->diag_valid, BFM_EINVAL, "coarse space needs the diagonals of the current mesh");
-    double *cen = P.ccen.ensure(3 * (size_t)nb), *area = P.carea.ensure(nb);
-    k_coarse_geom<<<nb, 256, 0, st>>>(c->xyz.get(), c->s.get(), nd, cen, area);
-    BFM_LAUNCHED();
-    double *lii = P.Y.ensure((size_t)nd * nb);  // work: L_ii in caller order
-    to_original(c, c->lii_s.get(), lii);
-    double *U = P.U.ensure((size_t)nd * nb);
-    k_coarse_u<<<dim3(nblk(nd, 256), nb), 256, 0, st>>>(c->xyz.get(), c->s.get(), lii, nd, U);
-    BFM_LAUNCHED();
-    double *A = P.Ainv.ensure((size_t)nb * nb);
-    k_coarse_matrix<<<nblk((int64_t)nb * nb, 256), 256, 0, st>>>(cen, area, U, nd, nb, A);
-    BFM_LAUNCHED();
-    // blocked Gauss-Jordan inversion in place
+// In-place inverse of a symmetric positive definite n x n matrix
+// (column-major) by blocked Gauss-Jordan elimination without pivoting:
+// per diagonal block K, P = A_KK^{-1}; A_Kj <- P A_Kj, A_ij <- A_ij - A_iK P A_Kj,
+// A_iK <- -A_iK P, A_KK <- P (j, i outside K).
+void spd_inverse(double *A, int nb, DevBuf<double> &piv, DevBuf<double> &row, DevBuf<double> &col,
+                 hipStream_t st) {
     const int B = kGjBlock;
-    double *Pn = P.gj_piv.ensure((size_t)B * B);
-    double *Rn = P.gj_row.ensure((size_t)B * nb);
-    double *Cn = P.gj_col.ensure((size_t)nb * B);
+    double *Pn = piv.ensure((size_t)B * B);
+    double *Rn = row.ensure((size_t)B * nb);
+    double *Cn = col.ensure((size_t)nb * B);
     for (int k0 = 0; k0 < nb; k0 += B) {
         const int bs = std::min(B, nb - k0);
         k_gj_block<<<1, 256, 0, st>>>(A, nb, k0, bs, Pn);
@@ -546,6 +547,25 @@ void coarse_build(bfm_ctx *c) {
         k_gj_fix<<<nblk(2 * (int64_t)bs * nb, 256), 256, 0, st>>>(A, nb, k0, bs, Rn, Cn, Pn);
         BFM_LAUNCHED();
     }
+}
+
+void coarse_build(bfm_ctx *c) {
+    Precond &P = c->pre;
+    hipStream_t st = c->stream;
+    const int nd = P.nd, nb = c->nb;
+    BFM_CHECK(c->diag_valid, BFM_EINVAL, "coarse space needs the diagonals of the current mesh");
+    double *cen = P.ccen.ensure(3 * (size_t)nb), *area = P.carea.ensure(nb);
+    k_coarse_geom<<<nb, 256, 0, st>>>(c->xyz.get(), c->s.get(), nd, cen, area);
+    BFM_LAUNCHED();
+    double *lii = P.Y.ensure((size_t)nd * nb);  // work: L_ii in caller order
+    to_original(c, c->lii_s.get(), lii);
+    double *U = P.U.ensure((size_t)nd * nb);
+    k_coarse_u<<<dim3(nblk(nd, 256), nb), 256, 0, st>>>(c->xyz.get(), c->s.get(), lii, nd, U);
+    BFM_LAUNCHED();
+    double *A = P.Ainv.ensure((size_t)nb * nb);
+    k_coarse_matrix<<<nblk((int64_t)nb * nb, 256), 256, 0, st>>>(cen, area, U, nd, nb, A);
+    BFM_LAUNCHED();
+    spd_inverse(A, nb, P.gj_piv, P.gj_row, P.gj_col, st);
     P.csum.ensure(3 * (size_t)nb);
     P.cy.ensure(nb);
 }
