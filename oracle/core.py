@@ -281,7 +281,8 @@ def solve(xyz, tri, phi, method="gmres", tol=1e-12, restart=50, x0=None, maxit=2
         L, _ = dense_offdiag(xyz, s, n)
         L[np.diag_indices_from(L)] = Lii
         q = np.linalg.solve(L, b)
-        info.update(iterations=0, rel_residual=np.linalg.norm(L @ q - b) / np.linalg.norm(b))
+        nb = np.linalg.norm(b)
+        info.update(iterations=0, rel_residual=np.linalg.norm(L @ q - b) / nb if nb > 0 else 0.0)
         return q, info
     base = matvec_L(xyz, s, n, Lii)
     count = [0]
