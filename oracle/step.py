@@ -8,7 +8,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring). Follows the paper:
   0..p_f-1 at the template directions of the bubble's vertices; applied to
   r and phi before the right-hand side and to dr/dt and dphi/dt after it;
 * geometry (Section 3.2, ns1) and bubble volumes by the divergence theorem
-  over the flat triangles, V = sum r1 . (r2 x r3) / 6;
+  over the flat triangles, V = sum r1 . (r2 x r3) / 6 (about the bubble's
+  own first vertex);
 * mean curvature by the fitted paraboloid (Section 3.5, parab1/parab2):
   five one-ring neighbours, local frame with z along n_j, 5 x 5 solve,
   H = -B3 - B5;
@@ -76,11 +77,19 @@ def apply_filter(F, values, nb, nd):
 
 
 def volumes(xyz, tri, tri_off):
-    """Per-bubble volume of the closed polyhedron (divergence theorem)."""
+    """Per-bubble volume of the closed polyhedron (divergence theorem),
+    V = sum (r1 - o) . ((r2 - o) x (r3 - o)) / 6, which is the same for any
+    origin o of a closed surface; o = the first vertex of the bubble's first
+    triangle keeps the terms at the bubble's own scale."""
     r = np.asarray(xyz, dtype=np.float64)
     t = np.asarray(tri)
-    vt = np.einsum("ij,ij->i", r[t[:, 0]], np.cross(r[t[:, 1]], r[t[:, 2]])) / 6.0
-    return np.array([vt[tri_off[b]:tri_off[b + 1]].sum() for b in range(len(tri_off) - 1)])
+    out = []
+    for b in range(len(tri_off) - 1):
+        tb = t[tri_off[b]:tri_off[b + 1]]
+        o = r[tb[0, 0]]
+        a, bb, c = r[tb[:, 0]] - o, r[tb[:, 1]] - o, r[tb[:, 2]] - o
+        out.append(np.einsum("ij,ij->i", a, np.cross(bb, c)).sum() / 6.0)
+    return np.array(out)
 
 
 def one_ring(tri, nv):

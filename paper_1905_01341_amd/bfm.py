@@ -37,6 +37,36 @@ class BfmError(RuntimeError):
         self.code = code
 
 
+class Physics(ctypes.Structure):
+    _fields_ = [
+        ("rho", ctypes.c_double),
+        ("p0", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("pa", ctypes.c_double),
+        ("period", ctypes.c_double),
+        ("forcing_sign", ctypes.c_double),
+        ("g", ctypes.c_double * 3),
+        ("alpha", ctypes.c_double),
+        ("filter_degree", ctypes.c_int),
+        ("guess", ctypes.c_int),
+        ("collect", ctypes.c_int),
+    ]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [
+        ("scheme", ctypes.c_int),
+        ("solves", ctypes.c_int),
+        ("iterations", ctypes.c_int),
+        ("t", ctypes.c_double),
+        ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Options(ctypes.Structure):
     _fields_ = [
         ("abi_version", ctypes.c_int),
@@ -118,6 +148,12 @@ def load(path: str = LIB_PATH):
         "bfm_debug_spd_inverse": ([I, I, P, P], I),
         "bfm_profile": ([P, I], I),
         "bfm_profile_read": ([P, P, P, P], I),
+        "bfm_default_physics": ([ctypes.POINTER(Physics)], I),
+        "bfm_set_physics": ([P, ctypes.POINTER(Physics)], I),
+        "bfm_state_set": ([P, P, P, D], I),
+        "bfm_state_get": ([P, P, P, ctypes.POINTER(D)], I),
+        "bfm_step": ([P, D, ctypes.POINTER(StepInfo)], I),
+        "bfm_rhs": ([P, D, P, P, P, P, P, P], I),
         "bfm_mlp_init": ([P, ctypes.c_uint64], I),
         "bfm_mlp_set_params": ([P, P], I),
         "bfm_mlp_get_params": ([P, P], I),
@@ -388,3 +424,44 @@ class Solver:
     def mlp_guess_dev(self, phi_t, q_t):
         _check(self.lib.bfm_mlp_guess_dev(self.h, ctypes.c_void_p(phi_t.data_ptr()),
                                           ctypes.c_void_p(q_t.data_ptr())))
+
+    # -- time-step harness (include/bfm_step.h) ------------------------------
+
+    def set_physics(self, **kw):
+        ph = Physics()
+        _check(self.lib.bfm_default_physics(ctypes.byref(ph)))
+        for k, v in kw.items():
+            if k == "g":
+                for i in range(3):
+                    ph.g[i] = float(v[i])
+                continue
+            if not hasattr(ph, k):
+                raise KeyError(k)
+            setattr(ph, k, v)
+        _check(self.lib.bfm_set_physics(self.h, ctypes.byref(ph)))
+        self.physics = ph
+
+    def state_set(self, xyz, phi, t=0.0):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        _check(self.lib.bfm_state_set(self.h, _ptr(xyz), _ptr(phi), float(t)))
+
+    def state_get(self):
+        xyz = np.empty((self.nv, 3))
+        phi = np.empty(self.nv)
+        t = ctypes.c_double()
+        _check(self.lib.bfm_state_get(self.h, _ptr(xyz), _ptr(phi), ctypes.byref(t)))
+        return xyz, phi, t.value
+
+    def step(self, dt):
+        info = StepInfo()
+        _check(self.lib.bfm_step(self.h, float(dt), ctypes.byref(info)))
+        return info.as_dict()
+
+    def rhs(self, t, xyz, phi):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        dx = np.empty((self.nv, 3))
+        dp, q, H = (np.empty(self.nv) for _ in range(3))
+        _check(self.lib.bfm_rhs(self.h, float(t), _ptr(xyz), _ptr(phi), _ptr(dx), _ptr(dp), _ptr(q), _ptr(H)))
+        return dx, dp, q, H

@@ -9,6 +9,7 @@
 
 #include "../../include/bfm_debug.h"
 #include "../../include/bfm_mlp.h"
+#include "../../include/bfm_step.h"
 #include "ctx.h"
 #include "learn.h"
 #include "ops.h"
@@ -95,7 +96,7 @@ struct Timer {
     }
 };
 
-static void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm_solve_info *info) {
+void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm_solve_info *info) {
     BFM_CHECK(guess == BFM_GUESS_ZERO || guess == BFM_GUESS_GIVEN || guess == BFM_GUESS_LEARNED, BFM_EINVAL,
               "use_guess must be BFM_GUESS_ZERO, BFM_GUESS_GIVEN or BFM_GUESS_LEARNED");
     bfm_solve_info loc{};
@@ -187,6 +188,7 @@ int bfm_destroy(bfm_ctx *c) {
         DeviceScope ds(c->device);
         (void)hipStreamSynchronize(c->stream);
         mlp_free(c);
+        step_free(c);
         if (c->host_small) (void)hipHostFree(c->host_small);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
@@ -251,11 +253,13 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
             vo = {0, nv};
             to = {0, nt};
         }
+        c->tri_h.assign(tri, tri + 3 * nt);
+        step_mesh_changed(c);
         c->tri0_h.clear();
         for (int64_t k = 3 * to[0]; k < 3 * to[1]; ++k) c->tri0_h.push_back(tri[k] - (int)vo[0]);
         c->pre.nd = 0;
         c->pre.ready = false;
-        c->pre.basis.nmax = -1;
+        c->pre.gen += 1;
         c->vtx_off = vo;
         c->tri_off = to;
         c->xyz.ensure(3 * nv);
@@ -290,7 +294,8 @@ int bfm_set_sphere_template(bfm_ctx *c, int32_t nd, const double *dirs) {
         c->pre.tri_h = c->tri0_h;
         c->pre.nd = nd;
         c->pre.ready = false;
-        c->pre.basis.nmax = -1;  // rebuild harmonics for the new template
+        c->pre.gen += 1;  // rebuild every harmonic basis for the new template
+        step_mesh_changed(c);
     });
 }
 
@@ -671,6 +676,63 @@ int bfm_debug_spd_inverse(int device, int n, const double *A, double *Ainv) {
         spd_inverse(a.get(), n, piv, row, col, nullptr);
         BFM_HIP(hipDeviceSynchronize());
         BFM_HIP(hipMemcpy(Ainv, a.get(), sizeof(double) * n * n, hipMemcpyDeviceToHost));
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Time-step harness (include/bfm_step.h)
+
+int bfm_default_physics(bfm_physics *ph) {
+    if (!ph) return BFM_EINVAL;
+    std::memset(ph, 0, sizeof(*ph));
+    ph->rho = 1.0;
+    ph->p0 = 1.0;
+    ph->sigma = 0.0;
+    ph->kappa = 1.4;
+    ph->forcing_sign = -1.0;
+    ph->alpha = -1.0;
+    ph->guess = BFM_GUESS_GIVEN;
+    return BFM_OK;
+}
+
+int bfm_set_physics(bfm_ctx *c, const bfm_physics *ph) {
+    return guarded([&] {
+        BFM_CHECK(c && ph, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        step_set_physics(c, *ph);
+    });
+}
+
+int bfm_state_set(bfm_ctx *c, const double *xyz, const double *phi, double t) {
+    return guarded([&] {
+        BFM_CHECK(c && xyz && phi, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        step_state_set(c, xyz, phi, t);
+    });
+}
+
+int bfm_state_get(bfm_ctx *c, double *xyz, double *phi, double *t) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        step_state_get(c, xyz, phi, t);
+    });
+}
+
+int bfm_step(bfm_ctx *c, double dt, bfm_step_info *info) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        step_advance(c, dt, info);
+    });
+}
+
+int bfm_rhs(bfm_ctx *c, double t, const double *xyz, const double *phi, double *dxyz, double *dphi, double *q,
+            double *H) {
+    return guarded([&] {
+        BFM_CHECK(c && xyz && phi, BFM_EINVAL, "null argument");
+        DeviceScope ds(c->device);
+        step_rhs(c, t, xyz, phi, dxyz, dphi, q, H);
     });
 }
 

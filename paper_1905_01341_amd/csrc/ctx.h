@@ -3,6 +3,7 @@
 
 #include <vector>
 
+#include "../../include/bfm_step.h"
 #include "common.h"
 #include "fmm.h"
 #include "prof.h"
@@ -13,11 +14,13 @@ namespace bfm {
 // vertices (G, column-major [nd x nc]) and their weighted least-squares
 // projector (Gp, column-major [nc x nd]).
 struct ShBasis {
-    int nmax = -1, nc = 0, nd = 0;
+    int nmax = -1, nc = 0, nd = 0, weighted = 1;
+    uint64_t gen = 0;  // template generation the basis was built for
     DevBuf<double> G, Gp;
 };
 struct Precond {
     int nd = 0, nc = 0, nmax = -1;
+    uint64_t gen = 1;  // bumped whenever the template changes (invalidates every ShBasis)
     double cc = 0.0;
     bool ready = false;
     std::vector<double> dirs_h;  // template directions [nd][3]
@@ -30,7 +33,8 @@ struct Precond {
     DevBuf<double> Ainv, gj_row, gj_col, gj_piv;  // inverse coarse matrix [nb x nb] and Gauss-Jordan work
     DevBuf<double> csum, cy;           // per-bubble sums [3][nb], coarse correction [nb]
 };
-struct Mlp;  // learned initial guess (learn.hip)
+struct Mlp;      // learned initial guess (learn.hip)
+struct Stepper;  // time-step harness (step.hip)
 }  // namespace bfm
 
 struct bfm_ctx {
@@ -68,7 +72,9 @@ struct bfm_ctx {
     bfm::Precond pre;
     std::vector<int> tri0_h;  // first bubble's triangles (local indices), kept for templates
 
-    bfm::Mlp *mlp = nullptr;  // learned initial guess, created on first use
+    bfm::Mlp *mlp = nullptr;          // learned initial guess, created on first use
+    bfm::Stepper *stepper = nullptr;  // time-step harness, created on first use
+    std::vector<int> tri_h;           // triangles (host copy, for the harness's one-rings)
 
     // GMRES workspace (sorted order)
     bfm::DevBuf<double> V, work, x_s, part, small, zbuf, tbuf;
@@ -94,7 +100,8 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
 void gmres_sorted(bfm_ctx *c, double *x_s, bool use_guess, bfm_solve_info *info);
 
 // Spherical-harmonic preconditioner (precond.hip)
-void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st);
+// weighted: G+ = (G^T W G)^{-1} G^T W with W the template vertex areas; else plain least squares
+void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st, bool weighted = true);
 void precond_build(bfm_ctx *c);
 void precond_radii(bfm_ctx *c);
 void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);
@@ -106,6 +113,20 @@ void spd_inverse(double *A, int n, DevBuf<double> &piv, DevBuf<double> &row, Dev
 // C = A B, column-major FP64 (precond.hip)
 void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                  hipStream_t st);
+
+// the solve of bfm_solve_dev: tree, diagonals and b, optional guess, GMRES
+// (guess: BFM_GUESS_*); throws BFM_ENOCONV when GMRES stops at gmres_maxit
+void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm_solve_info *info);
+
+// time-step harness (step.hip)
+void step_free(bfm_ctx *c);
+void step_mesh_changed(bfm_ctx *c);
+void step_set_physics(bfm_ctx *c, const bfm_physics &ph);
+void step_state_set(bfm_ctx *c, const double *xyz_h, const double *phi_h, double t);
+void step_state_get(bfm_ctx *c, double *xyz_h, double *phi_h, double *t);
+void step_advance(bfm_ctx *c, double dt, bfm_step_info *info);
+void step_rhs(bfm_ctx *c, double t, const double *xyz_h, const double *phi_h, double *dxyz, double *dphi, double *q,
+              double *H);
 
 // gather (original -> sorted) and scatter (sorted -> original)
 void to_sorted(bfm_ctx *c, const double *in_orig, double *out_s);

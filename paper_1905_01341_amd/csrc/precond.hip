@@ -85,16 +85,17 @@ static void cholesky_solve(int n, std::vector<double> &S, std::vector<double> &B
     }
 }
 
-void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st) {
+void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st, bool weighted) {
     const int nd = P.nd;
     BFM_CHECK(nd > 0 && !P.dirs_h.empty(), BFM_EINVAL, "no sphere template set");
-    BFM_CHECK(nmax >= 1 && (nmax + 1) * (nmax + 1) <= nd, BFM_EINVAL,
+    BFM_CHECK(nmax >= 0 && (nmax + 1) * (nmax + 1) <= nd, BFM_EINVAL,
               "harmonic degree must satisfy (degree + 1)^2 <= vertices per bubble");
-    if (B.nmax == nmax && B.nd == nd) return;
+    if (B.nmax == nmax && B.nd == nd && B.weighted == (int)weighted && B.gen == P.gen) return;
     const int nc = (nmax + 1) * (nmax + 1);
-    // template vertex areas from the first bubble's triangles on the unit directions
-    std::vector<double> wv(nd, 0.0);
-    for (size_t k = 0; k + 2 < P.tri_h.size(); k += 3) {
+    // weights: template vertex areas from the first bubble's triangles on the
+    // unit directions, or all ones (plain least squares)
+    std::vector<double> wv(nd, weighted ? 0.0 : 1.0);
+    for (size_t k = 0; weighted && k + 2 < P.tri_h.size(); k += 3) {
         const double *a = &P.dirs_h[3 * P.tri_h[k]], *b = &P.dirs_h[3 * P.tri_h[k + 1]],
                      *d = &P.dirs_h[3 * P.tri_h[k + 2]];
         const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
@@ -132,6 +133,8 @@ void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st) {
     B.nmax = nmax;
     B.nc = nc;
     B.nd = nd;
+    B.weighted = (int)weighted;
+    B.gen = P.gen;
 }
 
 void precond_build(bfm_ctx *c) {
