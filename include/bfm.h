@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BFM_ABI_VERSION 2
+#define BFM_ABI_VERSION 3
 
 enum {
     BFM_OK = 0,
@@ -95,6 +95,10 @@ typedef struct bfm_options {
     int gmres_maxit;   /* total iteration limit */
     int precond;       /* BFM_PRECOND_* */
     int precond_degree; /* highest harmonic degree resolved by BFM_PRECOND_SH, (d+1)^2 <= nd */
+    int use_graph;     /* != 0: GMRES replays each product (preconditioner + fast multipole
+                          product) from one captured HIP graph per octree */
+    int m2l_shape;     /* M2L launch shape: -1 = by size, 0 = wide tiles, 1 = row slabs,
+                          2 = narrow slabs (set by bfm_autotune) */
 } bfm_options;
 
 typedef struct bfm_solve_info {
@@ -113,7 +117,7 @@ typedef struct bfm_ctx bfm_ctx;
 
 /* Fill *opt with defaults: p = 16, p_diag = 0, lmax = 0, leaf_target = 64,
  * FP64, tol 1e-10, restart 30, maxit 300, device 0, stream NULL, no
- * preconditioner (precond_degree 12). */
+ * preconditioner (precond_degree 12), no graph, M2L shape by size. */
 int bfm_default_options(bfm_options *opt);
 
 /* Create a handle on opt->device. The handle owns every device buffer
@@ -199,6 +203,22 @@ int bfm_matvec(bfm_ctx *ctx, double f, const double *x, double g, const double *
 int bfm_solve(bfm_ctx *ctx, const double *phi, double *q, int use_guess, bfm_solve_info *info);
 int bfm_solve_dev(bfm_ctx *ctx, const double *phi_dev, double *q_dev, int use_guess,
                   bfm_solve_info *info);
+
+/* Autotuning of the fast multipole product for the current mesh (not in the
+ * paper, which tunes the octree depth by hand, Section 4): p = the smallest
+ * of 8, 12, 16, 20 whose product with a fixed pseudo-random vector is within
+ * mvp_tol (relative 2-norm) of the p = 20 product (p = 20 if none); then
+ * the octree depth (the depth chosen from leaf_target and one level either
+ * side) and the M2L launch shape that give the fastest product, timed with
+ * HIP events after a warm-up. The choice is stored in the handle's options
+ * (p, lmax, m2l_shape; p_diag is left as set). out may be NULL. */
+typedef struct bfm_tune_result {
+    int p, lmax, m2l_shape; /* chosen */
+    int candidates;         /* configurations timed */
+    double mvp_ms;          /* time of one product with the chosen configuration */
+    double p_err;           /* relative difference of the chosen p's product from p = 20 */
+} bfm_tune_result;
+int bfm_autotune(bfm_ctx *ctx, double mvp_tol, bfm_tune_result *out);
 
 /* Octree statistics of the current mesh (builds the tree if needed):
  * stats[0] = lmax, [1] = leaves, [2] = boxes (all levels), [3] = near-field

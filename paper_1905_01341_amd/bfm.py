@@ -24,7 +24,7 @@ PRECOND_SH_COARSE = 2
 GUESS_ZERO = 0
 GUESS_GIVEN = 1
 GUESS_LEARNED = 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 MLP_INPUTS = 174
 MLP_OUTPUTS = 81
 MLP_NUM_PARAMS = 656465
@@ -52,6 +52,20 @@ class Physics(ctypes.Structure):
         ("guess", ctypes.c_int),
         ("collect", ctypes.c_int),
     ]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int),
+        ("lmax", ctypes.c_int),
+        ("m2l_shape", ctypes.c_int),
+        ("candidates", ctypes.c_int),
+        ("mvp_ms", ctypes.c_double),
+        ("p_err", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class StepInfo(ctypes.Structure):
@@ -82,6 +96,8 @@ class Options(ctypes.Structure):
         ("gmres_maxit", ctypes.c_int),
         ("precond", ctypes.c_int),
         ("precond_degree", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
+        ("m2l_shape", ctypes.c_int),
     ]
 
 
@@ -148,6 +164,7 @@ def load(path: str = LIB_PATH):
         "bfm_debug_spd_inverse": ([I, I, P, P], I),
         "bfm_profile": ([P, I], I),
         "bfm_profile_read": ([P, P, P, P], I),
+        "bfm_autotune": ([P, D, ctypes.POINTER(TuneResult)], I),
         "bfm_default_physics": ([ctypes.POINTER(Physics)], I),
         "bfm_set_physics": ([P, ctypes.POINTER(Physics)], I),
         "bfm_state_set": ([P, P, P, D], I),
@@ -341,6 +358,12 @@ class Solver:
         _check(self.lib.bfm_profile_read(self.h, _ptr(ms), _ptr(n), _ptr(fl)))
         return {k: dict(ms=float(ms[i]), launches=int(n[i]), flops=float(fl[i]))
                 for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    def autotune(self, mvp_tol=1e-7):
+        r = TuneResult()
+        _check(self.lib.bfm_autotune(self.h, float(mvp_tol), ctypes.byref(r)))
+        self.opt.p, self.opt.lmax, self.opt.m2l_shape = r.p, r.lmax, r.m2l_shape
+        return r.as_dict()
 
     def tree_stats(self):
         st = (ctypes.c_int64 * 8)()

@@ -54,6 +54,7 @@ static void check_options(const bfm_options &o) {
     BFM_CHECK(o.precond == BFM_PRECOND_NONE || o.precond == BFM_PRECOND_SH || o.precond == BFM_PRECOND_SH_COARSE,
               BFM_EINVAL, "unknown precond");
     BFM_CHECK(o.precond_degree >= 1 && o.precond_degree <= 40, BFM_EINVAL, "precond_degree must be in [1, 40]");
+    BFM_CHECK(o.m2l_shape >= -1 && o.m2l_shape <= 2, BFM_EINVAL, "m2l_shape must be -1, 0, 1 or 2");
 }
 
 struct DeviceScope {
@@ -153,6 +154,8 @@ int bfm_default_options(bfm_options *opt) {
     opt->gmres_maxit = 300;
     opt->precond = BFM_PRECOND_NONE;
     opt->precond_degree = 12;
+    opt->use_graph = 0;
+    opt->m2l_shape = -1;
     return BFM_OK;
 }
 
@@ -189,6 +192,7 @@ int bfm_destroy(bfm_ctx *c) {
         (void)hipStreamSynchronize(c->stream);
         mlp_free(c);
         step_free(c);
+        graph_invalidate(c);
         if (c->host_small) (void)hipHostFree(c->host_small);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
@@ -210,6 +214,7 @@ int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
             c->diag_valid = false;
         }
         if (p_change) c->diag_valid = false;
+        graph_invalidate(c);
         if (opt->precond_degree != c->pre.nmax) c->pre.ready = false;
     });
 }
@@ -733,6 +738,18 @@ int bfm_rhs(bfm_ctx *c, double t, const double *xyz, const double *phi, double *
         BFM_CHECK(c && xyz && phi, BFM_EINVAL, "null argument");
         DeviceScope ds(c->device);
         step_rhs(c, t, xyz, phi, dxyz, dphi, q, H);
+    });
+}
+
+int bfm_autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
+    return guarded([&] {
+        BFM_CHECK(c, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        BFM_CHECK(mvp_tol > 0.0, BFM_EINVAL, "mvp_tol must be positive");
+        DeviceScope ds(c->device);
+        bfm_tune_result r{};
+        autotune(c, mvp_tol, &r);
+        if (out) *out = r;
     });
 }
 

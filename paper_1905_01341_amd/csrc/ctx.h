@@ -34,7 +34,13 @@ struct Precond {
     DevBuf<double> csum, cy;           // per-bubble sums [3][nb], coarse correction [nb]
 };
 struct Mlp;      // learned initial guess (learn.hip)
-struct Stepper;  // time-step harness (step.hip)
+struct Stepper;  // captured product (tune.hip)
+void graph_invalidate(bfm_ctx *c);
+// out_s = A P^{-1} in_s (pc) or A in_s through the captured graph; captures on first use
+void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc);
+void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out);
+
+// time-step harness (step.hip)
 }  // namespace bfm
 
 struct bfm_ctx {
@@ -75,6 +81,12 @@ struct bfm_ctx {
     bfm::Mlp *mlp = nullptr;          // learned initial guess, created on first use
     bfm::Stepper *stepper = nullptr;  // time-step harness, created on first use
     std::vector<int> tri_h;           // triangles (host copy, for the harness's one-rings)
+
+    // captured product of the GMRES iteration (use_graph): preconditioner and
+    // fast multipole product from gin to gout, valid for one octree
+    hipGraphExec_t mvp_graph = nullptr;
+    int mvp_graph_pc = -1;                 // preconditioner the graph was captured with
+    bfm::DevBuf<double> gin, gout;
 
     // GMRES workspace (sorted order)
     bfm::DevBuf<double> V, work, x_s, part, small, zbuf, tbuf;
@@ -117,6 +129,12 @@ void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B,
 // the solve of bfm_solve_dev: tree, diagonals and b, optional guess, GMRES
 // (guess: BFM_GUESS_*); throws BFM_ENOCONV when GMRES stops at gmres_maxit
 void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm_solve_info *info);
+
+// captured product (tune.hip)
+void graph_invalidate(bfm_ctx *c);
+// out_s = A P^{-1} in_s (pc) or A in_s through the captured graph; captures on first use
+void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc);
+void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out);
 
 // time-step harness (step.hip)
 void step_free(bfm_ctx *c);

@@ -26,6 +26,7 @@ struct FmmWork {
     DevBuf<double> mexp, lexp;      // [nbox][nch][P]
     DevBuf<double> ops_m2m, ops_l2l, ops_m2l;  // operators, column-major per op: [op][k][row]
     int ops_p = 0;
+    int m2l_shape = -1;    // M2L launch shape (-1: chosen by size)
     Prof *prof = nullptr;  // optional kernel timing
 };
 

@@ -603,7 +603,8 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
     // tiles, fewest operator re-reads) when there are many columns, row slabs
     // (more waves, columns re-read per slab) when there are few.
     const int64_t wave_tiles = (cols + 15) / 16;
-    const int shape = (wave_tiles >= 8192) ? 0 : (wave_tiles * (PP / mid_rows(PP)) >= 8192 ? 1 : 2);
+    int shape = (wave_tiles >= 8192) ? 0 : (wave_tiles * (PP / mid_rows(PP)) >= 8192 ? 1 : 2);
+    if (cls == KC_M2L && w.m2l_shape >= 0) shape = w.m2l_shape;
     const int width = (shape == 0) ? 128 : 64;
     prepare_tiles(tl, nch, width, st);
     const int nt = tl.ntiles_for(nch, width);

@@ -1,0 +1,204 @@
+// Graph capture of the GMRES product and autotuning of the fast multipole
+// product (include/bfm.h: use_graph, m2l_shape, bfm_autotune).
+//
+// The product inside GMRES (right preconditioner, then the fast multipole
+// product with the diagonal) launches a few dozen kernels whose arguments
+// are fixed for one octree. It is captured once per octree into a HIP graph
+// that reads a fixed input buffer and writes a fixed output buffer; each
+// GMRES step copies its Krylov vector in and the product out with plain
+// kernels (no memset or memcpy nodes in the graph).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ctx.h"
+
+namespace bfm {
+
+static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+__global__ void k_copy_vec(const double *in, int64_t n, double *out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+static void copy_vec(const double *in, int64_t n, double *out, hipStream_t st) {
+    k_copy_vec<<<nblk(n, 256), 256, 0, st>>>(in, n, out);
+    BFM_LAUNCHED();
+}
+
+void graph_invalidate(bfm_ctx *c) {
+    if (c->mvp_graph) (void)hipGraphExecDestroy(c->mvp_graph);
+    c->mvp_graph = nullptr;
+    c->mvp_graph_pc = -1;
+}
+
+// gout = A P^{-1} gin (pc) or A gin
+static void mvp_body(bfm_ctx *c, bool pc) {
+    if (pc) {
+        double *Z = c->zbuf.ensure(c->nv);
+        precond_apply(c, c->gin.get(), Z);
+        matvec_sorted(c, 1.0, Z, 0.0, nullptr, c->gout.get(), true, c->opt.precision, false);
+    } else {
+        matvec_sorted(c, 1.0, c->gin.get(), 0.0, nullptr, c->gout.get(), true, c->opt.precision, false);
+    }
+}
+
+void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nv;
+    c->gin.ensure(n);
+    c->gout.ensure(n);
+    copy_vec(in_s, n, c->gin.get(), st);
+    if (c->mvp_graph && c->mvp_graph_pc == (int)pc) {
+        BFM_HIP(hipGraphLaunch(c->mvp_graph, st));
+        copy_vec(c->gout.get(), n, out_s, st);
+        return;
+    }
+    graph_invalidate(c);
+    // eager run first: every lazy preparation (tiles, buffers, operators)
+    // happens here, outside the capture, and its result is this call's product
+    mvp_body(c, pc);
+    copy_vec(c->gout.get(), n, out_s, st);
+    BFM_HIP(hipStreamSynchronize(st));
+    hipGraph_t g = nullptr;
+    BFM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+        mvp_body(c, pc);
+    } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(st, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        throw;
+    }
+    BFM_HIP(hipStreamEndCapture(st, &g));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BFM_CHECK(e == hipSuccess, BFM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    c->mvp_graph = ge;
+    c->mvp_graph_pc = (int)pc;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning
+
+static double norm2_host(const double *d, int64_t n, hipStream_t st) {
+    std::vector<double> h(n);
+    BFM_HIP(hipMemcpyAsync(h.data(), d, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : h) s += v * v;
+    return std::sqrt(s);
+}
+
+static double diff_host(const double *a, const double *b, int64_t n, hipStream_t st) {
+    std::vector<double> ha(n), hb(n);
+    BFM_HIP(hipMemcpyAsync(ha.data(), a, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipMemcpyAsync(hb.data(), b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (ha[i] - hb[i]) * (ha[i] - hb[i]);
+    return std::sqrt(s);
+}
+
+static double time_mvp(bfm_ctx *c, const double *x, double *y, int reps) {
+    hipStream_t st = c->stream;
+    matvec_sorted(c, 1.0, x, 0.0, nullptr, y, false, BFM_PREC_FP64, false);  // warm-up
+    hipEvent_t a, b;
+    BFM_HIP(hipEventCreate(&a));
+    BFM_HIP(hipEventCreate(&b));
+    BFM_HIP(hipEventRecord(a, st));
+    for (int r = 0; r < reps; ++r) matvec_sorted(c, 1.0, x, 0.0, nullptr, y, false, BFM_PREC_FP64, false);
+    BFM_HIP(hipEventRecord(b, st));
+    BFM_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    BFM_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
+    hipStream_t st = c->stream;
+    const int64_t n = c->nv;
+    const bfm_options saved = c->opt;
+    graph_invalidate(c);
+    // fixed pseudo-random input (sorted order; any vector serves)
+    std::vector<double> xh(n);
+    uint64_t state = 0x9e3779b97f4a7c15ull;
+    for (int64_t i = 0; i < n; ++i) {
+        state = state * 6364136223846793005ull + 1442695040888963407ull;
+        xh[i] = (double)(state >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    DevBuf<double> x, yref, y;
+    x.ensure(n);
+    yref.ensure(n);
+    y.ensure(n);
+    BFM_HIP(hipMemcpyAsync(x.get(), xh.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    try {
+        // 1. expansion order: smallest p within mvp_tol of p = 20
+        c->opt.m2l_shape = -1;
+        ensure_tree(c);
+        const int auto_lmax = c->opt.lmax > 0 ? c->opt.lmax : c->tree.lmax;
+        c->opt.p = 20;
+        ensure_ops(c);
+        matvec_sorted(c, 1.0, x.get(), 0.0, nullptr, yref.get(), false, BFM_PREC_FP64, false);
+        const double nref = norm2_host(yref.get(), n, st);
+        int best_p = 20;
+        double best_err = 0.0;
+        for (int p : {16, 12, 8}) {
+            c->opt.p = p;
+            ensure_ops(c);
+            matvec_sorted(c, 1.0, x.get(), 0.0, nullptr, y.get(), false, BFM_PREC_FP64, false);
+            const double err = diff_host(y.get(), yref.get(), n, st) / nref;
+            if (err > mvp_tol) break;
+            best_p = p;
+            best_err = err;
+        }
+        c->opt.p = best_p;
+        ensure_ops(c);
+        // 2. octree depth and M2L launch shape: fastest product
+        double best_ms = 1e300;
+        int best_l = auto_lmax, best_s = -1, cand = 0;
+        for (int l = std::max(2, auto_lmax - 1); l <= std::min(15, auto_lmax + 1); ++l) {
+            c->opt.lmax = l;
+            c->tree_valid = false;
+            ensure_tree(c);
+            for (int shape = 0; shape <= 2; ++shape) {
+                c->opt.m2l_shape = shape;
+                ensure_ops(c);
+                const double ms = time_mvp(c, x.get(), y.get(), 3);
+                ++cand;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_l = l;
+                    best_s = shape;
+                }
+            }
+        }
+        c->opt = saved;
+        c->opt.p = best_p;
+        c->opt.lmax = best_l;
+        c->opt.m2l_shape = best_s;
+        c->tree_valid = false;
+        c->diag_valid = false;
+        graph_invalidate(c);
+        if (out) {
+            out->p = best_p;
+            out->lmax = best_l;
+            out->m2l_shape = best_s;
+            out->candidates = cand;
+            out->mvp_ms = best_ms;
+            out->p_err = best_err;
+        }
+    } catch (...) {
+        c->opt = saved;
+        c->tree_valid = false;
+        c->diag_valid = false;
+        graph_invalidate(c);
+        throw;
+    }
+}
+
+}  // namespace bfm
