@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--graph", type=int, default=0, help="tuned form: replay GMRES products from a HIP graph")
     ap.add_argument("--autotune", type=int, default=1, help="tuned form: autotune p, octree depth, M2L shape")
     ap.add_argument("--tune-tol", type=float, default=1e-7)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed region, copy a buffer of this many MiB once (reference "
+                         "dispatch for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -89,6 +92,12 @@ def main():
 
     cl, phi = wl.make(a.workload)
     dev = torch.device("cuda:0")
+    if a.calib_copy_mib > 0:
+        src = torch.ones(a.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     xyz_t = torch.tensor(cl.xyz, dtype=torch.float64, device=dev).contiguous()
     phi_t = torch.tensor(phi, dtype=torch.float64, device=dev).contiguous()
     q_t = torch.zeros_like(phi_t)

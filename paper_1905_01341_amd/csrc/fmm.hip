@@ -265,6 +265,7 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t leaf0, const int *pt_leaf, 
 // small (coarse octree levels). KIND only separates the kernel symbols of
 // M2L (0) and M2M/L2L (1) for profilers.
 constexpr int kTKC = 16;
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
 template <int PP, int ROWS, int WAVES, int KIND>
 __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *tile_off, int ntiles,
@@ -275,7 +276,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     static_assert(PP % ROWS == 0 && ROWS % 16 == 0, "row slab");
     constexpr int NSLAB = PP / ROWS;
     __shared__ double As[2][kTKC * ROWS];  // two buffers of [k][row within slab]
-    const int g = blockIdx.x / NSLAB, slab = blockIdx.x % NSLAB;
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so
+    // XCD x takes a contiguous run of logical blocks (the tiles of a few
+    // operators) and fetches each operator into its own L2 once
+    const int nblock = gridDim.x, per = nblock / kXcds, rem = nblock % kXcds;
+    const int xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
+    const int logical = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    const int g = logical / NSLAB, slab = logical % NSLAB;
     if (g >= ntiles) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int lo = 0, hi = nops;
@@ -325,14 +332,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     };
     fetch(0);
     stash(As[0]);
+    // the wave's input columns are prefetched one chunk ahead as well
+    double bv[kTKC / 4], bn[kTKC / 4];
+#pragma unroll
+    for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bok ? bcol[4 * kk + kq] : 0.0;
     __syncthreads();
     int cur = 0;
     for (int k0 = 0; k0 < PP; k0 += kTKC) {
         const bool more = k0 + kTKC < PP;
-        if (more) fetch(k0 + kTKC);
-        double bv[kTKC / 4];
+        if (more) {
+            fetch(k0 + kTKC);
 #pragma unroll
-        for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bok ? bcol[k0 + 4 * kk + kq] : 0.0;
+            for (int kk = 0; kk < kTKC / 4; ++kk) bn[kk] = bok ? bcol[k0 + kTKC + 4 * kk + kq] : 0.0;
+        }
 #pragma unroll
         for (int kk = 0; kk < kTKC / 4; ++kk) {
             const double *Ak = As[cur] + (4 * kk + kq) * ROWS + rl;
@@ -344,6 +356,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
             stash(As[cur ^ 1]);
             __syncthreads();
             cur ^= 1;
+#pragma unroll
+            for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bn[kk];
         }
     }
 #pragma unroll
