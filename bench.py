@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--graph", type=int, default=0, help="tuned form: replay GMRES products from a HIP graph")
     ap.add_argument("--autotune", type=int, default=1, help="tuned form: autotune p, octree depth, M2L shape")
     ap.add_argument("--tune-tol", type=float, default=1e-7)
+    ap.add_argument("--learned-steps", type=int, default=0,
+                    help="run the learned-guess study instead: this many time steps collect training "
+                         "pairs, then the same number of steps are run with zero, previous-step and "
+                         "learned initial guesses")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, copy a buffer of this many MiB once (reference "
                          "dispatch for hardware byte counters)")
@@ -80,12 +84,61 @@ def cpu_baseline(cl, phi, matvecs, rows_n):
     }
 
 
+def learned_study(a):
+    """Time-stepped cluster (the 1000-bubble cluster, phi = 0 at rest,
+    p_inf = 1 + 0.5 sin(2 pi t / 5), surface tension 0.073, kappa 1.4, shape
+    filter p_f = 9, dt = 0.1 min edge (rho / P_a)^(1/2)): the first
+    `learned_steps` steps collect (features, targets) of every solve and the
+    network is trained on them; then the same number of steps is run from
+    that state three times, starting GMRES from zero, from the previous
+    solve's q, and from the learned guess. Prints one JSON line."""
+    import torch
+    from paper_1905_01341_amd import bfm
+    from paper_1905_01341_amd import workload as wl
+    cl, _ = wl.make(a.workload)
+    t0 = time.perf_counter()
+    edges = np.concatenate([np.linalg.norm(cl.xyz[cl.tri[:, i]] - cl.xyz[cl.tri[:, (i + 1) % 3]], axis=1)
+                            for i in range(3)])
+    dt = 0.1 * float(edges.min()) * (1.0 / 0.5) ** 0.5
+    sv = bfm.Solver(device=0, p=a.p, leaf_target=a.leaf, gmres_tol=a.tol, gmres_restart=a.restart,
+                    gmres_maxit=1000, precond=bfm.PRECOND_SH_COARSE, precond_degree=a.precond_degree)
+    sv.set_cluster(cl)
+    phys = dict(sigma=0.073, kappa=1.4, p0=1.0, pa=0.5, period=5.0, forcing_sign=1.0, filter_degree=9)
+    sv.set_physics(guess=bfm.GUESS_GIVEN, collect=1, **phys)
+    sv.state_set(cl.xyz, np.zeros(cl.nv), 0.0)
+    train = []
+    for _ in range(a.learned_steps):
+        train.append(sv.step(dt))
+    xyz, phi, t = sv.state_get()
+    rows = sv.mlp_dataset()
+    torch.cuda.synchronize()
+    tf = time.perf_counter()
+    loss1 = sv.mlp_fit(1, batch=256, lr=1e-3, seed=1)
+    loss = sv.mlp_fit(30, batch=256, lr=1e-3, seed=2)
+    t_fit = time.perf_counter() - tf
+    runs = {}
+    for name, guess in (("zero", bfm.GUESS_ZERO), ("previous", bfm.GUESS_GIVEN), ("learned", bfm.GUESS_LEARNED)):
+        sv.set_physics(guess=guess, collect=0, **phys)
+        sv.state_set(xyz, phi, t)
+        infos = [sv.step(dt) for _ in range(a.learned_steps)]
+        solves = sum(i["solves"] for i in infos)
+        runs[name] = {"iterations_per_solve": round(sum(i["iterations"] for i in infos) / solves, 3),
+                      "ms_per_step": round(sum(i["ms"] for i in infos) / len(infos), 3), "solves": solves}
+    out = {"study": "learned initial guess", "workload": f"{a.workload} time-stepped, dt={dt:.5f}",
+           "train_steps": a.learned_steps, "train_rows": rows, "fit_seconds": round(t_fit, 3),
+           "loss_first_epoch": loss1, "loss_last_epoch": loss, "eval_steps": a.learned_steps,
+           "runs": runs, "seconds": round(time.perf_counter() - t0, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
               f"(asked for --gpus {a.gpus})", file=sys.stderr)
         sys.exit(2)
+    if a.learned_steps > 0:
+        return learned_study(a)
     import torch
     from paper_1905_01341_amd import bfm
     from paper_1905_01341_amd import workload as wl
