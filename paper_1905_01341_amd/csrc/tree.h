@@ -72,6 +72,18 @@ struct Tree {
 
     TaskList m2l;                   // all levels 2..lmax
     std::vector<TaskList *> m2m;    // per level l = 3..lmax: child (level l) -> parent
+
+    // build scratch, kept between builds so that a rebuild allocates nothing
+    // once the sizes have been seen
+    struct Scratch {
+        DevBuf<unsigned long long> cnt, np;
+        DevBuf<int> mo, flag, pos, tmp, icnt, ioff, iidx, iidx2, count, offs, ts, td, to, hist;
+        DevBuf<int> rs_hist, rs_scanned, rs_tmp;
+        DevBuf<uint64_t> ikey, ikey2;
+        DevBuf<int2> raw;
+        DevBuf<double> bbox;
+    } scratch;
+
     ~Tree() {
         for (auto *t : m2m) delete t;
     }
@@ -91,7 +103,7 @@ void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st);
 
 // Stable LSD radix sort of (u64 key, int value) on the low `bits` bits of the
 // key; results end in (keys, vals) (the *_tmp buffers are scratch of size n).
-void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits,
+void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits, Tree::Scratch &scr,
                 hipStream_t st);
 
 // Device-wide exclusive scan of int32 (in place allowed); returns the total.

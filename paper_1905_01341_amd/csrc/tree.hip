@@ -17,6 +17,20 @@
 
 namespace bfm {
 
+static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// fill with a value (a kernel rather than a memset, so that the same code can
+// be replayed from a captured graph)
+__global__ void k_fill_int(int *p, int64_t n, int v) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+
 // ---------------------------------------------------------------------------
 // Morton keys
 
@@ -178,11 +192,11 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, 
     }
 }
 
-void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits,
+void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits, Tree::Scratch &scr,
                 hipStream_t st) {
     if (n <= 1) return;
     const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
-    DevBuf<int> hist, scanned, tmp;
+    DevBuf<int> &hist = scr.rs_hist, &scanned = scr.rs_scanned, &tmp = scr.rs_tmp;
     hist.ensure((size_t)256 * nblocks);
     scanned.ensure((size_t)256 * nblocks);
     uint64_t *kin = keys, *kout = keys_tmp;
@@ -543,8 +557,26 @@ __global__ void k_op_group(const int *top, const int *src, const int *dst, int64
     }
 }
 
+__global__ void k_op_keys(const int *top, int64_t n, uint64_t *key, int *idx) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = (uint64_t)top[i];
+    idx[i] = (int)i;
+}
+
+__global__ void k_op_gather(const int *order, const int *src, const int *dst, int64_t n, int *osrc, int *odst) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int i = order[r];
+    osrc[r] = src[i];
+    odst[r] = dst[i];
+}
+
+// Group tasks by operator, keeping the input order within each group: a
+// per-operator scan for a few operators, a stable radix sort on the operator
+// index for many.
 static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst, const int *top,
-                        int64_t n, hipStream_t st) {
+                        int64_t n, Tree::Scratch &scr, hipStream_t st) {
     tl.nops = nops;
     tl.ntasks = n;
     tl.op_off_h.assign(nops + 1, 0);
@@ -553,9 +585,10 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
         tl.ntiles[c] = 0;
         tl.tiles_ready[c] = false;
     }
-    DevBuf<int> hist;
+    DevBuf<int> &hist = scr.hist;
     hist.ensure(nops);
-    BFM_HIP(hipMemsetAsync(hist.get(), 0, sizeof(int) * nops, st));
+    k_fill_int<<<nblk(nops, 256), 256, 0, st>>>(hist.get(), nops, 0);
+    BFM_LAUNCHED();
     if (n > 0) {
         k_op_hist<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(top, n, hist.get());
         BFM_LAUNCHED();
@@ -568,12 +601,20 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
                            hipMemcpyHostToDevice, st));
     tl.src.ensure(n > 0 ? n : 1);
     tl.dst.ensure(n > 0 ? n : 1);
-    if (n > 0) {
-        k_op_group<<<nops, 64, 0, st>>>(top, tsrc, tdst, n, tl.op_off.get(), tl.src.get(),
-                                        tl.dst.get());
+    if (n > 0 && nops <= 16) {
+        k_op_group<<<nops, 64, 0, st>>>(top, tsrc, tdst, n, tl.op_off.get(), tl.src.get(), tl.dst.get());
+        BFM_LAUNCHED();
+    } else if (n > 0) {
+        uint64_t *k0 = scr.ikey.ensure(n), *k1 = scr.ikey2.ensure(n);
+        int *i0 = scr.iidx.ensure(n), *i1 = scr.iidx2.ensure(n);
+        k_op_keys<<<nblk(n, 256), 256, 0, st>>>(top, n, k0, i0);
+        BFM_LAUNCHED();
+        int bits = 1;
+        while ((1 << bits) < nops) ++bits;
+        radix_sort(k0, i0, k1, i1, n, bits, scr, st);
+        k_op_gather<<<nblk(n, 256), 256, 0, st>>>(i0, tsrc, tdst, n, tl.src.get(), tl.dst.get());
         BFM_LAUNCHED();
     }
-    BFM_HIP(hipStreamSynchronize(st));
 }
 
 void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st) {
@@ -620,7 +661,6 @@ __global__ void k_sort_geom(const double *s, const double *nrm, const int *perm,
     pnz[i] = nrm[2 * n + o];
 }
 
-static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target, hipStream_t st) {
     BFM_CHECK(n >= 1, BFM_EINVAL, "tree of no points");
@@ -628,7 +668,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     t.n = n;
     // bounding cube
     const int nbb = 256;
-    DevBuf<double> part;
+    DevBuf<double> &part = t.scratch.bbox;
     part.ensure(6 * nbb);
     k_bbox_partial<<<nbb, 256, 0, st>>>(xyz, n, part.get());
     BFM_LAUNCHED();
@@ -659,13 +699,15 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     k_morton<<<nblk(n, 256), 256, 0, st>>>(xyz, n, t.origin[0], t.origin[1], t.origin[2], inv_cell,
                                            t.key_a.get(), t.idx_a.get());
     BFM_LAUNCHED();
-    radix_sort(t.key_a.get(), t.idx_a.get(), t.key_b.get(), t.idx_b.get(), n, 3 * kKeyBits, st);
-    DevBuf<int> tmp;
+    Tree::Scratch &scr = t.scratch;
+    radix_sort(t.key_a.get(), t.idx_a.get(), t.key_b.get(), t.idx_b.get(), n, 3 * kKeyBits, scr, st);
+    DevBuf<int> &tmp = scr.tmp;
 
     // boxes per level
-    DevBuf<unsigned long long> cnt;
+    DevBuf<unsigned long long> &cnt = scr.cnt;
     cnt.ensure(kKeyBits + 1);
-    BFM_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(unsigned long long) * (kKeyBits + 1), st));
+    k_fill_u64<<<1, 64, 0, st>>>(cnt.get(), kKeyBits + 1, 0ull);
+    BFM_LAUNCHED();
     k_level_counts<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, kKeyBits, cnt.get());
     BFM_LAUNCHED();
     std::vector<unsigned long long> ch(kKeyBits + 1);
@@ -694,7 +736,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     t.box_parent.ensure(t.nbox);
     t.box_centre.ensure(3 * t.nbox);
     t.nbr.ensure(27 * t.nbox);
-    DevBuf<int> flag, pos;
+    DevBuf<int> &flag = scr.flag, &pos = scr.pos;
     flag.ensure(n);
     pos.ensure(n);
     for (int l = 0; l <= lmax; ++l) {
@@ -719,12 +761,14 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     BFM_LAUNCHED();
     // leaves
     t.leaf_pt.ensure(t.nleaf + 1);
-    DevBuf<unsigned long long> np;
+    DevBuf<unsigned long long> &np = scr.np;
     np.ensure(1);
-    DevBuf<int> mo;
+    DevBuf<int> &mo = scr.mo;
     mo.ensure(1);
-    BFM_HIP(hipMemsetAsync(np.get(), 0, sizeof(unsigned long long), st));
-    BFM_HIP(hipMemsetAsync(mo.get(), 0, sizeof(int), st));
+    k_fill_u64<<<1, 64, 0, st>>>(np.get(), 1, 0ull);
+    BFM_LAUNCHED();
+    k_fill_int<<<1, 64, 0, st>>>(mo.get(), 1, 0);
+    BFM_LAUNCHED();
     k_leaf_near<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.box_pt0.get(), n,
                                                     t.nbr.get(), t.leaf_pt.get(), np.get(), mo.get());
     BFM_LAUNCHED();
@@ -741,9 +785,9 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                       t.near_rng.get(), t.near_cnt.get());
     BFM_LAUNCHED();
     {
-        DevBuf<int> icnt, ioff, iidx, iidx2;
-        DevBuf<uint64_t> ikey, ikey2;
-        DevBuf<int2> raw;
+        DevBuf<int> &icnt = scr.icnt, &ioff = scr.ioff, &iidx = scr.iidx, &iidx2 = scr.iidx2;
+        DevBuf<uint64_t> &ikey = scr.ikey, &ikey2 = scr.ikey2;
+        DevBuf<int2> &raw = scr.raw;
         icnt.ensure(t.nleaf);
         ioff.ensure(t.nleaf);
         k_item_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), icnt.get());
@@ -757,7 +801,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
         k_item_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.near_rng.get(),
                                                         t.near_cnt.get(), raw.get(), ikey.get(), iidx.get());
         BFM_LAUNCHED();
-        radix_sort(ikey.get(), iidx.get(), ikey2.get(), iidx2.get(), ni, 32, st);
+        radix_sort(ikey.get(), iidx.get(), ikey2.get(), iidx2.get(), ni, 32, scr, st);
         t.p2p_items.ensure(ni);
         k_item_permute<<<nblk(ni, 256), 256, 0, st>>>(raw.get(), iidx.get(), ni, t.p2p_items.get());
         BFM_LAUNCHED();
@@ -767,16 +811,22 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     // M2L lists over levels 2..lmax
     {
         {
-            signed short lut[343];
-            for (int a = -3; a <= 3; ++a)
-                for (int b = -3; b <= 3; ++b)
-                    for (int c = -3; c <= 3; ++c)
-                        lut[(a + 3) * 49 + (b + 3) * 7 + (c + 3)] = (signed short)m2l_op_index(a, b, c);
-            BFM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_m2l_lut), lut, sizeof(lut)));
+            static int lut_done = 0;  // one bit per device ordinal < 32
+            int dev = 0;
+            BFM_HIP(hipGetDevice(&dev));
+            if (dev >= 32 || !((lut_done >> dev) & 1)) {
+                signed short lut[343];
+                for (int a = -3; a <= 3; ++a)
+                    for (int b = -3; b <= 3; ++b)
+                        for (int c = -3; c <= 3; ++c)
+                            lut[(a + 3) * 49 + (b + 3) * 7 + (c + 3)] = (signed short)m2l_op_index(a, b, c);
+                BFM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_m2l_lut), lut, sizeof(lut)));
+                if (dev < 32) lut_done |= 1 << dev;
+            }
         }
         const int64_t b0 = t.lvl_off[2], b1 = t.lvl_off[lmax + 1];
         const int64_t nb = b1 - b0;
-        DevBuf<int> count, offs;
+        DevBuf<int> &count = scr.count, &offs = scr.offs;
         count.ensure(nb);
         offs.ensure(nb);
         k_m2l_pairs<<<nblk(nb, 128), 128, 0, st>>>(0, b0, b1, li, t.box_key.get(), t.box_level.get(),
@@ -784,7 +834,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                    nullptr, nullptr, nullptr, nullptr);
         BFM_LAUNCHED();
         const int64_t total = exclusive_scan(count.get(), offs.get(), nb, st, tmp);
-        DevBuf<int> ts, td, to;
+        DevBuf<int> &ts = scr.ts, &td = scr.td, &to = scr.to;
         ts.ensure(total + 1);
         td.ensure(total + 1);
         to.ensure(total + 1);
@@ -792,23 +842,27 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                    t.box_parent.get(), t.nbr.get(), count.get(),
                                                    offs.get(), ts.get(), td.get(), to.get());
         BFM_LAUNCHED();
-        group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, st);
+        group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, scr, st);
     }
     // M2M / L2L lists: child levels 3..lmax (index l)
-    for (auto *p : t.m2m) delete p;
-    t.m2m.assign(lmax + 1, nullptr);
+    // task lists are reused between builds (their buffers only grow)
+    for (size_t l = lmax + 1; l < t.m2m.size(); ++l) {
+        delete t.m2m[l];
+        t.m2m[l] = nullptr;
+    }
+    t.m2m.resize(lmax + 1, nullptr);
     for (int l = 3; l <= lmax; ++l) {
         const int64_t b0 = t.lvl_off[l], b1 = t.lvl_off[l + 1];
         const int64_t nb = b1 - b0;
-        DevBuf<int> ts, td, to;
+        DevBuf<int> &ts = scr.ts, &td = scr.td, &to = scr.to;
         ts.ensure(nb);
         td.ensure(nb);
         to.ensure(nb);
         k_tree_pairs<<<nblk(nb, 128), 128, 0, st>>>(b0, b1, t.box_key.get(), t.box_parent.get(),
                                                     ts.get(), td.get(), to.get());
         BFM_LAUNCHED();
-        t.m2m[l] = new TaskList();
-        group_tasks(*t.m2m[l], 8, ts.get(), td.get(), to.get(), nb, st);
+        if (!t.m2m[l]) t.m2m[l] = new TaskList();
+        group_tasks(*t.m2m[l], 8, ts.get(), td.get(), to.get(), nb, scr, st);
     }
     // sorted positions
     t.iperm.ensure(n);
