@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--p-diag", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--lmax", type=int, default=0)
-    ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=3000)
