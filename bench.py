@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=3000)
+    ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--form", choices=["tuned", "plain"], default="tuned")
     ap.add_argument("--precond-degree", type=int, default=12)

@@ -209,9 +209,10 @@ int bfm_solve_dev(bfm_ctx *ctx, const double *phi_dev, double *q_dev, int use_gu
  * of 8, 12, 16, 20 whose product with a fixed pseudo-random vector is within
  * mvp_tol (relative 2-norm) of the p = 20 product (p = 20 if none); then
  * the octree depth (the depth chosen from leaf_target and one level either
- * side) and the M2L launch shape that give the fastest product, timed with
- * HIP events after a warm-up. The choice is stored in the handle's options
- * (p, lmax, m2l_shape; p_diag is left as set). out may be NULL. */
+ * side) that minimises one diagonal/right-hand-side pass plus ten products,
+ * and the M2L launch shape with the fastest product at that depth, timed
+ * with HIP events after a warm-up. The choice is stored in the handle's
+ * options (p, lmax, m2l_shape; p_diag is left as set). out may be NULL. */
 typedef struct bfm_tune_result {
     int p, lmax, m2l_shape; /* chosen */
     int candidates;         /* configurations timed */

@@ -386,7 +386,9 @@ constexpr int kP2PThreads = 64;
 // Receivers xi..zi (R per lane) against sources [j0, j1): every lane reads
 // the same source at the same time, so the loads are wave-uniform (scalar
 // loads of read-only data) and no LDS staging is needed.
-template <int NCH, bool MONO, bool DIP, int R>
+// SELF: the sources may include the receiver itself (r = 0, excluded);
+// otherwise every pair is at a positive distance and needs no test.
+template <int NCH, bool MONO, bool DIP, int R, bool SELF>
 __device__ inline void p2p_pair(double sx, double sy, double sz, const double *sq, const double *sw,
                                 double nx, double ny, double nz, const double *xi, const double *yi,
                                 const double *zi, double (*acc)[NCH]) {
@@ -394,7 +396,7 @@ __device__ inline void p2p_pair(double sx, double sy, double sz, const double *s
     for (int k = 0; k < R; ++k) {
         const double dx = xi[k] - sx, dy = yi[k] - sy, dz = zi[k] - sz;
         const double r2 = dx * dx + dy * dy + dz * dz;
-        const double inv = (r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
+        const double inv = (!SELF || r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
         if (MONO) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c) acc[k][c] += sq[c] * inv;
@@ -411,7 +413,7 @@ __device__ inline void p2p_pair(double sx, double sy, double sz, const double *s
 // the same source at the same time, so the loads are wave-uniform (scalar
 // loads of read-only data); sources are fetched in batches of B so one wait
 // covers B sources.
-template <int NCH, bool MONO, bool DIP, int R>
+template <int NCH, bool MONO, bool DIP, int R, bool SELF>
 __device__ inline void p2p_range(int j0, int j1, const double *__restrict__ px,
                                  const double *__restrict__ py, const double *__restrict__ pz,
                                  const double *__restrict__ pnx, const double *__restrict__ pny,
@@ -439,7 +441,7 @@ __device__ inline void p2p_range(int j0, int j1, const double *__restrict__ px,
         }
 #pragma unroll
         for (int u = 0; u < B; ++u)
-            p2p_pair<NCH, MONO, DIP, R>(bx[u], by[u], bz[u], bq[u], bw[u], bnx[u], bny[u], bnz[u], xi, yi, zi,
+            p2p_pair<NCH, MONO, DIP, R, SELF>(bx[u], by[u], bz[u], bq[u], bw[u], bnx[u], bny[u], bnz[u], xi, yi, zi,
                                         acc);
     }
     for (; j < j1; ++j) {
@@ -449,13 +451,13 @@ __device__ inline void p2p_range(int j0, int j1, const double *__restrict__ px,
             sq[c] = MONO ? q[(int64_t)c * n + j] : 0.0;
             sw[c] = DIP ? w[(int64_t)c * n + j] : 0.0;
         }
-        p2p_pair<NCH, MONO, DIP, R>(px[j], py[j], pz[j], sq, sw, DIP ? pnx[j] : 0.0, DIP ? pny[j] : 0.0,
+        p2p_pair<NCH, MONO, DIP, R, SELF>(px[j], py[j], pz[j], sq, sw, DIP ? pnx[j] : 0.0, DIP ? pny[j] : 0.0,
                                     DIP ? pnz[j] : 0.0, xi, yi, zi, acc);
     }
 }
 
 template <int NCH, bool MONO, bool DIP, int R>
-__device__ inline void p2p_pass(int rc, int r1, int nr, const int2 *__restrict__ rng,
+__device__ inline void p2p_pass(int rc, int l0, int r1, int nr, const int2 *__restrict__ rng,
                                 const double *__restrict__ px, const double *__restrict__ py,
                                 const double *__restrict__ pz, const double *__restrict__ pnx,
                                 const double *__restrict__ pny, const double *__restrict__ pnz,
@@ -474,9 +476,18 @@ __device__ inline void p2p_pass(int rc, int r1, int nr, const int2 *__restrict__
 #pragma unroll
         for (int c = 0; c < NCH; ++c) acc[k][c] = 0.0;
     }
+    // only the leaf's own points can coincide with a receiver: the merged
+    // range holding them is split so that the rest runs without the test
     for (int g = 0; g < nr; ++g) {
         const int2 r = rng[g];
-        p2p_range<NCH, MONO, DIP, R>(r.x, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+        const int l1 = r1;  // the leaf's points are [l0, r1)
+        if (r.x <= l0 && l1 <= r.y) {
+            p2p_range<NCH, MONO, DIP, R, false>(r.x, l0, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+            p2p_range<NCH, MONO, DIP, R, true>(l0, l1, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+            p2p_range<NCH, MONO, DIP, R, false>(l1, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+        } else {
+            p2p_range<NCH, MONO, DIP, R, false>(r.x, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+        }
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -506,7 +517,7 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int2 *__restrict__ it
     const int2 it = items[blockIdx.x];
     const int leaf = it.x, rc = it.y;
     const int r1 = leaf_pt[leaf + 1];
-    p2p_pass<NCH, MONO, DIP, 1>(rc, r1, near_cnt[leaf], near_rng + 27 * (int64_t)leaf, px, py, pz, pnx,
+    p2p_pass<NCH, MONO, DIP, 1>(rc, leaf_pt[leaf], r1, near_cnt[leaf], near_rng + 27 * (int64_t)leaf, px, py, pz, pnx,
                                 pny, pnz, n, q, w, y);
 }
 
@@ -532,7 +543,7 @@ __global__ void __launch_bounds__(kP2PThreads) k_direct(const double *__restrict
     yi[0] = ok ? py[i] : 0.0;
     zi[0] = ok ? pz[i] : 0.0;
     for (int c = 0; c < NCH; ++c) acc[0][c] = 0.0;
-    p2p_range<NCH, MONO, DIP, 1>(all.x, all.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+    p2p_range<NCH, MONO, DIP, 1, true>(all.x, all.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
     if (ok)
         for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[0][c];
 }

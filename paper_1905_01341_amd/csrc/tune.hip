@@ -158,23 +158,54 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
         }
         c->opt.p = best_p;
         ensure_ops(c);
-        // 2. octree depth and M2L launch shape: fastest product
-        double best_ms = 1e300;
+        // 2. octree depth and M2L launch shape: the depth minimises one
+        // diagonal/right-hand-side pass plus ten products (a typical solve);
+        // the shape, the product at that depth
+        DevBuf<double> xo;
+        xo.ensure(n);
+        BFM_HIP(hipMemcpyAsync(xo.get(), xh.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+        double best_cost = 1e300, best_ms = 1e300;
         int best_l = auto_lmax, best_s = -1, cand = 0;
+        bool warm = false;
         for (int l = std::max(2, auto_lmax - 1); l <= std::min(15, auto_lmax + 1); ++l) {
             c->opt.lmax = l;
+            c->opt.m2l_shape = -1;
             c->tree_valid = false;
             ensure_tree(c);
+            ensure_ops(c);
+            if (!warm) {  // first pass uploads the diagonal pass's operators
+                diagonal_pass(c, xo.get());
+                warm = true;
+            }
+            hipEvent_t a, b;
+            BFM_HIP(hipEventCreate(&a));
+            BFM_HIP(hipEventCreate(&b));
+            BFM_HIP(hipEventRecord(a, st));
+            diagonal_pass(c, xo.get());
+            BFM_HIP(hipEventRecord(b, st));
+            BFM_HIP(hipEventSynchronize(b));
+            float dms = 0.f;
+            BFM_HIP(hipEventElapsedTime(&dms, a, b));
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            double lvl_ms = 1e300;
+            int lvl_s = -1;
             for (int shape = 0; shape <= 2; ++shape) {
                 c->opt.m2l_shape = shape;
                 ensure_ops(c);
-                const double ms = time_mvp(c, x.get(), y.get(), 3);
+                const double ms = time_mvp(c, x.get(), y.get(), 5);
                 ++cand;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best_l = l;
-                    best_s = shape;
+                if (ms < lvl_ms) {
+                    lvl_ms = ms;
+                    lvl_s = shape;
                 }
+            }
+            const double cost = dms + 10.0 * lvl_ms;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best_ms = lvl_ms;
+                best_l = l;
+                best_s = lvl_s;
             }
         }
         c->opt = saved;
