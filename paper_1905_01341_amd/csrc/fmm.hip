@@ -513,11 +513,12 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int2 *__restrict__ it
                                                      const double *__restrict__ pnz, int64_t n,
                                                      const double *__restrict__ q,
                                                      const double *__restrict__ w, double *__restrict__ y) {
-    static_assert(kP2PChunk == kP2PThreads, "one receiver per lane");
+    constexpr int R = kP2PChunk / kP2PThreads;
+    static_assert(kP2PChunk == R * kP2PThreads, "whole receivers per lane");
     const int2 it = items[blockIdx.x];
     const int leaf = it.x, rc = it.y;
     const int r1 = leaf_pt[leaf + 1];
-    p2p_pass<NCH, MONO, DIP, 1>(rc, leaf_pt[leaf], r1, near_cnt[leaf], near_rng + 27 * (int64_t)leaf, px, py, pz, pnx,
+    p2p_pass<NCH, MONO, DIP, R>(rc, leaf_pt[leaf], r1, near_cnt[leaf], near_rng + 27 * (int64_t)leaf, px, py, pz, pnx,
                                 pny, pnz, n, q, w, y);
 }
 

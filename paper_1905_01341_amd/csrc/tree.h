@@ -11,7 +11,7 @@
 namespace bfm {
 
 constexpr int kKeyBits = 15;  // bits per axis of the point keys (levels 0..15)
-constexpr int kP2PChunk = 64;  // receivers per near-field work item
+constexpr int kP2PChunk = 128;  // receivers per near-field work item (two per lane)
 
 // Translation tasks grouped by operator: tasks op_off[o]..op_off[o+1] use
 // operator o; task t moves expansion src[t] into expansion dst[t] (global
