@@ -14,6 +14,7 @@ the timed region.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FMM-BEM solve s/step at 1.28M tris: tuned vs plain FP64, dphi/dn rel err<=1e-6"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and FP64 matrix (dense)
+# HBM bytes per launch measured with hardware counters (FETCH_SIZE and
+# WRITE_SIZE, scaled by a copy of known size), one line per kernel, workload,
+# octree depth and order; a line counts only while the kernels' sources hash
+# to the value it was measured with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c1000.txt")
+KERNEL_SOURCES = {"p2p": ("fmm_near.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h"),
+                  "m2l": ("fmm.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h")}
 
 
 def parse():
@@ -38,6 +46,7 @@ def parse():
     ap.add_argument("--p-diag", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--lmax", type=int, default=0)
+    ap.add_argument("--m2l-shape", type=int, default=-1, help="M2L launch shape 0..2 (-1: by size)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -57,6 +66,45 @@ def parse():
                     help="before the timed region, copy a buffer of this many MiB once (reference "
                          "dispatch for hardware byte counters)")
     return ap.parse_args()
+
+
+def kernel_source_sha(cls):
+    """First 16 hex digits of the SHA-256 of the sources of a kernel class
+    ("p2p" or "m2l")."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[cls]:
+        with open(os.path.join(ROOT, "paper_1905_01341_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls, kernel, workload, lmax, p):
+    """(bytes per launch, fetch KiB, write KiB) of the line for this kernel,
+    workload, depth and order measured on the kernel class's current
+    sources, else None.
+    Lines: kernel, workload, lmax, p, source hash, launches, FETCH_SIZE KiB,
+    WRITE_SIZE KiB, fetch scale, write scale, bytes per launch (tab separated)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = kernel_source_sha(cls)
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.rstrip("\n").split("\t")
+            if (len(f) == 11 and f[0] == kernel and f[1] == workload and int(f[2]) == lmax
+                    and int(f[3]) == p and f[4] == sha):
+                return float(f[10]), float(f[6]), float(f[7])
+    return None
+
+
+def m2l_kernel_name(p, shape):
+    """Instantiation of the M2L translation kernel for order p and launch
+    shape (template arguments: p^2, rows per block, waves, class)."""
+    pp = p * p
+    mid = 48 if pp == 144 else (80 if pp == 400 else (64 if pp >= 64 else pp))
+    rows, waves = {0: (pp if pp <= 256 else mid, 8), 1: (mid, 4), 2: (16, 4)}[shape]
+    return f"bfm::k_translate<{pp}, {rows}, {waves}, 0>"
 
 
 def cpu_baseline(cl, phi, matvecs, rows_n):
@@ -156,7 +204,7 @@ def main():
     q_t = torch.zeros_like(phi_t)
     def make_solver(precond, graph=0):
         sv = bfm.Solver(device=0, p=a.p, p_diag=a.p_diag, leaf_target=a.leaf, lmax=a.lmax,
-                        gmres_tol=a.tol, gmres_restart=a.restart, gmres_maxit=1000,
+                        m2l_shape=a.m2l_shape, gmres_tol=a.tol, gmres_restart=a.restart, gmres_maxit=1000,
                         precond=precond, precond_degree=a.precond_degree, use_graph=graph)
         sv.set_cluster(cl)
         return sv
@@ -220,13 +268,28 @@ def main():
         d = prof[dom]
         avg_ms = d["ms"] / max(d["launches"], 1)
         ach = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
-        pp = sv.opt.p * sv.opt.p
-        roof = {"kernel": {"p2p": "bfm::k_p2p<1, true, false> (near field, GMRES products)",
-                           "m2l": f"bfm::k_translate<{pp}, 0> (M2L, GMRES products)",
-                           "m2m_l2l": f"bfm::k_translate<{pp}, 1> (M2M/L2L, GMRES products)"}[dom],
+        if dom == "p2p":
+            kname = "bfm::k_p2p<1, true, false>"
+            # compulsory bytes: positions (24 B) and strength (8 B) of every
+            # point read once, its sum (8 B) written once
+            alg_bytes = 40.0 * cl.nv
+        elif dom == "m2l":
+            kname = m2l_kernel_name(sv.opt.p, stats["m2l_shape"]) if stats["m2l_shape"] >= 0 else None
+            # every M2L operator read once, every box's multipole read and
+            # local expansion written once
+            pp = sv.opt.p * sv.opt.p
+            alg_bytes = 8.0 * (316 * pp * pp + 2 * stats["boxes"] * pp)
+        else:
+            kname, alg_bytes = None, None
+        tr = measured_traffic(dom, kname, a.workload, stats["lmax"], sv.opt.p) if kname else None
+        roof = {"kernel": kname or dom,
                 "bound": "alu" if dom == "p2p" else "mfma",
                 "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                "traffic": None if tr is None else round(tr[0]),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
+                "traffic_GBps": None if tr is None else round(tr[0] / (avg_ms * 1e-3) / 1e9, 1),
+                "algorithmic_bytes": alg_bytes,
                 "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
                 "flops_per_launch": d["flops"] / max(d["launches"], 1)}
     out = {

@@ -223,7 +223,9 @@ int bfm_autotune(bfm_ctx *ctx, double mvp_tol, bfm_tune_result *out);
 
 /* Octree statistics of the current mesh (builds the tree if needed):
  * stats[0] = lmax, [1] = leaves, [2] = boxes (all levels), [3] = near-field
- * pairs, [4] = M2L pairs, [5] = M2M+L2L pairs, [6] = max points per leaf. */
+ * pairs, [4] = M2L pairs, [5] = M2M+L2L pairs, [6] = max points per leaf,
+ * [7] = launch shape (0, 1, 2 as bfm_options.m2l_shape) of the last M2L
+ * launch of a GMRES product, -1 before the first product. */
 int bfm_tree_stats(bfm_ctx *ctx, int64_t stats[8]);
 
 /*

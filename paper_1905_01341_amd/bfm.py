@@ -368,7 +368,7 @@ class Solver:
     def tree_stats(self):
         st = (ctypes.c_int64 * 8)()
         _check(self.lib.bfm_tree_stats(self.h, st))
-        keys = ["lmax", "leaves", "boxes", "near_pairs", "m2l_pairs", "tree_pairs", "max_leaf"]
+        keys = ["lmax", "leaves", "boxes", "near_pairs", "m2l_pairs", "tree_pairs", "max_leaf", "m2l_shape"]
         return {k: int(st[i]) for i, k in enumerate(keys)}
 
     # -- learned initial guess (include/bfm_mlp.h) ---------------------------

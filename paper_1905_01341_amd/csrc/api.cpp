@@ -450,7 +450,7 @@ int bfm_tree_stats(bfm_ctx *c, int64_t stats[8]) {
         stats[4] = t.m2l.ntasks;
         stats[5] = 2 * tr;
         stats[6] = t.max_leaf;
-        stats[7] = 0;
+        stats[7] = c->fmm.m2l_shape_used;
     });
 }
 

@@ -27,6 +27,7 @@ struct FmmWork {
     DevBuf<double> ops_m2m, ops_l2l, ops_m2l;  // operators, column-major per op: [op][k][row]
     int ops_p = 0;
     int m2l_shape = -1;    // M2L launch shape (-1: chosen by size)
+    int m2l_shape_used = -1;  // shape of the last M2L launch (-1: none yet)
     Prof *prof = nullptr;  // optional kernel timing
 };
 

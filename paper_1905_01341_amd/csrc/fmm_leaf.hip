@@ -1,0 +1,404 @@
+// Leaf expansions of the fast multipole product (Section 3.9): P2M forms
+// the multipole expansion of every leaf from its points' monopoles and
+// dipoles, L2P evaluates every leaf's local expansion at its points. Both
+// build the regular solid harmonics of a point by the three-term recurrences
+// of the box-scaled normalised basis, in registers.
+//
+// Both kernels run one wave per near-field work item (a leaf and up to
+// kP2PChunk of its points, the same items as the near field), each lane
+// taking kP2PChunk / 64 points, so the grid has about twice as many waves as
+// the octree has leaves and every wave does the same amount of work.
+#include <cmath>
+#include <vector>
+
+#include "fmm_kernels.h"
+
+namespace bfm {
+
+constexpr int kTri = kMaxP * (kMaxP + 1) / 2;  // (n, m >= 0) pairs, n < kMaxP
+constexpr int kPPL = kP2PChunk / 64;            // points per lane
+static_assert(kPPL * 64 == kP2PChunk, "whole points per lane");
+
+// Recurrence of the regular harmonics for degree n > m:
+//   Rt_n^m = ae(n, m) z Rt_{n-1}^m - ab(n, m) r^2 Rt_{n-2}^m,
+//   ae = (2n-1)/sqrt((n-m)(n+m)), ab = sqrt((n-m-1)(n+m-1))/sqrt((n-m)(n+m)),
+// and for the sectoral ones Rt_m^m = f_m (x + i y) Rt_{m-1}^{m-1},
+//   f_m = sqrt((2m-1)/(2m)).
+__constant__ double2 c_rec[kTri];  // (ae, ab) at tri(n, m)
+__constant__ double c_sect[kMaxP];  // f_m
+
+__host__ __device__ constexpr int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+
+void leaf_tables_upload(int device) {
+    static int done_mask = 0;  // one bit per device ordinal < 32
+    if (device < 32 && (done_mask >> device) & 1) return;
+    std::vector<double2> rec(kTri, make_double2(0.0, 0.0));
+    std::vector<double> sect(kMaxP, 0.0);
+    for (int n = 0; n < kMaxP; ++n)
+        for (int m = 0; m < n; ++m) {
+            const double a = 1.0 / std::sqrt((double)(n - m) * (n + m));
+            const double b = n >= m + 2 ? std::sqrt((double)(n - m - 1) * (n + m - 1)) : 0.0;
+            rec[tri(n, m)] = make_double2((2.0 * n - 1.0) * a, b * a);
+        }
+    for (int m = 1; m < kMaxP; ++m) sect[m] = std::sqrt((2.0 * m - 1.0) / (2.0 * m));
+    BFM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_rec), rec.data(), sizeof(double2) * kTri));
+    BFM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_sect), sect.data(), sizeof(double) * kMaxP));
+    if (device < 32) done_mask |= 1 << device;
+}
+
+// Copy the recurrence tables for order P into LDS (block-wide).
+template <int P_>
+__device__ inline void stage_tables(double2 *rec, double *sect, int tid, int nthreads) {
+    constexpr int NT = P_ * (P_ + 1) / 2;
+    for (int t = tid; t < NT; t += nthreads) rec[t] = c_rec[t];
+    for (int t = tid; t < P_; t += nthreads) sect[t] = c_sect[t];
+}
+
+// ---------------------------------------------------------------------------
+// P2M. Lane l takes the item's points l, l + 64, ..., builds their regular
+// harmonics order by order (loops over order m and degree k uniform across
+// the wave, recurrence constants read from LDS at wave-uniform addresses)
+// and sums its points' contributions for every coefficient (slot) and
+// channel. The wave's 64 partial sums of each (slot, channel) column are
+// buffered in LDS (one row per column) and, once COLS or more columns are
+// buffered, lane t adds up row t and adds it to the leaf's expansion with an
+// FP64 atomic (a leaf with more points than one item has several items).
+//   Mt_n^m += q_j conj(Rt_n^m(v_j)) + (w_j / h) conj(n_j . grad_v Rt_n^m(v_j)),
+// v_j = (r_j - c)/h. The directional derivative D = n_j . grad_v follows the
+// same recurrence by forward differentiation:
+//   D Rt_m^m = f_m [D Rt_{m-1}^{m-1} (x+iy) + Rt_{m-1}^{m-1} (n_x+i n_y)]
+//   D Rt_n^m = ae (n_z Rt_{n-1} + z D Rt_{n-1}) - ab (2 v.n Rt_{n-2} + r^2 D Rt_{n-2})
+// Slots run over m, then degree k >= m, then (real, imaginary) for m > 0;
+// column = slot * NCH + channel.
+template <int P_, int NCH, bool MONO, bool DIP>
+__global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int64_t leaf0,
+                                            const int *__restrict__ leaf_pt, const double *__restrict__ centre,
+                                            double h, const double *__restrict__ px, const double *__restrict__ py,
+                                            const double *__restrict__ pz, const double *__restrict__ pnx,
+                                            const double *__restrict__ pny, const double *__restrict__ pnz, int64_t n,
+                                            const double *__restrict__ q, const double *__restrict__ w,
+                                            double *__restrict__ mexp) {
+    constexpr int PP = P_ * P_;
+    constexpr int NT = P_ * (P_ + 1) / 2;
+    constexpr int NCOL = PP * NCH;
+    constexpr int COLS = NCH == 1 ? 32 : 4 * NCH;  // flush threshold
+    constexpr int CAP = COLS + 4 * NCH;              // a loop trip adds at most 4 NCH columns
+    static_assert(CAP <= 64, "one lane per buffered column");
+    __shared__ double red[CAP][65];
+    __shared__ double2 rec[NT];
+    __shared__ double sect[P_];
+    __shared__ int outi[PP];
+    const int lane = threadIdx.x;
+    const int2 it = items[blockIdx.x];
+    const int leaf = it.x, rb = it.y;
+    const int re = min(rb + kP2PChunk, leaf_pt[leaf + 1]);
+    const int64_t box = leaf0 + leaf;
+    stage_tables<P_>(rec, sect, lane, 64);
+    // slot -> coefficient index in the packed expansion (n^2 + 2m - 1 + imaginary)
+    for (int s = lane; s < PP; s += 64) {
+        int k = s, o = s * s;
+        if (s >= P_) {
+            int r = s - P_, m = 1;
+            while (r >= 2 * (P_ - m)) {
+                r -= 2 * (P_ - m);
+                ++m;
+            }
+            k = m + r / 2;
+            o = k * k + 2 * m - 1 + (r & 1);
+        }
+        outi[s] = o;
+    }
+    const double cx = centre[3 * box], cy = centre[3 * box + 1], cz = centre[3 * box + 2];
+    const double ih = 1.0 / h;
+    double x[kPPL], y[kPPL], z[kPPL], r2[kPPL], sq[kPPL][NCH], sw[kPPL][NCH];
+    double ux[kPPL], uy[kPPL], uz[kPPL], vu2[kPPL];
+#pragma unroll
+    for (int u = 0; u < kPPL; ++u) {
+        const int j0 = rb + 64 * u + lane;
+        const bool ok = j0 < re;
+        const int j = ok ? j0 : rb;  // idle slots: the first point, zero strength
+        x[u] = (px[j] - cx) * ih;
+        y[u] = (py[j] - cy) * ih;
+        z[u] = (pz[j] - cz) * ih;
+        r2[u] = x[u] * x[u] + y[u] * y[u] + z[u] * z[u];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            sq[u][c] = MONO ? (ok ? q[(int64_t)c * n + j] : 0.0) : 0.0;
+            sw[u][c] = DIP ? (ok ? w[(int64_t)c * n + j] * ih : 0.0) : 0.0;
+        }
+        ux[u] = DIP ? pnx[j] : 0.0;
+        uy[u] = DIP ? pny[j] : 0.0;
+        uz[u] = DIP ? pnz[j] : 0.0;
+        vu2[u] = 2.0 * (x[u] * ux[u] + y[u] * uy[u] + z[u] * uz[u]);
+    }
+    __syncthreads();
+    double *mbox = mexp + box * NCH * PP;
+    int col = 0, fill = 0;  // next column, buffered columns (wave-uniform)
+    // buffered column sums -> the leaf's expansion
+    auto flush = [&]() {
+        __syncthreads();
+        if (lane < fill) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int l = 0; l < 64; l += 4) {
+                s0 += red[lane][l];
+                s1 += red[lane][l + 1];
+                s2 += red[lane][l + 2];
+                s3 += red[lane][l + 3];
+            }
+            const int cc = col - fill + lane;
+            const int sl = cc / NCH, c = cc - sl * NCH;
+            unsafeAtomicAdd(mbox + c * PP + outi[sl], (s0 + s1) + (s2 + s3));
+        }
+        __syncthreads();
+        fill = 0;
+    };
+    auto put = [&](double v) {
+        red[fill][lane] = v;
+        ++fill;
+        ++col;
+    };
+    double dr[kPPL], di[kPPL], Ddr[kPPL], Ddi[kPPL];  // Rt_m^m and its derivative
+#pragma unroll
+    for (int u = 0; u < kPPL; ++u) {
+        dr[u] = 1.0;
+        di[u] = Ddr[u] = Ddi[u] = 0.0;
+    }
+#pragma unroll 1
+    for (int m = 0; m < P_; ++m) {
+        if (m > 0) {
+            const double f = sect[m];
+#pragma unroll
+            for (int u = 0; u < kPPL; ++u) {
+                const double nr = (dr[u] * x[u] - di[u] * y[u]) * f, ni = (dr[u] * y[u] + di[u] * x[u]) * f;
+                if (DIP) {
+                    const double nDr = (Ddr[u] * x[u] - Ddi[u] * y[u] + dr[u] * ux[u] - di[u] * uy[u]) * f;
+                    const double nDi = (Ddr[u] * y[u] + Ddi[u] * x[u] + dr[u] * uy[u] + di[u] * ux[u]) * f;
+                    Ddr[u] = nDr;
+                    Ddi[u] = nDi;
+                }
+                dr[u] = nr;
+                di[u] = ni;
+            }
+        }
+        // degrees k = m, m+1, ...: two register sets take turns holding the
+        // current and the previous degree (the new degree overwrites the
+        // previous one), two degrees per loop trip
+        double Ar[kPPL], Ai[kPPL], Br[kPPL], Bi[kPPL], DAr[kPPL], DAi[kPPL], DBr[kPPL], DBi[kPPL];
+#pragma unroll
+        for (int u = 0; u < kPPL; ++u) {
+            Ar[u] = dr[u];
+            Ai[u] = di[u];
+            DAr[u] = Ddr[u];
+            DAi[u] = Ddi[u];
+            Br[u] = Bi[u] = DBr[u] = DBi[u] = 0.0;
+        }
+        // P <- degree k from C (degree k-1) and P (degree k-2)
+        auto advance = [&](int t, const double(&Cr)[kPPL], const double(&Ci)[kPPL], const double(&DCr)[kPPL],
+                           const double(&DCi)[kPPL], double(&Pr)[kPPL], double(&Pi)[kPPL], double(&DPr)[kPPL],
+                           double(&DPi)[kPPL]) {
+            const double2 ca = rec[t];
+#pragma unroll
+            for (int u = 0; u < kPPL; ++u) {
+                const double ez = ca.x * z[u], br = ca.y * r2[u];
+                if (DIP) {
+                    const double eu = ca.x * uz[u], bv = ca.y * vu2[u];
+                    const double nDr = eu * Cr[u] + ez * DCr[u] - bv * Pr[u] - br * DPr[u];
+                    const double nDi = eu * Ci[u] + ez * DCi[u] - bv * Pi[u] - br * DPi[u];
+                    DPr[u] = nDr;
+                    DPi[u] = nDi;
+                }
+                Pr[u] = ez * Cr[u] - br * Pr[u];
+                Pi[u] = ez * Ci[u] - br * Pi[u];
+            }
+        };
+        // the conjugated coefficient of degree k (held in C) for every channel
+        auto emit = [&](const double(&Cr)[kPPL], const double(&Ci)[kPPL], const double(&DCr)[kPPL],
+                        const double(&DCi)[kPPL]) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                double v = sq[0][c] * Cr[0] + sw[0][c] * DCr[0];
+#pragma unroll
+                for (int u = 1; u < kPPL; ++u) v += sq[u][c] * Cr[u] + sw[u][c] * DCr[u];
+                put(v);
+            }
+            if (m > 0) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    double v = sq[0][c] * Ci[0] + sw[0][c] * DCi[0];
+#pragma unroll
+                    for (int u = 1; u < kPPL; ++u) v += sq[u][c] * Ci[u] + sw[u][c] * DCi[u];
+                    put(-v);
+                }
+            }
+        };
+        emit(Ar, Ai, DAr, DAi);
+        int k = m + 1, t = tri(m + 1, m);
+#pragma unroll 1
+        for (; k + 1 < P_; k += 2) {
+            if (fill >= COLS) flush();
+            advance(t, Ar, Ai, DAr, DAi, Br, Bi, DBr, DBi);
+            emit(Br, Bi, DBr, DBi);
+            t += k + 1;
+            advance(t, Br, Bi, DBr, DBi, Ar, Ai, DAr, DAi);
+            emit(Ar, Ai, DAr, DAi);
+            t += k + 2;
+        }
+        if (fill >= COLS) flush();
+        if (k < P_) {
+            advance(t, Ar, Ai, DAr, DAi, Br, Bi, DBr, DBi);
+            emit(Br, Bi, DBr, DBi);
+        }
+    }
+    flush();
+}
+
+// L2P. Lane l takes the item's points l, l + 64, ...:
+//   y_i += (1/h) sum_n [Lt_n^0 Rt_n^0 + 2 sum_{m>0} Re(Lt_n^m Rt_n^m)],
+// the harmonics built in registers order by order. The leaf's coefficients
+// and the recurrence constants are first copied to LDS with coalesced loads;
+// every step reads them at a wave-uniform LDS address.
+template <int P_, int NCH>
+__global__ void __launch_bounds__(64) k_l2p(const int2 *__restrict__ items, int64_t leaf0,
+                                            const int *__restrict__ leaf_pt, const double *__restrict__ centre,
+                                            double h, const double *__restrict__ px, const double *__restrict__ py,
+                                            const double *__restrict__ pz, int64_t n,
+                                            const double *__restrict__ lexp, double *__restrict__ y) {
+    constexpr int PP = P_ * P_;
+    constexpr int NT = P_ * (P_ + 1) / 2;
+    __shared__ double Ls[NCH * PP];
+    __shared__ double2 rec[NT];
+    __shared__ double sect[P_];
+    const int lane = threadIdx.x;
+    const int2 it = items[blockIdx.x];
+    const int leaf = it.x, rb = it.y;
+    const int re = min(rb + kP2PChunk, leaf_pt[leaf + 1]);
+    const int64_t box = leaf0 + leaf;
+    const double *L = lexp + box * NCH * PP;
+    for (int t = lane; t < NCH * PP; t += 64) Ls[t] = L[t];
+    stage_tables<P_>(rec, sect, lane, 64);
+    const double ih = 1.0 / h;
+    const double cx = centre[3 * box], cy = centre[3 * box + 1], cz = centre[3 * box + 2];
+    double x[kPPL], yy[kPPL], z[kPPL], r2[kPPL], acc[kPPL][NCH];
+#pragma unroll
+    for (int u = 0; u < kPPL; ++u) {
+        const int j0 = rb + 64 * u + lane;
+        const int j = j0 < re ? j0 : rb;
+        x[u] = (px[j] - cx) * ih;
+        yy[u] = (py[j] - cy) * ih;
+        z[u] = (pz[j] - cz) * ih;
+        r2[u] = x[u] * x[u] + yy[u] * yy[u] + z[u] * z[u];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) acc[u][c] = 0.0;
+    }
+    __syncthreads();
+    double dr[kPPL], di[kPPL];
+#pragma unroll
+    for (int u = 0; u < kPPL; ++u) {
+        dr[u] = 1.0;
+        di[u] = 0.0;
+    }
+#pragma unroll 1
+    for (int m = 0; m < P_; ++m) {
+        if (m > 0) {
+            const double f = sect[m];
+#pragma unroll
+            for (int u = 0; u < kPPL; ++u) {
+                const double nr = (dr[u] * x[u] - di[u] * yy[u]) * f, ni = (dr[u] * yy[u] + di[u] * x[u]) * f;
+                dr[u] = nr;
+                di[u] = ni;
+            }
+        }
+        double Ar[kPPL], Ai[kPPL], Br[kPPL], Bi[kPPL];  // current / previous degree, taking turns
+#pragma unroll
+        for (int u = 0; u < kPPL; ++u) {
+            Ar[u] = dr[u];
+            Ai[u] = di[u];
+            Br[u] = Bi[u] = 0.0;
+        }
+        const double wgt = (m == 0) ? 1.0 : 2.0;
+        auto advance = [&](int t, const double(&Cr)[kPPL], const double(&Ci)[kPPL], double(&Pr)[kPPL],
+                           double(&Pi)[kPPL]) {
+            const double2 ca = rec[t];
+#pragma unroll
+            for (int u = 0; u < kPPL; ++u) {
+                const double ez = ca.x * z[u], br = ca.y * r2[u];
+                Pr[u] = ez * Cr[u] - br * Pr[u];
+                Pi[u] = ez * Ci[u] - br * Pi[u];
+            }
+        };
+        auto gather = [&](int li, const double(&Cr)[kPPL], const double(&Ci)[kPPL]) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const double lre = wgt * Ls[c * PP + li], lim = (m == 0) ? 0.0 : wgt * Ls[c * PP + li + 1];
+#pragma unroll
+                for (int u = 0; u < kPPL; ++u) acc[u][c] += lre * Cr[u] - lim * Ci[u];
+            }
+        };
+        int li = m * m + (m == 0 ? 0 : 2 * m - 1);  // real part of (k, m) in the packed layout
+        gather(li, Ar, Ai);
+        int k = m + 1, t = tri(m + 1, m);
+        li += 2 * m + 1;
+#pragma unroll 1
+        for (; k + 1 < P_; k += 2) {
+            advance(t, Ar, Ai, Br, Bi);
+            gather(li, Br, Bi);
+            t += k + 1;
+            li += 2 * k + 1;
+            advance(t, Br, Bi, Ar, Ai);
+            gather(li, Ar, Ai);
+            t += k + 2;
+            li += 2 * k + 3;
+        }
+        if (k < P_) {
+            advance(t, Ar, Ai, Br, Bi);
+            gather(li, Br, Bi);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kPPL; ++u) {
+        const int j = rb + 64 * u + lane;
+        if (j < re) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + j] += acc[u][c] * ih;
+        }
+    }
+}
+
+template <int P_, int NCH, bool MONO, bool DIP>
+void launch_p2m(const Tree &t, const Sources &src, double *M, hipStream_t st) {
+    if (t.n_p2p_items <= 0) return;
+    const int64_t leaf0 = t.lvl_off[t.lmax];
+    const double hleaf = t.side / (double)(1 << t.lmax);
+    k_p2m<P_, NCH, MONO, DIP><<<(unsigned)t.n_p2p_items, 64, 0, st>>>(
+        t.p2p_items.get(), leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf, t.px.get(), t.py.get(), t.pz.get(),
+        t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, M);
+    BFM_LAUNCHED();
+}
+
+template <int P_, int NCH>
+void launch_l2p(const Tree &t, const double *L, double *y, hipStream_t st) {
+    if (t.n_p2p_items <= 0) return;
+    const int64_t leaf0 = t.lvl_off[t.lmax];
+    const double hleaf = t.side / (double)(1 << t.lmax);
+    k_l2p<P_, NCH><<<(unsigned)t.n_p2p_items, 64, 0, st>>>(t.p2p_items.get(), leaf0, t.leaf_pt.get(),
+                                                           t.box_centre.get(), hleaf, t.px.get(), t.py.get(),
+                                                           t.pz.get(), t.n, L, y);
+    BFM_LAUNCHED();
+}
+
+#define BFM_LEAF_INST(P)                                                                   \
+    template void launch_p2m<P, 1, true, false>(const Tree &, const Sources &, double *, hipStream_t); \
+    template void launch_p2m<P, 1, false, true>(const Tree &, const Sources &, double *, hipStream_t); \
+    template void launch_p2m<P, 1, true, true>(const Tree &, const Sources &, double *, hipStream_t);  \
+    template void launch_p2m<P, 5, true, true>(const Tree &, const Sources &, double *, hipStream_t);  \
+    template void launch_l2p<P, 1>(const Tree &, const double *, double *, hipStream_t);               \
+    template void launch_l2p<P, 5>(const Tree &, const double *, double *, hipStream_t);
+BFM_LEAF_INST(4)
+BFM_LEAF_INST(8)
+BFM_LEAF_INST(12)
+BFM_LEAF_INST(16)
+BFM_LEAF_INST(20)
+#undef BFM_LEAF_INST
+
+}  // namespace bfm

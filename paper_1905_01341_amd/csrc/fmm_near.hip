@@ -1,0 +1,213 @@
+// Near field of the fast multipole product (Section 3.9): direct sums of
+// every leaf's receivers over the points of the leaf and its neighbours
+// (P2P), and the all-pairs sum used as a check.
+#include <cmath>
+
+#include "fmm_kernels.h"
+
+namespace bfm {
+
+// ---------------------------------------------------------------------------
+// Near field. 1/sqrt in FP64: the hardware estimate (relative error about
+// 5e-8) refined by one Newton step with an FMA-formed residual.
+__device__ inline double rsqrt_f64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+constexpr int kP2PThreads = 64;
+
+// Receivers xi..zi (R per lane) against sources [j0, j1): every lane reads
+// the same source at the same time, so the loads are wave-uniform (scalar
+// loads of read-only data) and no LDS staging is needed.
+// SELF: the sources may include the receiver itself (r = 0, excluded);
+// otherwise every pair is at a positive distance and needs no test.
+template <int NCH, bool MONO, bool DIP, int R, bool SELF>
+__device__ inline void p2p_pair(double sx, double sy, double sz, const double *sq, const double *sw,
+                                double nx, double ny, double nz, const double *xi, const double *yi,
+                                const double *zi, double (*acc)[NCH]) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const double dx = xi[k] - sx, dy = yi[k] - sy, dz = zi[k] - sz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double inv = (!SELF || r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
+        if (MONO) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) acc[k][c] += sq[c] * inv;
+        }
+        if (DIP) {
+            const double tt = (nx * dx + ny * dy + nz * dz) * (inv * inv * inv);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) acc[k][c] += sw[c] * tt;
+        }
+    }
+}
+
+// Receivers xi..zi (R per lane) against sources [j0, j1): every lane reads
+// the same source at the same time, so the loads are wave-uniform (scalar
+// loads of read-only data); sources are fetched in batches of B so one wait
+// covers B sources.
+template <int NCH, bool MONO, bool DIP, int R, bool SELF>
+__device__ inline void p2p_range(int j0, int j1, const double *__restrict__ px,
+                                 const double *__restrict__ py, const double *__restrict__ pz,
+                                 const double *__restrict__ pnx, const double *__restrict__ pny,
+                                 const double *__restrict__ pnz, int64_t n,
+                                 const double *__restrict__ q, const double *__restrict__ w,
+                                 const double *xi, const double *yi, const double *zi,
+                                 double (*acc)[NCH]) {
+    constexpr int B = (NCH == 1 && !DIP) ? 8 : (NCH == 1 ? 4 : 2);
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        double bx[B], by[B], bz[B], bq[B][NCH], bw[B][NCH], bnx[B], bny[B], bnz[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            bx[u] = px[j + u];
+            by[u] = py[j + u];
+            bz[u] = pz[j + u];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                bq[u][c] = MONO ? q[(int64_t)c * n + j + u] : 0.0;
+                bw[u][c] = DIP ? w[(int64_t)c * n + j + u] : 0.0;
+            }
+            bnx[u] = DIP ? pnx[j + u] : 0.0;
+            bny[u] = DIP ? pny[j + u] : 0.0;
+            bnz[u] = DIP ? pnz[j + u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            p2p_pair<NCH, MONO, DIP, R, SELF>(bx[u], by[u], bz[u], bq[u], bw[u], bnx[u], bny[u], bnz[u], xi, yi, zi,
+                                        acc);
+    }
+    for (; j < j1; ++j) {
+        double sq[NCH], sw[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            sq[c] = MONO ? q[(int64_t)c * n + j] : 0.0;
+            sw[c] = DIP ? w[(int64_t)c * n + j] : 0.0;
+        }
+        p2p_pair<NCH, MONO, DIP, R, SELF>(px[j], py[j], pz[j], sq, sw, DIP ? pnx[j] : 0.0, DIP ? pny[j] : 0.0,
+                                    DIP ? pnz[j] : 0.0, xi, yi, zi, acc);
+    }
+}
+
+template <int NCH, bool MONO, bool DIP, int R>
+__device__ inline void p2p_pass(int rc, int l0, int r1, int nr, const int2 *__restrict__ rng,
+                                const double *__restrict__ px, const double *__restrict__ py,
+                                const double *__restrict__ pz, const double *__restrict__ pnx,
+                                const double *__restrict__ pny, const double *__restrict__ pnz,
+                                int64_t n, const double *__restrict__ q, const double *__restrict__ w,
+                                double *__restrict__ y) {
+    const int lane = threadIdx.x;
+    double xi[R], yi[R], zi[R], acc[R][NCH];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        const bool ok = i < r1;
+        // idle lanes sit far away: their sums are never stored
+        xi[k] = ok ? px[i] : 1e100;
+        yi[k] = ok ? py[i] : 0.0;
+        zi[k] = ok ? pz[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) acc[k][c] = 0.0;
+    }
+    // only the leaf's own points can coincide with a receiver: the merged
+    // range holding them is split so that the rest runs without the test
+    for (int g = 0; g < nr; ++g) {
+        const int2 r = rng[g];
+        const int l1 = r1;  // the leaf's points are [l0, r1)
+        if (r.x <= l0 && l1 <= r.y) {
+            p2p_range<NCH, MONO, DIP, R, false>(r.x, l0, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+            p2p_range<NCH, MONO, DIP, R, true>(l0, l1, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+            p2p_range<NCH, MONO, DIP, R, false>(l1, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+        } else {
+            p2p_range<NCH, MONO, DIP, R, false>(r.x, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        if (i < r1)
+            for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[k][c];
+    }
+}
+
+// One wave per near-field work item (a leaf and up to 64 of its receivers,
+// items ordered by decreasing pair count); sources = the leaf's merged
+// near-field ranges (the points of up to 27 neighbour leaves).
+template <int NCH, bool MONO, bool DIP>
+__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int2 *__restrict__ items,
+                                                     const int *__restrict__ leaf_pt,
+                                                     const int2 *__restrict__ near_rng,
+                                                     const int *__restrict__ near_cnt,
+                                                     const double *__restrict__ px,
+                                                     const double *__restrict__ py,
+                                                     const double *__restrict__ pz,
+                                                     const double *__restrict__ pnx,
+                                                     const double *__restrict__ pny,
+                                                     const double *__restrict__ pnz, int64_t n,
+                                                     const double *__restrict__ q,
+                                                     const double *__restrict__ w, double *__restrict__ y) {
+    constexpr int R = kP2PChunk / kP2PThreads;
+    static_assert(kP2PChunk == R * kP2PThreads, "whole receivers per lane");
+    const int2 it = items[blockIdx.x];
+    const int leaf = it.x, rc = it.y;
+    const int r1 = leaf_pt[leaf + 1];
+    p2p_pass<NCH, MONO, DIP, R>(rc, leaf_pt[leaf], r1, near_cnt[leaf], near_rng + 27 * (int64_t)leaf, px, py, pz, pnx,
+                                pny, pnz, n, q, w, y);
+}
+
+// All-pairs sum (checking path): 64 receivers per wave x every source.
+template <int NCH, bool MONO, bool DIP>
+__global__ void __launch_bounds__(kP2PThreads) k_direct(const double *__restrict__ px,
+                                                        const double *__restrict__ py,
+                                                        const double *__restrict__ pz,
+                                                        const double *__restrict__ pnx,
+                                                        const double *__restrict__ pny,
+                                                        const double *__restrict__ pnz, int64_t n,
+                                                        const double *__restrict__ q,
+                                                        const double *__restrict__ w,
+                                                        double *__restrict__ y) {
+    const int64_t base = (int64_t)blockIdx.x * kP2PThreads;
+    const int r1 = (int)((n - base) < kP2PThreads ? (n - base) : kP2PThreads);
+    const int2 all = make_int2(0, (int)n);
+    // receivers base + lane (pass of one receiver per lane), sources all points
+    double xi[1], yi[1], zi[1], acc[1][NCH];
+    const int i = (int)base + threadIdx.x;
+    const bool ok = threadIdx.x < (unsigned)r1;
+    xi[0] = ok ? px[i] : 1e100;
+    yi[0] = ok ? py[i] : 0.0;
+    zi[0] = ok ? pz[i] : 0.0;
+    for (int c = 0; c < NCH; ++c) acc[0][c] = 0.0;
+    p2p_range<NCH, MONO, DIP, 1, true>(all.x, all.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+    if (ok)
+        for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[0][c];
+}
+
+static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int NCH, bool MONO, bool DIP>
+void launch_p2p(const Tree &t, const Sources &src, double *y, hipStream_t st) {
+    k_p2p<NCH, MONO, DIP><<<(unsigned)t.n_p2p_items, kP2PThreads, 0, st>>>(
+        t.p2p_items.get(), t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
+        t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, y);
+    BFM_LAUNCHED();
+}
+
+template <int NCH, bool MONO, bool DIP>
+void launch_direct(const Tree &t, const Sources &src, double *y, hipStream_t st) {
+    k_direct<NCH, MONO, DIP><<<nblk(t.n, kP2PThreads), kP2PThreads, 0, st>>>(
+        t.px.get(), t.py.get(), t.pz.get(), t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, y);
+    BFM_LAUNCHED();
+}
+
+#define BFM_NEAR_INST(NCH, MONO, DIP)                                                                    \
+    template void launch_p2p<NCH, MONO, DIP>(const Tree &, const Sources &, double *, hipStream_t); \
+    template void launch_direct<NCH, MONO, DIP>(const Tree &, const Sources &, double *, hipStream_t);
+BFM_NEAR_INST(1, true, false)
+BFM_NEAR_INST(1, false, true)
+BFM_NEAR_INST(1, true, true)
+BFM_NEAR_INST(5, true, true)
+#undef BFM_NEAR_INST
+
+}  // namespace bfm
