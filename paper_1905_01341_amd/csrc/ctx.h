@@ -27,6 +27,7 @@ struct Precond {
     std::vector<int> tri_h;      // template triangles (first bubble, local indices)
     ShBasis basis;
     DevBuf<double> fac, R, X, C, Y;
+    DevBuf<double> gws;                // split-K partial products of the GEMMs
     // coarse space of per-bubble constants (two-level form)
     DevBuf<double> U;                  // own-bubble column sums of s^T L, caller order [nv]
     DevBuf<double> ccen, carea;        // area-weighted centroids [nb][3], areas [nb]
@@ -125,6 +126,10 @@ void spd_inverse(double *A, int n, DevBuf<double> &piv, DevBuf<double> &row, Dev
 // C = A B, column-major FP64 (precond.hip)
 void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                  hipStream_t st);
+// C = rowscale o (A B) + beta D (rowscale, D may be null; C may alias D);
+// ws non-null allows a split of K (partial products kept in ws)
+void gemm_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              const double *rowscale, double beta, const double *D, int ldd, DevBuf<double> *ws, hipStream_t st);
 
 // the solve of bfm_solve_dev: tree, diagonals and b, optional guess, GMRES
 // (guess: BFM_GUESS_*); throws BFM_ENOCONV when GMRES stops at gmres_maxit

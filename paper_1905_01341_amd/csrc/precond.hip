@@ -13,6 +13,7 @@
 // nmax get the first unresolved eigenvalue. Applied as a right
 // preconditioner inside GMRES, so the residual GMRES monitors is the true
 // one and the solution is unchanged.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -171,39 +172,61 @@ __global__ void k_bubble_radius(const double *s, int nd, double *R) {
     if (threadIdx.x == 0) R[b] = sqrt(red[0] / (4.0 * 3.14159265358979323846));
 }
 
-// C[M x N] = rowscale o (A[M x K] B[K x N]) + beta D, all column-major, FP64
-// MFMA (v_mfma_f64_16x16x4f64). A workgroup of 4 waves owns a 64 x 64 tile
-// of C (each wave a 32 x 32 quarter, 2 x 2 MFMA blocks); K advances in
-// chunks of 16 staged through LDS. rowscale and D may be null. C may alias D
+// C = rowscale o (A B) + beta D, column-major FP64 on MFMA
+// (v_mfma_f64_16x16x4f64). A workgroup of 4 waves owns a 64 x 64 tile of C
+// (each wave a 32 x 32 quarter, 2 x 2 MFMA blocks); K advances in chunks of
+// 32 staged through LDS, the next chunk's elements loaded into registers
+// while the current one is multiplied. With gridDim.z = S > 1 the K range is
+// split into S slices and slice z writes its raw partial product to
+// W + z M N (ld M); k_gemm_sum then adds the slices in a fixed order and
+// applies rowscale and beta D. rowscale and D may be null. C may alias D
 // (each element is read and written by the same lane) but not A or B.
 // MFMA operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
 // of a 16 x 4 by 4 x 16 product; element r of the result holds row
 // l / 16 + 4 r, column l % 16.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, const double *A, int lda,
+constexpr int kGemmKC = 32;  // K chunk
+
+__global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, int kslice, const double *A, int lda,
                                                  const double *B, int ldb, double *C, int ldc,
-                                                 const double *rowscale, double beta, const double *D,
-                                                 int ldd) {
-    __shared__ double As[16][64 + 1], Bs[16][64 + 1];  // [k][row], [k][col]
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                 const double *rowscale, double beta, const double *D, int ldd,
+                                                 double *W) {
+    __shared__ double As[kGemmKC][64 + 1], Bs[kGemmKC][64 + 1];  // [k][row], [k][col]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int ka = blockIdx.z * kslice, kb = min(K, ka + kslice);
     const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
     dbl4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int ii = e % 64, kk = e / 64;  // A: consecutive rows
+    // element e = tid + 256 u of a chunk: A (64 rows x 32 k, rows fastest),
+    // B (32 k x 64 columns, k fastest)
+    double ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
+            const int ii = e & 63, kk = e >> 6;
             const int gi = i0 + ii, gk = k0 + kk;
-            As[kk][ii] = (gi < M && gk < K) ? A[(int64_t)gk * lda + gi] : 0.0;
-            const int kb = e % 16, jj = e / 16;  // B: consecutive k within a column
-            const int gj = j0 + jj, gk2 = k0 + kb;
-            Bs[kb][jj] = (gj < N && gk2 < K) ? B[(int64_t)gj * ldb + gk2] : 0.0;
+            ra[u] = (gi < M && gk < kb) ? A[(int64_t)gk * lda + gi] : 0.0;
+            const int kq = e & 31, jj = e >> 5;
+            const int gj = j0 + jj, gk2 = k0 + kq;
+            rb[u] = (gj < N && gk2 < kb) ? B[(int64_t)gj * ldb + gk2] : 0.0;
+        }
+    };
+    if (ka < kb) load(ka);
+    for (int k0 = ka; k0 < kb; k0 += kGemmKC) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
+            As[e >> 6][e & 63] = ra[u];
+            Bs[e & 31][e >> 5] = rb[u];
         }
         __syncthreads();
+        if (k0 + kGemmKC < kb) load(k0 + kGemmKC);  // in flight during the products
 #pragma unroll
-        for (int k4 = 0; k4 < 4; ++k4) {
+        for (int k4 = 0; k4 < kGemmKC / 4; ++k4) {
             const int kk = 4 * k4 + lane / 16;
             double af[2], bf[2];
 #pragma unroll
@@ -218,6 +241,7 @@ __global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, const doub
         }
         __syncthreads();
     }
+    double *Wz = W ? W + (int64_t)blockIdx.z * M * N : nullptr;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -227,19 +251,55 @@ __global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, const doub
                 const int gi = i0 + wi + 16 * a + lane / 16 + 4 * r, gj = j0 + wj + 16 * b + lane % 16;
                 if (gi < M && gj < N) {
                     double val = acc[a][b][r];
-                    if (rowscale) val *= rowscale[gi];
-                    if (D) val += beta * D[(int64_t)gj * ldd + gi];
-                    C[(int64_t)gj * ldc + gi] = val;
+                    if (Wz) {
+                        Wz[(int64_t)gj * M + gi] = val;
+                    } else {
+                        if (rowscale) val *= rowscale[gi];
+                        if (D) val += beta * D[(int64_t)gj * ldd + gi];
+                        C[(int64_t)gj * ldc + gi] = val;
+                    }
                 }
             }
+}
+
+// C = rowscale o (sum over the S slices of W) + beta D
+__global__ void k_gemm_sum(int M, int N, int S, const double *W, double *C, int ldc, const double *rowscale,
+                           double beta, const double *D, int ldd) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (e >= mn) return;
+    const int i = (int)(e % M), j = (int)(e / M);
+    double v = 0.0;
+    for (int z = 0; z < S; ++z) v += W[z * mn + e];
+    if (rowscale) v *= rowscale[i];
+    if (D) v += beta * D[(int64_t)j * ldd + i];
+    C[(int64_t)j * ldc + i] = v;
+}
+
+void gemm_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              const double *rowscale, double beta, const double *D, int ldd, DevBuf<double> *ws, hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    // split K when the tiles alone leave most of the chip idle and the
+    // slices stay at least two chunks deep
+    int S = 1;
+    if (ws && tiles < 256) S = std::max(1, std::min((512 + tiles - 1) / tiles, K / (2 * kGemmKC)));
+    const int kslice = ((K + S - 1) / S + kGemmKC - 1) / kGemmKC * kGemmKC;
+    S = std::max(1, (K + kslice - 1) / kslice);
+    dim3 g((M + 63) / 64, (N + 63) / 64, S);
+    double *W = S > 1 ? ws->ensure((size_t)S * M * N) : nullptr;
+    k_gemm_nn<<<g, 256, 0, st>>>(M, N, K, kslice, A, lda, B, ldb, C, ldc, rowscale, beta, D, ldd, W);
+    BFM_LAUNCHED();
+    if (S > 1) {
+        k_gemm_sum<<<nblk((int64_t)M * N, 256), 256, 0, st>>>(M, N, S, W, C, ldc, rowscale, beta, D, ldd);
+        BFM_LAUNCHED();
+    }
 }
 
 // C = A B, all column-major (the plain product of k_gemm_nn)
 void gemm_nn_f64(int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                  hipStream_t st) {
-    dim3 g((M + 63) / 64, (N + 63) / 64);
-    k_gemm_nn<<<g, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, nullptr, 0.0, nullptr, 0);
-    BFM_LAUNCHED();
+    gemm_f64(M, N, K, A, lda, B, ldb, C, ldc, nullptr, 0.0, nullptr, 0, nullptr, st);
 }
 
 // out_s[i] = Y[perm[i]] / R[b] (+ cy[b]), b the bubble of perm[i]  (sorted order)
@@ -292,7 +352,8 @@ __global__ void k_coarse_geom(const double *xyz, const double *s, int nd, double
 
 // U_j = s_j (sum_{i in a, i != j} s_i / (4 pi r_ij) + L_jj) for vertex j of
 // bubble a (caller order). Grid (vertex blocks, bubbles); the bubble's
-// points pass through LDS in chunks.
+// points pass through LDS in chunks. 1/r: the hardware estimate refined by
+// one Newton step (relative error ~1e-15); the pair i = j (r = 0) is masked.
 __global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const double *s, const double *lii, int nd,
                                                   double *U) {
     constexpr int CH = 512;
@@ -303,7 +364,7 @@ __global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const doubl
     const bool ok = j < nd;
     const double xj = ok ? xyz[3 * (base + j)] : 0.0, yj = ok ? xyz[3 * (base + j) + 1] : 0.0,
                  zj = ok ? xyz[3 * (base + j) + 2] : 0.0;
-    double acc = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
     for (int c0 = 0; c0 < nd; c0 += CH) {
         const int cn = min(CH, nd - c0);
         __syncthreads();
@@ -315,14 +376,30 @@ __global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const doubl
             ss[t] = s[o];
         }
         __syncthreads();
-        if (ok)
-            for (int t = 0; t < cn; ++t) {
-                if (c0 + t == j) continue;
-                const double dx = xj - sx[t], dy = yj - sy[t], dz = zj - sz[t];
-                acc += ss[t] / sqrt(dx * dx + dy * dy + dz * dz);
+        int t = 0;
+        for (; t + 2 <= cn; t += 2) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const double dx = xj - sx[t + u], dy = yj - sy[t + u], dz = zj - sz[t + u];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double y = __builtin_amdgcn_rsq(r2);
+                const double inv = fma(0.5 * y, fma(-r2 * y, y, 1.0), y);
+                const double v = (c0 + t + u == j) ? 0.0 : ss[t + u] * inv;
+                if (u == 0)
+                    acc0 += v;
+                else
+                    acc1 += v;
             }
+        }
+        for (; t < cn; ++t) {
+            const double dx = xj - sx[t], dy = yj - sy[t], dz = zj - sz[t];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double y = __builtin_amdgcn_rsq(r2);
+            const double inv = fma(0.5 * y, fma(-r2 * y, y, 1.0), y);
+            acc0 += (c0 + t == j) ? 0.0 : ss[t] * inv;
+        }
     }
-    if (ok) U[base + j] = s[base + j] * (acc * (1.0 / (4.0 * 3.14159265358979323846)) + lii[base + j]);
+    if (ok) U[base + j] = s[base + j] * ((acc0 + acc1) * (1.0 / (4.0 * 3.14159265358979323846)) + lii[base + j]);
 }
 
 // A (column-major nb x nb): off-diagonal point-monopole couplings; the
@@ -350,42 +427,42 @@ __global__ void k_coarse_matrix(const double *cen, const double *area, const dou
 // step publishes the pivot row and column through LDS.
 constexpr int kGjBlock = 64;
 __global__ void __launch_bounds__(256) k_gj_block(const double *A, int n, int k0, int bs, double *P) {
-    __shared__ double prow[kGjBlock], pcol[kGjBlock];
-    const int j = threadIdx.x % kGjBlock, i0 = 16 * (threadIdx.x / kGjBlock);
-    double t[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = i0 + r;
+    // the block lives in LDS; thread (j, i0) updates column j, rows i0..i0+15
+    __shared__ double a[kGjBlock][kGjBlock + 1];  // [row][column]
+    const int tid = threadIdx.x;
+    const int j = tid % kGjBlock, i0 = 16 * (tid / kGjBlock);
+    for (int e = tid; e < kGjBlock * kGjBlock; e += 256) {
+        const int i = e % kGjBlock, c = e / kGjBlock;
         // identity outside the bs x bs block keeps the padded steps inert
-        t[r] = (i < bs && j < bs) ? A[(int64_t)(k0 + j) * n + k0 + i] : (i == j ? 1.0 : 0.0);
+        a[i][c] = (i < bs && c < bs) ? A[(int64_t)(k0 + c) * n + k0 + i] : (i == c ? 1.0 : 0.0);
     }
+    __syncthreads();
     for (int k = 0; k < kGjBlock; ++k) {
-        // publish column k (old values) and row k
+        // old row k, column k and pivot
+        const double p = 1.0 / a[k][k];
+        const double akj = a[k][j];
+        double f[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if (j == k) pcol[i0 + r] = t[r];
-            if (i0 + r == k) prow[j] = t[r];
-        }
+        for (int r = 0; r < 16; ++r) f[r] = a[i0 + r][k];
         __syncthreads();
-        const double p = 1.0 / prow[k];
-        const double rk = (j == k) ? p : prow[j] * p;  // new row k, column j
+        const double rk = (j == k) ? p : akj * p;  // new row k, column j
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int i = i0 + r;
-            const double f = pcol[i];
+            double v;
             if (i == k)
-                t[r] = rk;
+                v = rk;
             else if (j == k)
-                t[r] = -f * p;
+                v = -f[r] * p;
             else
-                t[r] -= f * rk;
+                v = a[i][j] - f[r] * rk;
+            a[i][j] = v;
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = i0 + r;
-        if (i < bs && j < bs) P[(int64_t)j * bs + i] = -t[r];
+    for (int e = tid; e < kGjBlock * kGjBlock; e += 256) {
+        const int i = e % kGjBlock, c = e / kGjBlock;
+        if (i < bs && c < bs) P[(int64_t)c * bs + i] = -a[i][c];
     }
 }
 
@@ -492,13 +569,10 @@ void precond_apply(bfm_ctx *c, const double *in_s, double *out_s) {
     double *Cm = P.C.ensure((size_t)nc * nb);
     double *Y = P.Y.ensure((size_t)nd * nb);
     to_original(c, in_s, X);
-    dim3 g1((nc + 63) / 64, (nb + 63) / 64), g2((nd + 63) / 64, (nb + 63) / 64);
     // C = diag(2n+1 - c) G+ X
-    k_gemm_nn<<<g1, 256, 0, st>>>(nc, nb, nd, P.basis.Gp.get(), nc, X, nd, Cm, nc, P.fac.get(), 0.0, nullptr, 0);
-    BFM_LAUNCHED();
+    gemm_f64(nc, nb, nd, P.basis.Gp.get(), nc, X, nd, Cm, nc, P.fac.get(), 0.0, nullptr, 0, &P.gws, st);
     // Y = G C + c X
-    k_gemm_nn<<<g2, 256, 0, st>>>(nd, nb, nc, P.basis.G.get(), nd, Cm, nc, Y, nd, nullptr, P.cc, X, nd);
-    BFM_LAUNCHED();
+    gemm_f64(nd, nb, nc, P.basis.G.get(), nd, Cm, nc, Y, nd, nullptr, P.cc, X, nd, &P.gws, st);
     const double *cy = nullptr;
     if (c->opt.precond == BFM_PRECOND_SH_COARSE) {
         double *sums = P.csum.get();
@@ -531,20 +605,12 @@ void spd_inverse(double *A, int nb, DevBuf<double> &piv, DevBuf<double> &row, De
         // Rn = Pn A_K,:  (= -P^{-1} A_K,:), bs x nb
         gemm_nn_f64(bs, nb, bs, Pn, bs, A + k0, nb, Rn, bs, st);
         // trailing columns outside the block: A += A_:,K Rn
-        dim3 g((nb + 63) / 64, 1);
-        if (k0 > 0) {
-            g.y = (k0 + 63) / 64;
-            k_gemm_nn<<<g, 256, 0, st>>>(nb, k0, bs, A + (int64_t)k0 * nb, nb, Rn, bs, A, nb, nullptr, 1.0, A,
-                                         nb);
-            BFM_LAUNCHED();
-        }
+        if (k0 > 0)
+            gemm_f64(nb, k0, bs, A + (int64_t)k0 * nb, nb, Rn, bs, A, nb, nullptr, 1.0, A, nb, nullptr, st);
         const int j1 = k0 + bs;
-        if (j1 < nb) {
-            g.y = (nb - j1 + 63) / 64;
-            k_gemm_nn<<<g, 256, 0, st>>>(nb, nb - j1, bs, A + (int64_t)k0 * nb, nb, Rn + (int64_t)j1 * bs, bs,
-                                         A + (int64_t)j1 * nb, nb, nullptr, 1.0, A + (int64_t)j1 * nb, nb);
-            BFM_LAUNCHED();
-        }
+        if (j1 < nb)
+            gemm_f64(nb, nb - j1, bs, A + (int64_t)k0 * nb, nb, Rn + (int64_t)j1 * bs, bs, A + (int64_t)j1 * nb,
+                     nb, nullptr, 1.0, A + (int64_t)j1 * nb, nb, nullptr, st);
         // Cn = A_:,K Pn  (= -A_:,K P^{-1}), nb x bs
         gemm_nn_f64(nb, bs, bs, A + (int64_t)k0 * nb, nb, Pn, bs, Cn, nb, st);
         k_gj_fix<<<nblk(2 * (int64_t)bs * nb, 256), 256, 0, st>>>(A, nb, k0, bs, Rn, Cn, Pn);
