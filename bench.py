@@ -33,7 +33,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and FP64 matrix (dense)
 # to the value it was measured with.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c1000.txt")
 KERNEL_SOURCES = {"p2p": ("fmm_near.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h"),
-                  "m2l": ("fmm.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h")}
+                  "m2l": ("fmm.hip", "fmm.h", "common.h")}
 
 
 def parse():

@@ -4,10 +4,10 @@
 // build the regular solid harmonics of a point by the three-term recurrences
 // of the box-scaled normalised basis, in registers.
 //
-// Both kernels run one wave per near-field work item (a leaf and up to
-// kP2PChunk of its points, the same items as the near field), each lane
-// taking kP2PChunk / 64 points, so the grid has about twice as many waves as
-// the octree has leaves and every wave does the same amount of work.
+// Both kernels run one wave per leaf work item (a leaf and up to kP2PChunk of
+// its points), each lane taking kP2PChunk / 64 points, so the grid has about
+// twice as many waves as the octree has leaves and every wave does the same
+// amount of work.
 #include <cmath>
 #include <vector>
 
@@ -367,21 +367,21 @@ __global__ void __launch_bounds__(64) k_l2p(const int2 *__restrict__ items, int6
 
 template <int P_, int NCH, bool MONO, bool DIP>
 void launch_p2m(const Tree &t, const Sources &src, double *M, hipStream_t st) {
-    if (t.n_p2p_items <= 0) return;
+    if (t.n_leaf_items <= 0) return;
     const int64_t leaf0 = t.lvl_off[t.lmax];
     const double hleaf = t.side / (double)(1 << t.lmax);
-    k_p2m<P_, NCH, MONO, DIP><<<(unsigned)t.n_p2p_items, 64, 0, st>>>(
-        t.p2p_items.get(), leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf, t.px.get(), t.py.get(), t.pz.get(),
+    k_p2m<P_, NCH, MONO, DIP><<<(unsigned)t.n_leaf_items, 64, 0, st>>>(
+        t.leaf_items.get(), leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf, t.px.get(), t.py.get(), t.pz.get(),
         t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, M);
     BFM_LAUNCHED();
 }
 
 template <int P_, int NCH>
 void launch_l2p(const Tree &t, const double *L, double *y, hipStream_t st) {
-    if (t.n_p2p_items <= 0) return;
+    if (t.n_leaf_items <= 0) return;
     const int64_t leaf0 = t.lvl_off[t.lmax];
     const double hleaf = t.side / (double)(1 << t.lmax);
-    k_l2p<P_, NCH><<<(unsigned)t.n_p2p_items, 64, 0, st>>>(t.p2p_items.get(), leaf0, t.leaf_pt.get(),
+    k_l2p<P_, NCH><<<(unsigned)t.n_leaf_items, 64, 0, st>>>(t.leaf_items.get(), leaf0, t.leaf_pt.get(),
                                                            t.box_centre.get(), hleaf, t.px.get(), t.py.get(),
                                                            t.pz.get(), t.n, L, y);
     BFM_LAUNCHED();

@@ -91,8 +91,12 @@ __device__ inline void p2p_range(int j0, int j1, const double *__restrict__ px,
     }
 }
 
-template <int NCH, bool MONO, bool DIP, int R>
-__device__ inline void p2p_pass(int rc, int l0, int r1, int nr, const int2 *__restrict__ rng,
+// Receivers rc + lane + 64 k (k < R) of the leaf whose points are [l0, r1)
+// against sources s0..s1-1 of the leaf's source list (its near ranges in
+// order). ATOMIC: several items share these receivers, so the sums are added
+// into the (cleared) output; otherwise they are stored.
+template <int NCH, bool MONO, bool DIP, int R, bool ATOMIC>
+__device__ inline void p2p_pass(int rc, int l0, int r1, int s0, int s1, int nr, const int2 *__restrict__ rng,
                                 const double *__restrict__ px, const double *__restrict__ py,
                                 const double *__restrict__ pz, const double *__restrict__ pnx,
                                 const double *__restrict__ pny, const double *__restrict__ pnz,
@@ -111,32 +115,46 @@ __device__ inline void p2p_pass(int rc, int l0, int r1, int nr, const int2 *__re
 #pragma unroll
         for (int c = 0; c < NCH; ++c) acc[k][c] = 0.0;
     }
-    // only the leaf's own points can coincide with a receiver: the merged
-    // range holding them is split so that the rest runs without the test
-    for (int g = 0; g < nr; ++g) {
+    // walk the ranges, keeping the part that falls in [s0, s1); only the
+    // leaf's own points [l0, r1) can coincide with a receiver, so that part
+    // runs with the test and the rest without
+    int cum = 0;
+    for (int g = 0; g < nr && cum < s1; ++g) {
         const int2 r = rng[g];
-        const int l1 = r1;  // the leaf's points are [l0, r1)
-        if (r.x <= l0 && l1 <= r.y) {
-            p2p_range<NCH, MONO, DIP, R, false>(r.x, l0, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
-            p2p_range<NCH, MONO, DIP, R, true>(l0, l1, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
-            p2p_range<NCH, MONO, DIP, R, false>(l1, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+        const int len = r.y - r.x;
+        const int a = r.x + max(0, s0 - cum), b = r.x + min(len, s1 - cum);
+        cum += len;
+        if (a >= b) continue;
+        if (a < r1 && l0 < b) {
+            const int m0 = max(a, l0), m1 = min(b, r1);
+            p2p_range<NCH, MONO, DIP, R, false>(a, m0, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+            p2p_range<NCH, MONO, DIP, R, true>(m0, m1, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+            p2p_range<NCH, MONO, DIP, R, false>(m1, b, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
         } else {
-            p2p_range<NCH, MONO, DIP, R, false>(r.x, r.y, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
+            p2p_range<NCH, MONO, DIP, R, false>(a, b, px, py, pz, pnx, pny, pnz, n, q, w, xi, yi, zi, acc);
         }
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int i = rc + lane + k * kP2PThreads;
         if (i < r1)
-            for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + i] = acc[k][c];
+            for (int c = 0; c < NCH; ++c) {
+                if (ATOMIC)
+                    unsafeAtomicAdd(y + (int64_t)c * n + i, acc[k][c]);
+                else
+                    y[(int64_t)c * n + i] = acc[k][c];
+            }
     }
 }
 
-// One wave per near-field work item (a leaf and up to 64 of its receivers,
-// items ordered by decreasing pair count); sources = the leaf's merged
-// near-field ranges (the points of up to 27 neighbour leaves).
-template <int NCH, bool MONO, bool DIP>
-__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int2 *__restrict__ items,
+// One wave per near-field work item (a leaf chunk of up to kP2PChunk
+// receivers, two per lane, and a piece of the leaf's source list; items
+// ordered by decreasing pair count). A leaf's sources are its merged
+// near-field ranges (the points of up to 27 neighbour leaves); lists longer
+// than kP2PPiece are split into balanced pieces so that no wave carries much
+// more work than the average and the dispatcher can balance the tail.
+template <int NCH, bool MONO, bool DIP, bool ATOMIC>
+__global__ void __launch_bounds__(kP2PThreads) k_p2p(const int4 *__restrict__ items,
                                                      const int *__restrict__ leaf_pt,
                                                      const int2 *__restrict__ near_rng,
                                                      const int *__restrict__ near_cnt,
@@ -150,11 +168,15 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int2 *__restrict__ it
                                                      const double *__restrict__ w, double *__restrict__ y) {
     constexpr int R = kP2PChunk / kP2PThreads;
     static_assert(kP2PChunk == R * kP2PThreads, "whole receivers per lane");
-    const int2 it = items[blockIdx.x];
-    const int leaf = it.x, rc = it.y;
-    const int r1 = leaf_pt[leaf + 1];
-    p2p_pass<NCH, MONO, DIP, R>(rc, leaf_pt[leaf], r1, near_cnt[leaf], near_rng + 27 * (int64_t)leaf, px, py, pz, pnx,
-                                pny, pnz, n, q, w, y);
+    const int4 it = items[blockIdx.x];
+    const int leaf = it.x;
+    p2p_pass<NCH, MONO, DIP, R, ATOMIC>(it.y, leaf_pt[leaf], leaf_pt[leaf + 1], it.z, it.w, near_cnt[leaf],
+                                        near_rng + 27 * (int64_t)leaf, px, py, pz, pnx, pny, pnz, n, q, w, y);
+}
+
+__global__ void k_clear(double *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
 }
 
 // All-pairs sum (checking path): 64 receivers per wave x every source.
@@ -188,9 +210,16 @@ static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 template <int NCH, bool MONO, bool DIP>
 void launch_p2p(const Tree &t, const Sources &src, double *y, hipStream_t st) {
-    k_p2p<NCH, MONO, DIP><<<(unsigned)t.n_p2p_items, kP2PThreads, 0, st>>>(
-        t.p2p_items.get(), t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
-        t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, y);
+    if (t.n_near_items <= 0) return;
+    if (t.near_split) {
+        k_clear<<<1024, 256, 0, st>>>(y, (int64_t)NCH * t.n);
+        BFM_LAUNCHED();
+    }
+    auto kern = t.near_split ? k_p2p<NCH, MONO, DIP, true> : k_p2p<NCH, MONO, DIP, false>;
+    kern<<<(unsigned)t.n_near_items, kP2PThreads, 0, st>>>(t.near_items.get(), t.leaf_pt.get(), t.near_rng.get(),
+                                                           t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
+                                                           t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w,
+                                                           y);
     BFM_LAUNCHED();
 }
 

@@ -11,7 +11,9 @@
 namespace bfm {
 
 constexpr int kKeyBits = 15;  // bits per axis of the point keys (levels 0..15)
-constexpr int kP2PChunk = 128;  // receivers per near-field work item (two per lane)
+constexpr int kP2PChunk = 128;   // receivers per leaf work item (two per lane)
+constexpr int kP2PPiece = 384;   // near-field sources per work item at most (a leaf's source
+                                 // list longer than this is split into balanced pieces)
 
 // Translation tasks grouped by operator: tasks op_off[o]..op_off[o+1] use
 // operator o; task t moves expansion src[t] into expansion dst[t] (global
@@ -61,10 +63,18 @@ struct Tree {
     // near_rng[leaf][k] = (start, end) for k < near_cnt[leaf] (at most 27)
     DevBuf<int2> near_rng;      // [nleaf][27]
     DevBuf<int> near_cnt;       // [nleaf]
-    // near-field work items: (leaf, first receiver) of chunks of at most
-    // kP2PChunk receivers, ordered by decreasing pair count
-    DevBuf<int2> p2p_items;
-    int64_t n_p2p_items = 0;
+    // leaf work items: (leaf, first point) of chunks of at most kP2PChunk
+    // points, ordered by decreasing near-field pair count (P2M, L2P)
+    DevBuf<int2> leaf_items;
+    int64_t n_leaf_items = 0;
+    // near-field work items: (leaf, first receiver, s0, s1): the receivers of
+    // a leaf chunk against sources s0..s1-1 of the leaf's source list (its
+    // near ranges in order), ordered by decreasing pair count. near_split:
+    // some leaf has more than one piece (the sums are then accumulated with
+    // atomics into a cleared output)
+    DevBuf<int4> near_items;
+    int64_t n_near_items = 0;
+    bool near_split = false;
 
     // sorted point data (per tree): positions, weights, normals
     DevBuf<double> px, py, pz;  // [n]
@@ -81,6 +91,7 @@ struct Tree {
         DevBuf<int> rs_hist, rs_scanned, rs_tmp;
         DevBuf<uint64_t> ikey, ikey2;
         DevBuf<int2> raw;
+        DevBuf<int4> raw4;
         DevBuf<double> bbox;
     } scratch;
 
