@@ -17,6 +17,7 @@ __device__ inline double rsqrt_f64(double x) {
 }
 
 constexpr int kP2PThreads = 64;
+constexpr int kXcdCount = 8;  // accelerator complex dies of an MI355X
 
 // Receivers xi..zi (R per lane) against sources [j0, j1): every lane reads
 // the same source at the same time, so the loads are wave-uniform (scalar
@@ -148,11 +149,11 @@ __device__ inline void p2p_pass(int rc, int l0, int r1, int s0, int s1, int nr, 
 }
 
 // One wave per near-field work item (a leaf chunk of up to kP2PChunk
-// receivers, two per lane, and a piece of the leaf's source list; items
-// ordered by decreasing pair count). A leaf's sources are its merged
-// near-field ranges (the points of up to 27 neighbour leaves); lists longer
-// than kP2PPiece are split into balanced pieces so that no wave carries much
-// more work than the average and the dispatcher can balance the tail.
+// receivers, two per lane, and a piece of the leaf's source list). A leaf's
+// sources are its merged near-field ranges (the points of up to 27
+// neighbour leaves); lists longer than kP2PPiece are split into balanced
+// pieces, so that no wave carries much more work than the average and there
+// are more waves than slots, which lets the dispatcher balance the tail.
 template <int NCH, bool MONO, bool DIP, bool ATOMIC>
 __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int4 *__restrict__ items,
                                                      const int *__restrict__ leaf_pt,
@@ -168,7 +169,12 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int4 *__restrict__ it
                                                      const double *__restrict__ w, double *__restrict__ y) {
     constexpr int R = kP2PChunk / kP2PThreads;
     static_assert(kP2PChunk == R * kP2PThreads, "whole receivers per lane");
-    const int4 it = items[blockIdx.x];
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so XCD
+    // x takes a contiguous run of items (neighbouring leaves, which share
+    // their sources) and keeps those sources in its own L2
+    const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
+    const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
+    const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
     const int leaf = it.x;
     p2p_pass<NCH, MONO, DIP, R, ATOMIC>(it.y, leaf_pt[leaf], leaf_pt[leaf + 1], it.z, it.w, near_cnt[leaf],
                                         near_rng + 27 * (int64_t)leaf, px, py, pz, pnx, pny, pnz, n, q, w, y);

@@ -64,12 +64,12 @@ struct Tree {
     DevBuf<int2> near_rng;      // [nleaf][27]
     DevBuf<int> near_cnt;       // [nleaf]
     // leaf work items: (leaf, first point) of chunks of at most kP2PChunk
-    // points, ordered by decreasing near-field pair count (P2M, L2P)
+    // points, in leaf order (P2M, L2P)
     DevBuf<int2> leaf_items;
     int64_t n_leaf_items = 0;
     // near-field work items: (leaf, first receiver, s0, s1): the receivers of
     // a leaf chunk against sources s0..s1-1 of the leaf's source list (its
-    // near ranges in order), ordered by decreasing pair count. near_split:
+    // near ranges in order), in leaf (Morton) order. near_split:
     // some leaf has more than one piece (the sums are then accumulated with
     // atomics into a cleared output)
     DevBuf<int4> near_items;
@@ -90,8 +90,6 @@ struct Tree {
         DevBuf<int> mo, flag, pos, tmp, icnt, ioff, iidx, iidx2, count, offs, ts, td, to, hist;
         DevBuf<int> rs_hist, rs_scanned, rs_tmp;
         DevBuf<uint64_t> ikey, ikey2;
-        DevBuf<int2> raw;
-        DevBuf<int4> raw4;
         DevBuf<double> bbox;
     } scratch;
 

@@ -450,25 +450,12 @@ __global__ void k_item_count(int64_t nleaf, const int *leaf_pt, int *cnt) {
     cnt[i] = (leaf_pt[i + 1] - leaf_pt[i] + kP2PChunk - 1) / kP2PChunk;
 }
 
-__global__ void k_item_fill(int64_t nleaf, const int *leaf_pt, const int *off, const int2 *rng,
-                            const int *rcnt, int2 *items, uint64_t *key, int *idx) {
+__global__ void k_item_fill(int64_t nleaf, const int *leaf_pt, const int *off, int2 *items) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
-    int src = 0;
-    for (int k = 0; k < rcnt[i]; ++k) src += rng[27 * i + k].y - rng[27 * i + k].x;
     const int r0 = leaf_pt[i], r1 = leaf_pt[i + 1];
     int o = off[i];
-    for (int r = r0; r < r1; r += kP2PChunk, ++o) {
-        const int nrec = (r1 - r) < kP2PChunk ? (r1 - r) : kP2PChunk;
-        items[o] = make_int2((int)i, r);
-        key[o] = 0xffffffffull - (uint64_t)((unsigned)nrec * (unsigned)src);  // descending cost
-        idx[o] = o;
-    }
-}
-
-__global__ void k_item_permute(const int2 *in, const int *idx, int64_t n, int2 *out) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = in[idx[i]];
+    for (int r = r0; r < r1; r += kP2PChunk, ++o) items[o] = make_int2((int)i, r);
 }
 
 // near-field sources of leaf i and the number of pieces they are split into
@@ -487,7 +474,7 @@ __global__ void k_piece_count(int64_t nleaf, const int *leaf_pt, const int2 *rng
 }
 
 __global__ void k_piece_fill(int64_t nleaf, const int *leaf_pt, const int *off, const int2 *rng, const int *rcnt,
-                             int4 *items, uint64_t *key, int *idx) {
+                             int4 *items) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
     const int src = leaf_sources(i, rng, rcnt);
@@ -496,18 +483,7 @@ __global__ void k_piece_fill(int64_t nleaf, const int *leaf_pt, const int *off, 
     const int r0 = leaf_pt[i], r1 = leaf_pt[i + 1];
     int o = off[i];
     for (int r = r0; r < r1; r += kP2PChunk)
-        for (int p = 0; p < pieces; ++p, ++o) {
-            const int s0 = min(src, p * ps), s1 = min(src, (p + 1) * ps);
-            const int nrec = (r1 - r) < kP2PChunk ? (r1 - r) : kP2PChunk;
-            items[o] = make_int4((int)i, r, s0, s1);
-            key[o] = 0xffffffffull - (uint64_t)((unsigned)nrec * (unsigned)(s1 - s0));  // descending cost
-            idx[o] = o;
-        }
-}
-
-__global__ void k_piece_permute(const int4 *in, const int *idx, int64_t n, int4 *out) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = in[idx[i]];
+        for (int p = 0; p < pieces; ++p, ++o) items[o] = make_int4((int)i, r, min(src, p * ps), min(src, (p + 1) * ps));
 }
 
 // ---------------------------------------------------------------------------
@@ -824,44 +800,25 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                       t.near_rng.get(), t.near_cnt.get());
     BFM_LAUNCHED();
     {
-        DevBuf<int> &icnt = scr.icnt, &ioff = scr.ioff, &iidx = scr.iidx, &iidx2 = scr.iidx2;
-        DevBuf<uint64_t> &ikey = scr.ikey, &ikey2 = scr.ikey2;
-        DevBuf<int2> &raw = scr.raw;
+        DevBuf<int> &icnt = scr.icnt, &ioff = scr.ioff;
         icnt.ensure(t.nleaf);
         ioff.ensure(t.nleaf);
         k_item_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), icnt.get());
         BFM_LAUNCHED();
         const int64_t ni = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);
-        raw.ensure(ni);
-        ikey.ensure(ni);
-        ikey2.ensure(ni);
-        iidx.ensure(ni);
-        iidx2.ensure(ni);
-        k_item_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.near_rng.get(),
-                                                        t.near_cnt.get(), raw.get(), ikey.get(), iidx.get());
-        BFM_LAUNCHED();
-        radix_sort(ikey.get(), iidx.get(), ikey2.get(), iidx2.get(), ni, 32, scr, st);
         t.leaf_items.ensure(ni);
-        k_item_permute<<<nblk(ni, 256), 256, 0, st>>>(raw.get(), iidx.get(), ni, t.leaf_items.get());
+        k_item_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.leaf_items.get());
         BFM_LAUNCHED();
         t.n_leaf_items = ni;
-        // near-field items: leaf chunks x balanced pieces of the source list
+        // near-field items: leaf chunks x balanced pieces of the source list,
+        // in leaf (Morton) order
         k_piece_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
                                                          t.near_cnt.get(), icnt.get());
         BFM_LAUNCHED();
         const int64_t nn = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);
-        DevBuf<int4> &raw4 = scr.raw4;
-        raw4.ensure(nn);
-        ikey.ensure(nn);
-        ikey2.ensure(nn);
-        iidx.ensure(nn);
-        iidx2.ensure(nn);
-        k_piece_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.near_rng.get(),
-                                                        t.near_cnt.get(), raw4.get(), ikey.get(), iidx.get());
-        BFM_LAUNCHED();
-        radix_sort(ikey.get(), iidx.get(), ikey2.get(), iidx2.get(), nn, 32, scr, st);
         t.near_items.ensure(nn);
-        k_piece_permute<<<nblk(nn, 256), 256, 0, st>>>(raw4.get(), iidx.get(), nn, t.near_items.get());
+        k_piece_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.near_rng.get(),
+                                                        t.near_cnt.get(), t.near_items.get());
         BFM_LAUNCHED();
         t.n_near_items = nn;
         t.near_split = nn > ni;

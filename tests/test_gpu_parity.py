@@ -93,6 +93,41 @@ def test_fmm_product_cluster_sampled(c100, p):
     assert e_l < tol_l and e_m < tol_m, (p, e_l, e_m)
 
 
+@pytest.mark.parametrize("lmax", [3, 4])
+def test_fmm_product_coarse_and_fine_leaves(c100, lmax):
+    """Fixed octree depths on the 100-bubble cluster: at lmax = 3 every
+    leaf's near-field source list runs to thousands of points and is split
+    into pieces whose sums are added atomically; at lmax = 4 the lists are
+    shorter. Both must give the same product to the expansion accuracy."""
+    cl, phi, s, n, rows = c100
+    sv = _solver(cl, p=16, lmax=lmax)
+    st = sv.tree_stats()
+    assert st["lmax"] == lmax
+    yl = sv.matvec(1.0, phi)
+    ym = sv.matvec(0.0, None, 1.0, phi)
+    ref_l = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, phi, rows=rows)
+    ref_m = oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi, rows=rows)
+    e_l, e_m = rel(yl[rows], ref_l), rel(ym[rows], ref_m)
+    print(f"lmax={lmax} near pairs={st['near_pairs']} L={e_l:.3e} M={e_m:.3e}")
+    assert e_l < 2e-7 and e_m < 3e-6, (lmax, e_l, e_m)
+
+
+def test_fmm_product_tiny_leaves(single):
+    """One sphere at lmax = 5: leaves of a few points, near-field source
+    lists short enough to stay in one piece (stores instead of atomics).
+    Nearly every far interaction of this tree is at the minimum separation,
+    so the truncation error at p = 16 is larger than at lmax = 2 (measured
+    1.1e-6 for L and 6.8e-6 for M); a lost or doubled near-field piece
+    would show as an error of order one."""
+    cl, phi, s, n = single
+    sv = _solver(cl, p=16, lmax=5)
+    x = np.cos(np.arange(cl.nv) * 0.37)
+    e_l = rel(sv.matvec(1.0, x), oracle.offdiag_mvp(cl.xyz, s, n, 1.0, x))
+    e_m = rel(sv.matvec(0.0, None, 1.0, phi), oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi))
+    print(f"L={e_l:.3e} M={e_m:.3e}")
+    assert e_l < 3e-6 and e_m < 2e-5, (e_l, e_m)
+
+
 def test_diagonals_and_rhs(single, c100):
     """M_ii = -1/2 - sum M_ij is a small difference of O(1/2) terms, so its
     error is judged against 1/2 (the size of the sum it comes from)."""
