@@ -103,7 +103,8 @@ def m2l_kernel_name(p, shape):
     shape (template arguments: p^2, rows per block, waves, class)."""
     pp = p * p
     mid = 48 if pp == 144 else (80 if pp == 400 else (64 if pp >= 64 else pp))
-    rows, waves = {0: (pp if pp <= 256 else mid, 8), 1: (mid, 4), 2: (16, 4)}[shape]
+    wide = pp if pp <= 144 else (128 if pp == 256 else mid)
+    rows, waves = {0: (wide, 8), 1: (mid, 4), 2: (16, 4)}[shape]
     return f"bfm::k_translate<{pp}, {rows}, {waves}, 0>"
 
 

@@ -46,7 +46,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
                                                           double *out) {
     static_assert(PP % ROWS == 0 && ROWS % 16 == 0, "row slab");
     constexpr int NSLAB = PP / ROWS;
-    __shared__ double As[2][kTKC * ROWS];  // two buffers of [k][row within slab]
+    __shared__ double As[2][kTKC * ROWS];         // two buffers of [k][row within slab]
+    __shared__ double Bs[2][WAVES][kTKC / 4][64];  // two buffers of each wave's input chunk
     // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so
     // XCD x takes a contiguous run of logical blocks (the tiles of a few
     // operators) and fetches each operator into its own L2 once
@@ -73,63 +74,68 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     const int btask = t0 + (bok ? bcolid / nch : 0);
     const int bch = bok ? bcolid % nch : 0;
     const int sb = bok ? (swap ? tdst[btask] : tsrc[btask]) : 0;
+    // idle columns read box 0's expansion (valid memory) and are never stored
     const double *bcol = in + ((int64_t)sb * nch + bch) * PP;
     const double *Top = T + (int64_t)op * PP * PP + slab * ROWS;
     const int kq = lane >> 4, rl = lane & 15;
     dbl4 acc[ROWS / 16];
 #pragma unroll
     for (int rb = 0; rb < ROWS / 16; ++rb) acc[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // double-buffered operator slab: the next chunk is fetched into
-    // registers while the current one feeds the MFMAs from LDS
+    // Operator slab chunks go global -> registers -> LDS (two LDS buffers),
+    // the input columns global -> registers; the loop is unrolled by two so
+    // that chunk c + 1 is in flight in its own registers while chunk c feeds
+    // the MFMAs, with no register copies between the stages.
     constexpr int NT = 64 * WAVES;
     constexpr int PER = (kTKC * ROWS + NT - 1) / NT;
-    double pre[PER];
-    auto fetch = [&](int k0) {
+    constexpr bool EXACT = PER * NT == kTKC * ROWS;  // every thread moves PER elements
+    static_assert(PP % kTKC == 0, "whole chunks");
+    constexpr int NC = PP / kTKC;
+    double pa[PER], pb[PER], ba[kTKC / 4], bb[kTKC / 4];
+    auto fetch = [&](int k0, double(&pre)[PER], double(&bv)[kTKC / 4]) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = tid + u * NT;
-            if (e < kTKC * ROWS) {
-                const int kk = e / ROWS, rr = e % ROWS;
-                pre[u] = Top[(int64_t)(k0 + kk) * PP + rr];
-            }
+            if (EXACT || e < kTKC * ROWS) pre[u] = Top[(int64_t)(k0 + e / ROWS) * PP + e % ROWS];
         }
+#pragma unroll
+        for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bcol[k0 + 4 * kk + kq];
     };
-    auto stash = [&](double *dst) {
+    // the chunk's operator slab and input columns -> LDS buffer `buf`
+    auto stash = [&](int buf, const double(&pre)[PER], const double(&bv)[kTKC / 4]) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = tid + u * NT;
-            if (e < kTKC * ROWS) dst[e] = pre[u];
-        }
+        for (int u = 0; u < PER; ++u)
+            if (EXACT || tid + u * NT < kTKC * ROWS) As[buf][tid + u * NT] = pre[u];
+#pragma unroll
+        for (int kk = 0; kk < kTKC / 4; ++kk) Bs[buf][wave][kk][lane] = bok ? bv[kk] : 0.0;
     };
-    fetch(0);
-    stash(As[0]);
-    // the wave's input columns are prefetched one chunk ahead as well
-    double bv[kTKC / 4], bn[kTKC / 4];
-#pragma unroll
-    for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bok ? bcol[4 * kk + kq] : 0.0;
-    __syncthreads();
-    int cur = 0;
-    for (int k0 = 0; k0 < PP; k0 += kTKC) {
-        const bool more = k0 + kTKC < PP;
-        if (more) {
-            fetch(k0 + kTKC);
-#pragma unroll
-            for (int kk = 0; kk < kTKC / 4; ++kk) bn[kk] = bok ? bcol[k0 + kTKC + 4 * kk + kq] : 0.0;
-        }
+    // the MFMAs of one chunk read only LDS, so no wait on the loads in flight
+    auto mult = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < kTKC / 4; ++kk) {
-            const double *Ak = As[cur] + (4 * kk + kq) * ROWS + rl;
+            const double *Ak = As[buf] + (4 * kk + kq) * ROWS + rl;
+            const double b = Bs[buf][wave][kk][lane];
 #pragma unroll
             for (int rb = 0; rb < ROWS / 16; ++rb)
-                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[kk], Ak[rb * 16], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, Ak[rb * 16], acc[rb], 0, 0, 0);
         }
-        if (more) {
-            stash(As[cur ^ 1]);
-            __syncthreads();
-            cur ^= 1;
-#pragma unroll
-            for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bn[kk];
-        }
+    };
+    fetch(0, pa, ba);
+    stash(0, pa, ba);
+    __syncthreads();
+    // the fetches are unconditional (past the end they repeat the last
+    // chunk) so that the memory-counter waits are the same on every path
+    for (int c = 0; c < NC; c += 2) {
+        // even chunk c in buffer 0; chunk c + 1 in flight
+        fetch(min(c + 1, NC - 1) * kTKC, pb, bb);
+        mult(0);
+        if (c + 1 >= NC) break;
+        stash(1, pb, bb);
+        __syncthreads();
+        // odd chunk c + 1 in buffer 1; chunk c + 2 in flight
+        fetch(min(c + 2, NC - 1) * kTKC, pa, ba);
+        mult(1);
+        stash(0, pa, ba);
+        __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -211,19 +217,21 @@ static void prof_end(FmmWork &w, int idx, hipStream_t st, double flops) {
 
 // Middle row-slab height: a multiple of 16 dividing p^2, at most 80.
 constexpr int mid_rows(int PP) { return PP == 144 ? 48 : (PP == 400 ? 80 : (PP >= 64 ? 64 : PP)); }
-// Wide-tile slab: every row while the accumulators fit in registers.
-constexpr int wide_rows(int PP) { return PP <= 256 ? PP : mid_rows(PP); }
+// Wide-tile slab: every row while 8 waves' accumulators and LDS stay small
+// (p <= 12), half the rows at p = 16.
+constexpr int wide_rows(int PP) { return PP <= 144 ? PP : (PP == 256 ? 128 : mid_rows(PP)); }
 
 template <int P_>
 static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, const double *T,
                       const double *in, double *out, hipStream_t st) {
     constexpr int PP = P_ * P_;
     const int64_t cols = tl.ntasks * nch;
-    // Enough waves for the whole chip: all rows per wave (wide 128-column
-    // tiles, fewest operator re-reads) when there are many columns, row slabs
-    // (more waves, columns re-read per slab) when there are few.
+    // Enough waves for the whole chip: row slabs of 64 (80 at p = 20) rows
+    // when there are many columns, 16-row slabs (more waves) when there are
+    // few; the wide 128-column tiles (shape 0, fewest operator re-reads but
+    // twice the LDS per workgroup) only on request.
     const int64_t wave_tiles = (cols + 15) / 16;
-    int shape = (wave_tiles >= 8192) ? 0 : (wave_tiles * (PP / mid_rows(PP)) >= 8192 ? 1 : 2);
+    int shape = (wave_tiles * (PP / mid_rows(PP)) >= 8192) ? 1 : 2;
     if (cls == KC_M2L && w.m2l_shape >= 0) shape = w.m2l_shape;
     if (cls == KC_M2L) w.m2l_shape_used = shape;
     const int width = (shape == 0) ? 128 : 64;

@@ -115,7 +115,10 @@ void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st);
 void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits, Tree::Scratch &scr,
                 hipStream_t st);
 
-// Device-wide exclusive scan of int32 (in place allowed); returns the total.
+// Device-wide exclusive scan of int32 (in place allowed); returns the total
+// (one wait for the stream).
 int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp);
+// The same scan left in flight on the stream (no total, no wait).
+void exclusive_scan_async(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp);
 
 }  // namespace bfm

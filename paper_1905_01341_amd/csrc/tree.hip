@@ -207,7 +207,7 @@ void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, in
         const int shift = 8 * pass;
         k_rs_hist<<<nblocks, RS_THREADS, 0, st>>>(kin, n, shift, hist.get(), nblocks);
         BFM_LAUNCHED();
-        exclusive_scan(hist.get(), scanned.get(), (int64_t)256 * nblocks, st, tmp);
+        exclusive_scan_async(hist.get(), scanned.get(), (int64_t)256 * nblocks, st, tmp);
         k_rs_scatter<<<nblocks, RS_THREADS, 0, st>>>(kin, vin, n, shift, scanned.get(), nblocks, kout, vout);
         BFM_LAUNCHED();
         std::swap(kin, kout);
@@ -268,22 +268,46 @@ static void scan_rec(const int *in, int *out, int64_t n, hipStream_t st, int *tm
     BFM_LAUNCHED();
 }
 
-int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp) {
-    if (n <= 0) return 0;
+// total = in[n-1] (kept before an in-place scan overwrites it), then
+// total += out[n-1]: the sum of all inputs, on the device
+__global__ void k_scan_last(const int *in, int64_t n, int *total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] = in[n - 1];
+}
+__global__ void k_scan_total(const int *out, int64_t n, int *total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] += out[n - 1];
+}
+
+// scratch of the recursion (the sums of every level) plus one slot for the
+// total at index *total_slot
+static int *scan_scratch(int64_t n, DevBuf<int> &tmp, int64_t *total_slot = nullptr) {
     int64_t need = 2, m = n;
     while (m > 1) {
         m = (m + SC_TILE - 1) / SC_TILE;
         need += m + 1;
     }
-    int *t = tmp.ensure((size_t)need + 2);
-    int last_in = 0;
-    BFM_HIP(hipMemcpyAsync(&last_in, in + n - 1, sizeof(int), hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipStreamSynchronize(st));
+    if (total_slot) *total_slot = need + 1;
+    return tmp.ensure((size_t)need + 2);
+}
+
+void exclusive_scan_async(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp) {
+    if (n <= 0) return;
+    scan_rec(in, out, n, st, scan_scratch(n, tmp));
+}
+
+int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp) {
+    if (n <= 0) return 0;
+    int64_t slot = 0;
+    int *t = scan_scratch(n, tmp, &slot);
+    int *dtotal = t + slot;
+    k_scan_last<<<1, 64, 0, st>>>(in, n, dtotal);
+    BFM_LAUNCHED();
     scan_rec(in, out, n, st, t);
-    int last_out = 0;
-    BFM_HIP(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    k_scan_total<<<1, 64, 0, st>>>(out, n, dtotal);
+    BFM_LAUNCHED();
+    int total = 0;
+    BFM_HIP(hipMemcpyAsync(&total, dtotal, sizeof(int), hipMemcpyDeviceToHost, st));
     BFM_HIP(hipStreamSynchronize(st));
-    return (int64_t)last_out + last_in;
+    return total;
 }
 
 // ---------------------------------------------------------------------------
