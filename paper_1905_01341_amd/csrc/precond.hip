@@ -426,43 +426,43 @@ __global__ void k_coarse_matrix(const double *cen, const double *area, const dou
 // Thread t owns column t % 64 and rows 16 (t / 64) .. +15 in registers; each
 // step publishes the pivot row and column through LDS.
 constexpr int kGjBlock = 64;
-__global__ void __launch_bounds__(256) k_gj_block(const double *A, int n, int k0, int bs, double *P) {
-    // the block lives in LDS; thread (j, i0) updates column j, rows i0..i0+15
-    __shared__ double a[kGjBlock][kGjBlock + 1];  // [row][column]
+constexpr int kGjThreads = 1024;
+constexpr int kGjRows = kGjBlock * kGjBlock / kGjThreads;  // rows per thread
+__global__ void __launch_bounds__(kGjThreads) k_gj_block(const double *A, int n, int k0, int bs, double *P) {
+    // The block lives in LDS, twice: step k reads buffer k % 2 and writes the
+    // other, so one barrier per step suffices. Thread (j, i0) updates column
+    // j, rows i0..i0+3: sixteen waves share the step, which is bound by the
+    // latency of its reads and writes rather than by their number.
+    __shared__ double a[2][kGjBlock][kGjBlock + 1];  // [buffer][row][column]
     const int tid = threadIdx.x;
-    const int j = tid % kGjBlock, i0 = 16 * (tid / kGjBlock);
-    for (int e = tid; e < kGjBlock * kGjBlock; e += 256) {
+    const int j = tid % kGjBlock, i0 = kGjRows * (tid / kGjBlock);
+    for (int e = tid; e < kGjBlock * kGjBlock; e += kGjThreads) {
         const int i = e % kGjBlock, c = e / kGjBlock;
         // identity outside the bs x bs block keeps the padded steps inert
-        a[i][c] = (i < bs && c < bs) ? A[(int64_t)(k0 + c) * n + k0 + i] : (i == c ? 1.0 : 0.0);
+        a[0][i][c] = (i < bs && c < bs) ? A[(int64_t)(k0 + c) * n + k0 + i] : (i == c ? 1.0 : 0.0);
     }
     __syncthreads();
     for (int k = 0; k < kGjBlock; ++k) {
-        // old row k, column k and pivot
-        const double p = 1.0 / a[k][k];
-        const double akj = a[k][j];
-        double f[16];
+        const double(*src)[kGjBlock + 1] = a[k & 1];
+        double(*dst)[kGjBlock + 1] = a[(k & 1) ^ 1];
+        // 1 / pivot: hardware reciprocal and two Newton steps
+        const double piv = src[k][k];
+        double p = __builtin_amdgcn_rcp(piv);
+        p = fma(p, fma(-piv, p, 1.0), p);
+        p = fma(p, fma(-piv, p, 1.0), p);
+        const double rk = (j == k) ? p : src[k][j] * p;  // new row k, column j
 #pragma unroll
-        for (int r = 0; r < 16; ++r) f[r] = a[i0 + r][k];
-        __syncthreads();
-        const double rk = (j == k) ? p : akj * p;  // new row k, column j
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kGjRows; ++r) {
             const int i = i0 + r;
-            double v;
-            if (i == k)
-                v = rk;
-            else if (j == k)
-                v = -f[r] * p;
-            else
-                v = a[i][j] - f[r] * rk;
-            a[i][j] = v;
+            const double f = src[i][k], old = src[i][j];
+            const double upd = (j == k) ? -f * p : old - f * rk;
+            dst[i][j] = (i == k) ? rk : upd;
         }
         __syncthreads();
     }
-    for (int e = tid; e < kGjBlock * kGjBlock; e += 256) {
+    for (int e = tid; e < kGjBlock * kGjBlock; e += kGjThreads) {
         const int i = e % kGjBlock, c = e / kGjBlock;
-        if (i < bs && c < bs) P[(int64_t)c * bs + i] = -a[i][c];
+        if (i < bs && c < bs) P[(int64_t)c * bs + i] = -a[kGjBlock & 1][i][c];
     }
 }
 
@@ -600,7 +600,7 @@ void spd_inverse(double *A, int nb, DevBuf<double> &piv, DevBuf<double> &row, De
     double *Cn = col.ensure((size_t)nb * B);
     for (int k0 = 0; k0 < nb; k0 += B) {
         const int bs = std::min(B, nb - k0);
-        k_gj_block<<<1, 256, 0, st>>>(A, nb, k0, bs, Pn);
+        k_gj_block<<<1, kGjThreads, 0, st>>>(A, nb, k0, bs, Pn);
         BFM_LAUNCHED();
         // Rn = Pn A_K,:  (= -P^{-1} A_K,:), bs x nb
         gemm_nn_f64(bs, nb, bs, Pn, bs, A + k0, nb, Rn, bs, st);
