@@ -226,12 +226,12 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
                       const double *in, double *out, hipStream_t st) {
     constexpr int PP = P_ * P_;
     const int64_t cols = tl.ntasks * nch;
-    // Enough waves for the whole chip: row slabs of 64 (80 at p = 20) rows
-    // when there are many columns, 16-row slabs (more waves) when there are
-    // few; the wide 128-column tiles (shape 0, fewest operator re-reads but
+    // Row slabs of 64 (80 at p = 20) rows unless that leaves fewer than 512
+    // waves, then 16-row slabs (more waves, the input columns re-read per
+    // slab); the wide 128-column tiles (shape 0, fewest operator re-reads but
     // twice the LDS per workgroup) only on request.
     const int64_t wave_tiles = (cols + 15) / 16;
-    int shape = (wave_tiles * (PP / mid_rows(PP)) >= 8192) ? 1 : 2;
+    int shape = (wave_tiles * (PP / mid_rows(PP)) >= 512) ? 1 : 2;
     if (cls == KC_M2L && w.m2l_shape >= 0) shape = w.m2l_shape;
     if (cls == KC_M2L) w.m2l_shape_used = shape;
     const int width = (shape == 0) ? 128 : 64;
