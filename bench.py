@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--lmax", type=int, default=0)
     ap.add_argument("--m2l-shape", type=int, default=-1, help="M2L launch shape 0..2 (-1: by size)")
-    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=40000)
@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--form", choices=["tuned", "plain"], default="tuned")
     ap.add_argument("--precond-degree", type=int, default=12)
     ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--graph", type=int, default=0, help="tuned form: replay GMRES products from a HIP graph")
+    ap.add_argument("--graph", type=int, default=1, help="tuned form: replay GMRES products from a HIP graph")
     ap.add_argument("--autotune", type=int, default=1, help="tuned form: autotune p, octree depth, M2L shape")
     ap.add_argument("--tune-tol", type=float, default=1e-7)
     ap.add_argument("--learned-steps", type=int, default=0,
