@@ -72,6 +72,7 @@ struct bfm_ctx {
 
     // sorted-order solve data
     bfm::DevBuf<double> src_q, src_w;  // channel monopole strengths, dipole weights
+    bfm::DevBuf<double> src_pk;        // packed five-channel near-field records [n][kDiagRec]
     bfm::DevBuf<double> ysum;           // channel sums
     bfm::DevBuf<double> mii_s, lii_s, b_s, phi_s;
     bool diag_valid = false;            // mii_s / lii_s current for the mesh

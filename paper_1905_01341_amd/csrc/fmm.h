@@ -12,11 +12,17 @@
 
 namespace bfm {
 
+constexpr int kDiagRec = 16;  // doubles per packed five-channel source record
+
 struct Sources {
     int nch = 1;
     bool mono = true, dip = false;
     const double *q = nullptr;  // [nch][n] monopole strengths
     const double *w = nullptr;  // [nch][n] dipole weights (moment w_j n_j)
+    // optional, five channels only: the same sources packed per point for the
+    // near field, kDiagRec doubles each: x, y, z, n_x, n_y, n_z, q1, q2, q3,
+    // w0, w1, w2, w3, w4 (channels 0 and 4 carry no monopole)
+    const double *packed = nullptr;
 };
 
 struct FmmWork {

@@ -275,7 +275,10 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     BFM_LAUNCHED();
     // near field first (writes y), far field adds
     int pi = prof_begin(w, KC_P2P, st);
-    launch_p2p<NCH, MONO, DIP>(t, src, y, st);
+    if (NCH == 5 && src.packed)
+        launch_p2p_packed(t, src.packed, y, st);
+    else
+        launch_p2p<NCH, MONO, DIP>(t, src, y, st);
     prof_end(w, pi, st, (double)(t.npairs_near - t.n) * p2p_flops_per_pair(NCH, MONO, DIP));
     pi = prof_begin(w, KC_P2M, st);
     launch_p2m<P_, NCH, MONO, DIP>(t, src, M, st);

@@ -23,6 +23,9 @@ void launch_l2p(const Tree &t, const double *L, double *y, hipStream_t st);
 template <int NCH, bool MONO, bool DIP>
 void launch_p2p(const Tree &t, const Sources &src, double *y, hipStream_t st);
 
+// y[c][i] = near-field sum of the five packed channels (Sources::packed).
+void launch_p2p_packed(const Tree &t, const double *packed, double *y, hipStream_t st);
+
 // y[c][i] = sum over every other point (all pairs).
 template <int NCH, bool MONO, bool DIP>
 void launch_direct(const Tree &t, const Sources &src, double *y, hipStream_t st);

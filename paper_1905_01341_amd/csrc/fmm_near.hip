@@ -180,6 +180,108 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p(const int4 *__restrict__ it
                                         near_rng + 27 * (int64_t)leaf, px, py, pz, pnx, pny, pnz, n, q, w, y);
 }
 
+// Near field of the five-channel pass from packed source records (one
+// 128-byte record per point, read at wave-uniform addresses: two scalar
+// loads per source instead of one per array). Per pair:
+//   t = n_j . (r_i - r_j) / r^3,  y_0 += w0 t,  y_c += q_c / r + w_c t (c = 1..3),
+//   y_4 += w4 t.
+template <int R, bool SELF>
+__device__ inline void p2p_diag_range(int j0, int j1, const double *__restrict__ pk, const double *xi,
+                                      const double *yi, const double *zi, double (*acc)[5]) {
+    constexpr int B = 2;
+    auto pair = [&](const double(&s)[14]) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const double dx = xi[k] - s[0], dy = yi[k] - s[1], dz = zi[k] - s[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double inv = (!SELF || r2 > 0.0) ? rsqrt_f64(r2) : 0.0;  // j == i excluded
+            const double t = (s[3] * dx + s[4] * dy + s[5] * dz) * (inv * inv * inv);
+            acc[k][0] += s[9] * t;
+            acc[k][1] += s[6] * inv + s[10] * t;
+            acc[k][2] += s[7] * inv + s[11] * t;
+            acc[k][3] += s[8] * inv + s[12] * t;
+            acc[k][4] += s[13] * t;
+        }
+    };
+    int j = j0;
+    for (; j + B <= j1; j += B) {
+        double rec[B][14];
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+#pragma unroll
+            for (int e = 0; e < 14; ++e) rec[u][e] = pk[(int64_t)(j + u) * kDiagRec + e];
+#pragma unroll
+        for (int u = 0; u < B; ++u) pair(rec[u]);
+    }
+    for (; j < j1; ++j) {
+        double rec[14];
+#pragma unroll
+        for (int e = 0; e < 14; ++e) rec[e] = pk[(int64_t)j * kDiagRec + e];
+        pair(rec);
+    }
+}
+
+// The five-channel counterpart of k_p2p (same items, pieces and order).
+template <bool ATOMIC>
+__global__ void __launch_bounds__(kP2PThreads) k_p2p_diag(const int4 *__restrict__ items,
+                                                          const int *__restrict__ leaf_pt,
+                                                          const int2 *__restrict__ near_rng,
+                                                          const int *__restrict__ near_cnt,
+                                                          const double *__restrict__ px,
+                                                          const double *__restrict__ py,
+                                                          const double *__restrict__ pz,
+                                                          const double *__restrict__ pk, int64_t n,
+                                                          double *__restrict__ y) {
+    constexpr int R = kP2PChunk / kP2PThreads;
+    const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
+    const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
+    const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
+    const int leaf = it.x, rc = it.y, s0 = it.z, s1 = it.w;
+    const int l0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
+    const int nr = near_cnt[leaf];
+    const int2 *rng = near_rng + 27 * (int64_t)leaf;
+    const int lane = threadIdx.x;
+    double xi[R], yi[R], zi[R], acc[R][5];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        const bool ok = i < r1;
+        xi[k] = ok ? px[i] : 1e100;  // idle lanes sit far away; never stored
+        yi[k] = ok ? py[i] : 0.0;
+        zi[k] = ok ? pz[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc[k][c] = 0.0;
+    }
+    int cum = 0;
+    for (int g = 0; g < nr && cum < s1; ++g) {
+        const int2 r = rng[g];
+        const int len = r.y - r.x;
+        const int a = r.x + max(0, s0 - cum), b = r.x + min(len, s1 - cum);
+        cum += len;
+        if (a >= b) continue;
+        if (a < r1 && l0 < b) {
+            const int m0 = max(a, l0), m1 = min(b, r1);
+            p2p_diag_range<R, false>(a, m0, pk, xi, yi, zi, acc);
+            p2p_diag_range<R, true>(m0, m1, pk, xi, yi, zi, acc);
+            p2p_diag_range<R, false>(m1, b, pk, xi, yi, zi, acc);
+        } else {
+            p2p_diag_range<R, false>(a, b, pk, xi, yi, zi, acc);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        if (i < r1)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                if (ATOMIC)
+                    unsafeAtomicAdd(y + (int64_t)c * n + i, acc[k][c]);
+                else
+                    y[(int64_t)c * n + i] = acc[k][c];
+            }
+    }
+}
+
 __global__ void k_clear(double *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -226,6 +328,19 @@ void launch_p2p(const Tree &t, const Sources &src, double *y, hipStream_t st) {
                                                            t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
                                                            t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w,
                                                            y);
+    BFM_LAUNCHED();
+}
+
+void launch_p2p_packed(const Tree &t, const double *packed, double *y, hipStream_t st) {
+    if (t.n_near_items <= 0) return;
+    if (t.near_split) {
+        k_clear<<<1024, 256, 0, st>>>(y, (int64_t)5 * t.n);
+        BFM_LAUNCHED();
+    }
+    auto kern = t.near_split ? k_p2p_diag<true> : k_p2p_diag<false>;
+    kern<<<(unsigned)t.n_near_items, kP2PThreads, 0, st>>>(t.near_items.get(), t.leaf_pt.get(), t.near_rng.get(),
+                                                           t.near_cnt.get(), t.px.get(), t.py.get(), t.pz.get(),
+                                                           packed, t.n, y);
     BFM_LAUNCHED();
 }
 

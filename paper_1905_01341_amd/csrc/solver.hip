@@ -148,20 +148,34 @@ void to_original(bfm_ctx *c, const double *in, double *out) {
 __global__ void k_diag_sources(const double *px, const double *py, const double *pz, const double *ps,
                                const double *pnx, const double *pny, const double *pnz,
                                const double *phi, int64_t n, double X, double Y, double Z, double *q,
-                               double *w) {
+                               double *w, double *pk) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double s = ps[i];
     const double nn[3] = {pnx[i], pny[i], pnz[i]};
     const double r[3] = {px[i] - X, py[i] - Y, pz[i] - Z};
+    const double w4 = s * (phi ? phi[i] : 0.0);
     q[i] = 0.0;
     q[4 * n + i] = 0.0;
     w[i] = s;
-    w[4 * n + i] = s * (phi ? phi[i] : 0.0);
+    w[4 * n + i] = w4;
     for (int a = 0; a < 3; ++a) {
         q[(1 + a) * n + i] = -s * nn[a];
         w[(1 + a) * n + i] = s * r[a];
     }
+    // packed record for the near field (layout of Sources::packed)
+    double *rec = pk + i * kDiagRec;
+    rec[0] = px[i];
+    rec[1] = py[i];
+    rec[2] = pz[i];
+    for (int a = 0; a < 3; ++a) {
+        rec[3 + a] = nn[a];
+        rec[6 + a] = -s * nn[a];
+        rec[10 + a] = s * r[a];
+    }
+    rec[9] = s;
+    rec[13] = w4;
+    rec[14] = rec[15] = 0.0;
 }
 
 __global__ void k_diag_finalize(const double *y, const double *px, const double *py, const double *pz,
@@ -197,9 +211,10 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
     double *q = c->src_q.ensure(5 * n);
     double *wd = c->src_w.ensure(5 * n);
     double *y = c->ysum.ensure(5 * n);
+    double *pk = c->src_pk.ensure((size_t)kDiagRec * n);
     k_diag_sources<<<nblk(n, 256), 256, 0, st>>>(t.px.get(), t.py.get(), t.pz.get(), t.ps.get(),
                                                  t.pnx.get(), t.pny.get(), t.pnz.get(), phs, n, X, Y, Z,
-                                                 q, wd);
+                                                 q, wd, pk);
     BFM_LAUNCHED();
     Sources src;
     src.nch = 5;
@@ -207,6 +222,7 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
     src.dip = true;
     src.q = q;
     src.w = wd;
+    src.packed = pk;
     fmm_apply(c->fmm_diag, t, src, y, false, st);
     c->mii_s.ensure(n);
     c->lii_s.ensure(n);
