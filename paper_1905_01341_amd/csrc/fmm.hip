@@ -81,16 +81,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     dbl4 acc[ROWS / 16];
 #pragma unroll
     for (int rb = 0; rb < ROWS / 16; ++rb) acc[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // Operator slab chunks go global -> registers -> LDS (two LDS buffers),
-    // the input columns global -> registers; the loop is unrolled by two so
-    // that chunk c + 1 is in flight in its own registers while chunk c feeds
-    // the MFMAs, with no register copies between the stages.
+    // Operator slab chunks and the input columns go global -> registers ->
+    // LDS (two LDS buffers); the loop is unrolled by three with no register
+    // copies between the stages.
     constexpr int NT = 64 * WAVES;
     constexpr int PER = (kTKC * ROWS + NT - 1) / NT;
     constexpr bool EXACT = PER * NT == kTKC * ROWS;  // every thread moves PER elements
     static_assert(PP % kTKC == 0, "whole chunks");
     constexpr int NC = PP / kTKC;
-    double pa[PER], pb[PER], ba[kTKC / 4], bb[kTKC / 4];
+    // three register sets take turns: while chunk c feeds the MFMAs from LDS,
+    // chunk c + 1 waits in registers for its LDS buffer and chunk c + 2 is
+    // being loaded, so a load has two chunks' MFMA time to arrive
+    double pa[PER], pb[PER], pc[PER], ba[kTKC / 4], bb[kTKC / 4], bc[kTKC / 4];
     auto fetch = [&](int k0, double(&pre)[PER], double(&bv)[kTKC / 4]) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -121,20 +123,28 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     };
     fetch(0, pa, ba);
     stash(0, pa, ba);
+    fetch(min(1, NC - 1) * kTKC, pb, bb);
     __syncthreads();
     // the fetches are unconditional (past the end they repeat the last
     // chunk) so that the memory-counter waits are the same on every path
-    for (int c = 0; c < NC; c += 2) {
-        // even chunk c in buffer 0; chunk c + 1 in flight
-        fetch(min(c + 1, NC - 1) * kTKC, pb, bb);
-        mult(0);
+    for (int c = 0; c < NC; c += 3) {
+        // chunk c in LDS buffer c & 1, c + 1 in (pb, bb); load c + 2 into (pc, bc)
+        fetch(min(c + 2, NC - 1) * kTKC, pc, bc);
+        mult(c & 1);
         if (c + 1 >= NC) break;
-        stash(1, pb, bb);
+        stash((c + 1) & 1, pb, bb);
         __syncthreads();
-        // odd chunk c + 1 in buffer 1; chunk c + 2 in flight
-        fetch(min(c + 2, NC - 1) * kTKC, pa, ba);
-        mult(1);
-        stash(0, pa, ba);
+        // chunk c + 1; c + 2 in (pc, bc); load c + 3 into (pa, ba)
+        fetch(min(c + 3, NC - 1) * kTKC, pa, ba);
+        mult((c + 1) & 1);
+        if (c + 2 >= NC) break;
+        stash(c & 1, pc, bc);
+        __syncthreads();
+        // chunk c + 2; c + 3 in (pa, ba); load c + 4 into (pb, bb)
+        fetch(min(c + 4, NC - 1) * kTKC, pb, bb);
+        mult(c & 1);
+        if (c + 3 >= NC) break;
+        stash((c + 1) & 1, pa, ba);
         __syncthreads();
     }
 #pragma unroll
