@@ -4,8 +4,8 @@
 // build the regular solid harmonics of a point by the three-term recurrences
 // of the box-scaled normalised basis, in registers.
 //
-// Both kernels run one wave per leaf work item (a leaf and up to kP2PChunk of
-// its points), each lane taking kP2PChunk / 64 points, so the grid has about
+// Both kernels run one wave per leaf work item (a leaf and up to kLeafChunk of
+// its points), each lane taking kLeafChunk / 64 points, so the grid has about
 // twice as many waves as the octree has leaves and every wave does the same
 // amount of work.
 #include <cmath>
@@ -16,8 +16,8 @@
 namespace bfm {
 
 constexpr int kTri = kMaxP * (kMaxP + 1) / 2;  // (n, m >= 0) pairs, n < kMaxP
-constexpr int kPPL = kP2PChunk / 64;            // points per lane
-static_assert(kPPL * 64 == kP2PChunk, "whole points per lane");
+constexpr int kPPL = kLeafChunk / 64;            // points per lane
+static_assert(kPPL * 64 == kLeafChunk, "whole points per lane");
 
 // Recurrence of the regular harmonics for degree n > m:
 //   Rt_n^m = ae(n, m) z Rt_{n-1}^m - ab(n, m) r^2 Rt_{n-2}^m,
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
     const int lane = threadIdx.x;
     const int2 it = items[blockIdx.x];
     const int leaf = it.x, rb = it.y;
-    const int re = min(rb + kP2PChunk, leaf_pt[leaf + 1]);
+    const int re = min(rb + kLeafChunk, leaf_pt[leaf + 1]);
     const int64_t box = leaf0 + leaf;
     stage_tables<P_>(rec, sect, lane, 64);
     // slot -> coefficient index in the packed expansion (n^2 + 2m - 1 + imaginary)
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(64) k_l2p(const int2 *__restrict__ items, int6
     const int lane = threadIdx.x;
     const int2 it = items[blockIdx.x];
     const int leaf = it.x, rb = it.y;
-    const int re = min(rb + kP2PChunk, leaf_pt[leaf + 1]);
+    const int re = min(rb + kLeafChunk, leaf_pt[leaf + 1]);
     const int64_t box = leaf0 + leaf;
     const double *L = lexp + box * NCH * PP;
     for (int t = lane; t < NCH * PP; t += 64) Ls[t] = L[t];

@@ -11,7 +11,8 @@
 namespace bfm {
 
 constexpr int kKeyBits = 15;  // bits per axis of the point keys (levels 0..15)
-constexpr int kP2PChunk = 128;   // receivers per leaf work item (two per lane)
+constexpr int kP2PChunk = 128;   // receivers per near-field work item (two per lane)
+constexpr int kLeafChunk = 128;  // points per leaf work item of P2M and L2P
 constexpr int kP2PPiece = 384;   // near-field sources per work item at most (a leaf's source
                                  // list longer than this is split into balanced pieces)
 
@@ -63,7 +64,7 @@ struct Tree {
     // near_rng[leaf][k] = (start, end) for k < near_cnt[leaf] (at most 27)
     DevBuf<int2> near_rng;      // [nleaf][27]
     DevBuf<int> near_cnt;       // [nleaf]
-    // leaf work items: (leaf, first point) of chunks of at most kP2PChunk
+    // leaf work items: (leaf, first point) of chunks of at most kLeafChunk
     // points, in leaf order (P2M, L2P)
     DevBuf<int2> leaf_items;
     int64_t n_leaf_items = 0;

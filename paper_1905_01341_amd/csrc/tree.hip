@@ -466,12 +466,11 @@ __global__ void k_leaf_ranges(int64_t nleaf, int64_t leaf0, const int *leaf_pt, 
     cnt[i] = m;
 }
 
-// Near-field work items: chunks of at most kP2PChunk receivers per leaf,
-// keyed by pair count so the largest run first.
+// Leaf work items (P2M, L2P): chunks of at most kLeafChunk points per leaf.
 __global__ void k_item_count(int64_t nleaf, const int *leaf_pt, int *cnt) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
-    cnt[i] = (leaf_pt[i + 1] - leaf_pt[i] + kP2PChunk - 1) / kP2PChunk;
+    cnt[i] = (leaf_pt[i + 1] - leaf_pt[i] + kLeafChunk - 1) / kLeafChunk;
 }
 
 __global__ void k_item_fill(int64_t nleaf, const int *leaf_pt, const int *off, int2 *items) {
@@ -479,7 +478,7 @@ __global__ void k_item_fill(int64_t nleaf, const int *leaf_pt, const int *off, i
     if (i >= nleaf) return;
     const int r0 = leaf_pt[i], r1 = leaf_pt[i + 1];
     int o = off[i];
-    for (int r = r0; r < r1; r += kP2PChunk, ++o) items[o] = make_int2((int)i, r);
+    for (int r = r0; r < r1; r += kLeafChunk, ++o) items[o] = make_int2((int)i, r);
 }
 
 // near-field sources of leaf i and the number of pieces they are split into
@@ -489,12 +488,14 @@ __device__ inline int leaf_sources(int64_t i, const int2 *rng, const int *rcnt) 
     return src;
 }
 
-__global__ void k_piece_count(int64_t nleaf, const int *leaf_pt, const int2 *rng, const int *rcnt, int *cnt) {
+__global__ void k_piece_count(int64_t nleaf, const int *leaf_pt, const int2 *rng, const int *rcnt, int *cnt,
+                              int *split) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
     const int src = leaf_sources(i, rng, rcnt);
     const int pieces = src > 0 ? (src + kP2PPiece - 1) / kP2PPiece : 1;
     cnt[i] = pieces * ((leaf_pt[i + 1] - leaf_pt[i] + kP2PChunk - 1) / kP2PChunk);
+    if (pieces > 1) split[0] = 1;  // any writer stores the same value
 }
 
 __global__ void k_piece_fill(int64_t nleaf, const int *leaf_pt, const int *off, const int2 *rng, const int *rcnt,
@@ -836,16 +837,21 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
         t.n_leaf_items = ni;
         // near-field items: leaf chunks x balanced pieces of the source list,
         // in leaf (Morton) order
-        k_piece_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                         t.near_cnt.get(), icnt.get());
+        int *dsplit = scr.mo.ensure(1);
+        k_fill_int<<<1, 64, 0, st>>>(dsplit, 1, 0);
         BFM_LAUNCHED();
-        const int64_t nn = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);
+        k_piece_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
+                                                         t.near_cnt.get(), icnt.get(), dsplit);
+        BFM_LAUNCHED();
+        int split = 0;
+        BFM_HIP(hipMemcpyAsync(&split, dsplit, sizeof(int), hipMemcpyDeviceToHost, st));
+        const int64_t nn = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);  // waits for split too
         t.near_items.ensure(nn);
         k_piece_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.near_rng.get(),
                                                         t.near_cnt.get(), t.near_items.get());
         BFM_LAUNCHED();
         t.n_near_items = nn;
-        t.near_split = nn > ni;
+        t.near_split = split != 0;
     }
 
     // M2L lists over levels 2..lmax
