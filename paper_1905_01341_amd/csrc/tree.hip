@@ -522,21 +522,23 @@ __device__ inline void child_range(const uint64_t *box_key, const LevelInfo &li,
     c1 = lower_bound_u64(box_key, li.off[l + 1], li.off[l + 2], (k + 1) << 3);
 }
 
-// mode 0: count M2L pairs per target box; mode 1: write them.
+// mode 0: count the M2L pairs of every (target box, parent-neighbour slot);
+// mode 1: write them. One thread per (box, slot), so a level's boxes give 27
+// times as many threads; the pairs come out ordered by box, then slot.
 __global__ void k_m2l_pairs(int mode, int64_t b0, int64_t b1, LevelInfo li, const uint64_t *box_key,
                             const int *box_level, const int *box_parent, const int *nbr, int *count,
                             const int *offs, int *tsrc, int *tdst, int *top) {
-    int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= b1) return;
-    const int l = box_level[b];
-    int ix, iy, iz;
-    demorton(box_key[b], ix, iy, iz);
-    const int pb = box_parent[b];
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (b1 - b0) * 27) return;
+    const int64_t b = b0 + t / 27;
+    const int s = (int)(t % 27);
+    const int q = nbr[27 * (int64_t)box_parent[b] + s];
     int c = 0;
-    int64_t w = (mode == 1) ? offs[b - b0] : 0;
-    for (int s = 0; s < 27; ++s) {
-        const int q = nbr[27 * (int64_t)pb + s];
-        if (q < 0) continue;
+    if (q >= 0) {
+        const int l = box_level[b];
+        int ix, iy, iz;
+        demorton(box_key[b], ix, iy, iz);
+        int64_t w = (mode == 1) ? offs[t] : 0;
         int64_t c0, c1;
         child_range(box_key, li, l - 1, box_key[q], c0, c1);
         for (int64_t cc = c0; cc < c1; ++cc) {
@@ -553,7 +555,7 @@ __global__ void k_m2l_pairs(int mode, int64_t b0, int64_t b1, LevelInfo li, cons
             ++c;
         }
     }
-    if (mode == 0) count[b - b0] = c;
+    if (mode == 0) count[t] = c;
 }
 
 // Tasks of one level's M2M/L2L: child box c (level l) <-> parent.
@@ -873,20 +875,20 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
         const int64_t b0 = t.lvl_off[2], b1 = t.lvl_off[lmax + 1];
         const int64_t nb = b1 - b0;
         DevBuf<int> &count = scr.count, &offs = scr.offs;
-        count.ensure(nb);
-        offs.ensure(nb);
-        k_m2l_pairs<<<nblk(nb, 128), 128, 0, st>>>(0, b0, b1, li, t.box_key.get(), t.box_level.get(),
-                                                   t.box_parent.get(), t.nbr.get(), count.get(),
-                                                   nullptr, nullptr, nullptr, nullptr);
+        count.ensure(27 * nb);
+        offs.ensure(27 * nb);
+        k_m2l_pairs<<<nblk(27 * nb, 256), 256, 0, st>>>(0, b0, b1, li, t.box_key.get(), t.box_level.get(),
+                                                       t.box_parent.get(), t.nbr.get(), count.get(),
+                                                       nullptr, nullptr, nullptr, nullptr);
         BFM_LAUNCHED();
-        const int64_t total = exclusive_scan(count.get(), offs.get(), nb, st, tmp);
+        const int64_t total = exclusive_scan(count.get(), offs.get(), 27 * nb, st, tmp);
         DevBuf<int> &ts = scr.ts, &td = scr.td, &to = scr.to;
         ts.ensure(total + 1);
         td.ensure(total + 1);
         to.ensure(total + 1);
-        k_m2l_pairs<<<nblk(nb, 128), 128, 0, st>>>(1, b0, b1, li, t.box_key.get(), t.box_level.get(),
-                                                   t.box_parent.get(), t.nbr.get(), count.get(),
-                                                   offs.get(), ts.get(), td.get(), to.get());
+        k_m2l_pairs<<<nblk(27 * nb, 256), 256, 0, st>>>(1, b0, b1, li, t.box_key.get(), t.box_level.get(),
+                                                       t.box_parent.get(), t.nbr.get(), count.get(),
+                                                       offs.get(), ts.get(), td.get(), to.get());
         BFM_LAUNCHED();
         group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, scr, st);
     }
