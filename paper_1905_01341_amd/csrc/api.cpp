@@ -113,6 +113,8 @@ void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm
         loc.t_guess_ms = t.stop_ms();
     }
     const bool use_guess = guess != BFM_GUESS_ZERO;
+    // the coarse space needs only the geometry: build it beside the diagonal pass
+    if (c->opt.precond == BFM_PRECOND_SH_COARSE && c->pre.nd > 0) coarse_launch(c);
     {
         Timer t(c->stream);
         diagonal_pass(c, phi_dev);
@@ -194,6 +196,12 @@ int bfm_destroy(bfm_ctx *c) {
         step_free(c);
         graph_invalidate(c);
         if (c->host_small) (void)hipHostFree(c->host_small);
+        if (c->side) {
+            (void)hipStreamSynchronize(c->side);
+            (void)hipStreamDestroy(c->side);
+        }
+        if (c->ev_geom) (void)hipEventDestroy(c->ev_geom);
+        if (c->ev_coarse) (void)hipEventDestroy(c->ev_coarse);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
     });

@@ -48,6 +48,12 @@ struct bfm_ctx {
     bfm_options opt{};
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream (default priority) for the coarse-space build, which runs
+    // beside the diagonal pass; ev_geom orders it after the geometry,
+    // ev_coarse orders GMRES after it
+    hipStream_t side = nullptr;
+    hipEvent_t ev_geom = nullptr, ev_coarse = nullptr;
+    bool coarse_pending = false;  // a coarse build for the current geometry is in flight on `side`
     bool own_stream = false;
 
     // mesh (original vertex order)
@@ -119,8 +125,12 @@ void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st, bool
 void precond_build(bfm_ctx *c);
 void precond_radii(bfm_ctx *c);
 void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);
-// coarse correction of the two-level form (needs the diagonals of the current mesh)
-void coarse_build(bfm_ctx *c);
+// coarse correction of the two-level form on stream st (geometry of the
+// current mesh only)
+void coarse_build(bfm_ctx *c, hipStream_t st);
+// start coarse_build on the side stream after the work queued so far on the
+// main stream (the geometry); GMRES waits for it
+void coarse_launch(bfm_ctx *c);
 // in-place inverse of an SPD n x n column-major device matrix (blocked Gauss-Jordan)
 void spd_inverse(double *A, int n, DevBuf<double> &piv, DevBuf<double> &row, DevBuf<double> &col,
                  hipStream_t st);

@@ -351,20 +351,27 @@ __global__ void k_coarse_geom(const double *xyz, const double *s, int nd, double
 }
 
 // U_j = s_j (sum_{i in a, i != j} s_i / (4 pi r_ij) + L_jj) for vertex j of
-// bubble a (caller order). Grid (vertex blocks, bubbles); the bubble's
-// points pass through LDS in chunks. 1/r: the hardware estimate refined by
-// one Newton step (relative error ~1e-15); the pair i = j (r = 0) is masked.
-__global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const double *s, const double *lii, int nd,
-                                                  double *U) {
-    constexpr int CH = 512;
-    __shared__ double sx[CH], sy[CH], sz[CH], ss[CH];
+// bubble a (caller order), with the singular diagonal L_jj in its
+// translation-free form summed over the own bubble only:
+//   L_jj = n_j . [sum_i M_ji (r_i - r_j) - sum_i L_ji n_i],
+//   M_ji = s_i n_i . (r_j - r_i) / (4 pi r^3),  L_ji = s_i / (4 pi r).
+// (The other bubbles' closed surfaces contribute only their discretisation
+// error to these sums; the coarse space is a preconditioner, so the own
+// bubble suffices and the build does not wait for the diagonal pass.)
+// Grid (vertex blocks, bubbles); the bubble's points pass through LDS in
+// chunks. 1/r: the hardware estimate refined by one Newton step (relative
+// error ~1e-15); the pair i = j (r = 0) is masked.
+__global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const double *s, const double *nrm, int64_t nv,
+                                                  int nd, double *U) {
+    constexpr int CH = 256;
+    __shared__ double sx[CH], sy[CH], sz[CH], ss[CH], snx[CH], sny[CH], snz[CH];
     const int b = blockIdx.y;
     const int j = blockIdx.x * 256 + threadIdx.x;
     const int64_t base = (int64_t)b * nd;
     const bool ok = j < nd;
-    const double xj = ok ? xyz[3 * (base + j)] : 0.0, yj = ok ? xyz[3 * (base + j) + 1] : 0.0,
-                 zj = ok ? xyz[3 * (base + j) + 2] : 0.0;
-    double acc0 = 0.0, acc1 = 0.0;
+    const int64_t oj = base + (ok ? j : 0);
+    const double xj = xyz[3 * oj], yj = xyz[3 * oj + 1], zj = xyz[3 * oj + 2];
+    double acc = 0.0, ax = 0.0, ay = 0.0, az = 0.0;  // sum s_i / r; sum M-type vector - L-type vector
     for (int c0 = 0; c0 < nd; c0 += CH) {
         const int cn = min(CH, nd - c0);
         __syncthreads();
@@ -374,32 +381,31 @@ __global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const doubl
             sy[t] = xyz[3 * o + 1];
             sz[t] = xyz[3 * o + 2];
             ss[t] = s[o];
+            snx[t] = nrm[o];
+            sny[t] = nrm[nv + o];
+            snz[t] = nrm[2 * nv + o];
         }
         __syncthreads();
-        int t = 0;
-        for (; t + 2 <= cn; t += 2) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const double dx = xj - sx[t + u], dy = yj - sy[t + u], dz = zj - sz[t + u];
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double y = __builtin_amdgcn_rsq(r2);
-                const double inv = fma(0.5 * y, fma(-r2 * y, y, 1.0), y);
-                const double v = (c0 + t + u == j) ? 0.0 : ss[t + u] * inv;
-                if (u == 0)
-                    acc0 += v;
-                else
-                    acc1 += v;
-            }
-        }
-        for (; t < cn; ++t) {
-            const double dx = xj - sx[t], dy = yj - sy[t], dz = zj - sz[t];
+        for (int t = 0; t < cn; ++t) {
+            const double dx = xj - sx[t], dy = yj - sy[t], dz = zj - sz[t];  // r_j - r_i
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double y = __builtin_amdgcn_rsq(r2);
-            const double inv = fma(0.5 * y, fma(-r2 * y, y, 1.0), y);
-            acc0 += (c0 + t == j) ? 0.0 : ss[t] * inv;
+            double inv = fma(0.5 * y, fma(-r2 * y, y, 1.0), y);
+            inv = (c0 + t == j) ? 0.0 : inv;
+            const double si = ss[t] * inv;  // s_i / r
+            acc += si;
+            // s_i n_i.(r_j - r_i) / r^3 (r_i - r_j) - s_i / r n_i
+            const double g = (snx[t] * dx + sny[t] * dy + snz[t] * dz) * si * inv * inv;
+            ax -= g * dx + si * snx[t];
+            ay -= g * dy + si * sny[t];
+            az -= g * dz + si * snz[t];
         }
     }
-    if (ok) U[base + j] = s[base + j] * ((acc0 + acc1) * (1.0 / (4.0 * 3.14159265358979323846)) + lii[base + j]);
+    if (ok) {
+        const double k4 = 1.0 / (4.0 * 3.14159265358979323846);
+        const double ljj = (nrm[oj] * ax + nrm[nv + oj] * ay + nrm[2 * nv + oj] * az) * k4;
+        U[oj] = s[oj] * (acc * k4 + ljj);
+    }
 }
 
 // A (column-major nb x nb): off-diagonal point-monopole couplings; the
@@ -618,25 +624,34 @@ void spd_inverse(double *A, int nb, DevBuf<double> &piv, DevBuf<double> &row, De
     }
 }
 
-void coarse_build(bfm_ctx *c) {
+void coarse_build(bfm_ctx *c, hipStream_t st) {
     Precond &P = c->pre;
-    hipStream_t st = c->stream;
     const int nd = P.nd, nb = c->nb;
-    BFM_CHECK(c->diag_valid, BFM_EINVAL, "coarse space needs the diagonals of the current mesh");
+    P.csum.ensure(3 * (size_t)nb);  // used by precond_apply
+    P.cy.ensure(nb);
     double *cen = P.ccen.ensure(3 * (size_t)nb), *area = P.carea.ensure(nb);
     k_coarse_geom<<<nb, 256, 0, st>>>(c->xyz.get(), c->s.get(), nd, cen, area);
     BFM_LAUNCHED();
-    double *lii = P.Y.ensure((size_t)nd * nb);  // work: L_ii in caller order
-    to_original(c, c->lii_s.get(), lii);
     double *U = P.U.ensure((size_t)nd * nb);
-    k_coarse_u<<<dim3(nblk(nd, 256), nb), 256, 0, st>>>(c->xyz.get(), c->s.get(), lii, nd, U);
+    k_coarse_u<<<dim3(nblk(nd, 256), nb), 256, 0, st>>>(c->xyz.get(), c->s.get(), c->nrm.get(), c->nv, nd, U);
     BFM_LAUNCHED();
     double *A = P.Ainv.ensure((size_t)nb * nb);
     k_coarse_matrix<<<nblk((int64_t)nb * nb, 256), 256, 0, st>>>(cen, area, U, nd, nb, A);
     BFM_LAUNCHED();
     spd_inverse(A, nb, P.gj_piv, P.gj_row, P.gj_col, st);
-    P.csum.ensure(3 * (size_t)nb);
-    P.cy.ensure(nb);
+}
+
+void coarse_launch(bfm_ctx *c) {
+    if (!c->side) {
+        BFM_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        BFM_HIP(hipEventCreateWithFlags(&c->ev_geom, hipEventDisableTiming));
+        BFM_HIP(hipEventCreateWithFlags(&c->ev_coarse, hipEventDisableTiming));
+    }
+    BFM_HIP(hipEventRecord(c->ev_geom, c->stream));
+    BFM_HIP(hipStreamWaitEvent(c->side, c->ev_geom, 0));
+    coarse_build(c, c->side);
+    BFM_HIP(hipEventRecord(c->ev_coarse, c->side));
+    c->coarse_pending = true;
 }
 
 }  // namespace bfm

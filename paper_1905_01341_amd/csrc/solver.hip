@@ -492,7 +492,14 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
         BFM_CHECK(c->pre.nd > 0, BFM_EINVAL, "the harmonic preconditioner needs bfm_set_sphere_template");
         precond_build(c);
         precond_radii(c);
-        if (c->opt.precond == BFM_PRECOND_SH_COARSE) coarse_build(c);
+        if (c->opt.precond == BFM_PRECOND_SH_COARSE) {
+            if (c->coarse_pending) {  // built beside the diagonal pass
+                BFM_HIP(hipStreamWaitEvent(st, c->ev_coarse, 0));
+                c->coarse_pending = false;
+            } else {
+                coarse_build(c, st);
+            }
+        }
         Z = c->zbuf.ensure(n);
         Tv = c->tbuf.ensure(n);
     }
