@@ -183,6 +183,21 @@ int bfm_create(const bfm_options *opt, bfm_ctx **out) {
             }
             c->own_stream = true;
         }
+        {
+            hipError_t e = hipStreamCreateWithFlags(&c->near, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm.ev_fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm.ev_join, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm_diag.ev_fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm_diag.ev_join, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                if (c->own_stream) (void)hipStreamDestroy(c->stream);
+                if (c->near) (void)hipStreamDestroy(c->near);
+                delete c;
+                fail(BFM_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+            }
+            c->fmm.near = c->near;
+            c->fmm_diag.near = c->near;
+        }
         *out = c;
     });
 }
@@ -199,6 +214,14 @@ int bfm_destroy(bfm_ctx *c) {
         if (c->side) {
             (void)hipStreamSynchronize(c->side);
             (void)hipStreamDestroy(c->side);
+        }
+        if (c->near) {
+            (void)hipStreamSynchronize(c->near);
+            (void)hipStreamDestroy(c->near);
+        }
+        for (bfm::FmmWork *w : {&c->fmm, &c->fmm_diag}) {
+            if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
+            if (w->ev_join) (void)hipEventDestroy(w->ev_join);
         }
         if (c->ev_geom) (void)hipEventDestroy(c->ev_geom);
         if (c->ev_coarse) (void)hipEventDestroy(c->ev_coarse);

@@ -54,6 +54,7 @@ struct bfm_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_geom = nullptr, ev_coarse = nullptr;
     bool coarse_pending = false;  // a coarse build for the current geometry is in flight on `side`
+    hipStream_t near = nullptr;   // near-field stream of both fast multipole products (default priority)
     bool own_stream = false;
 
     // mesh (original vertex order)

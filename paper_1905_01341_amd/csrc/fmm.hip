@@ -283,13 +283,20 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     BFM_LAUNCHED();
     k_zero<<<1024, 256, 0, st>>>(L, (int64_t)ncoef);
     BFM_LAUNCHED();
-    // near field first (writes y), far field adds
-    int pi = prof_begin(w, KC_P2P, st);
+    // near field (writes y) on the near-field stream when there is one,
+    // beside the far-field chain; the L2P adds into y after it
+    hipStream_t ns = w.near ? w.near : st;
+    if (ns != st) {
+        BFM_HIP(hipEventRecord(w.ev_fork, st));
+        BFM_HIP(hipStreamWaitEvent(ns, w.ev_fork, 0));
+    }
+    int pi = prof_begin(w, KC_P2P, ns);
     if (NCH == 5 && src.packed)
-        launch_p2p_packed(t, src.packed, y, st);
+        launch_p2p_packed(t, src.packed, y, ns);
     else
-        launch_p2p<NCH, MONO, DIP>(t, src, y, st);
-    prof_end(w, pi, st, (double)(t.npairs_near - t.n) * p2p_flops_per_pair(NCH, MONO, DIP));
+        launch_p2p<NCH, MONO, DIP>(t, src, y, ns);
+    prof_end(w, pi, ns, (double)(t.npairs_near - t.n) * p2p_flops_per_pair(NCH, MONO, DIP));
+    if (ns != st) BFM_HIP(hipEventRecord(w.ev_join, ns));
     pi = prof_begin(w, KC_P2M, st);
     launch_p2m<P_, NCH, MONO, DIP>(t, src, M, st);
     prof_end(w, pi, st, 0.0);
@@ -298,6 +305,7 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     translate<P_>(w, KC_M2L, t.m2l, NCH, false, w.ops_m2l.get(), M, L, st);
     for (int l = 3; l <= lmax; ++l)
         translate<P_>(w, KC_M2M_L2L, *t.m2m[l], NCH, true, w.ops_l2l.get(), L, L, st);
+    if (ns != st) BFM_HIP(hipStreamWaitEvent(st, w.ev_join, 0));
     pi = prof_begin(w, KC_L2P, st);
     launch_l2p<P_, NCH>(t, L, y, st);
     prof_end(w, pi, st, 0.0);
