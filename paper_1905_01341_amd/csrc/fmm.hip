@@ -285,7 +285,9 @@ static void run_fmm(FmmWork &w, const Tree &tc, const Sources &src, double *y, h
     BFM_LAUNCHED();
     // near field (writes y) on the near-field stream when there is one,
     // beside the far-field chain; the L2P adds into y after it
-    hipStream_t ns = w.near ? w.near : st;
+    // (kernel timing runs them one after the other, so that each kernel's
+    // events measure it alone)
+    hipStream_t ns = (w.near && !(w.prof && w.prof->on)) ? w.near : st;
     if (ns != st) {
         BFM_HIP(hipEventRecord(w.ev_fork, st));
         BFM_HIP(hipStreamWaitEvent(ns, w.ev_fork, 0));
