@@ -257,6 +257,11 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
         BFM_CHECK(nv >= 4 && nt >= 4, BFM_EINVAL, "a closed surface needs >= 4 vertices and triangles");
         BFM_CHECK(nv < (int64_t)1 << 30 && nt < (int64_t)1 << 30, BFM_EINVAL, "mesh too large");
         BFM_CHECK(nb >= 0, BFM_EINVAL, "negative bubble count");
+        if (c->side) {  // a coarse build in flight reads the buffers replaced below
+            DeviceScope ds(c->device);
+            BFM_HIP(hipStreamSynchronize(c->side));
+            c->coarse_pending = false;
+        }
         if (nb > 1) BFM_CHECK(vtx_off && tri_off, BFM_EINVAL, "bubble ranges required when nb > 1");
         DeviceScope ds(c->device);
         std::vector<int64_t> vo, to;
@@ -340,6 +345,7 @@ int bfm_set_positions(bfm_ctx *c, const double *xyz) {
         BFM_CHECK(c && xyz, BFM_EINVAL, "null argument");
         BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
         DeviceScope ds(c->device);
+        coarse_join(c);  // a coarse build in flight reads the positions
         BFM_HIP(hipMemcpyAsync(c->xyz.get(), xyz, sizeof(double) * 3 * c->nv, hipMemcpyHostToDevice,
                                c->stream));
         BFM_HIP(hipStreamSynchronize(c->stream));
@@ -352,6 +358,7 @@ int bfm_set_positions_dev(bfm_ctx *c, const double *xyz) {
         BFM_CHECK(c && xyz, BFM_EINVAL, "null argument");
         BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
         DeviceScope ds(c->device);
+        coarse_join(c);  // a coarse build in flight reads the positions
         BFM_HIP(hipMemcpyAsync(c->xyz.get(), xyz, sizeof(double) * 3 * c->nv, hipMemcpyDeviceToDevice,
                                c->stream));
         invalidate_positions(c);

@@ -132,6 +132,8 @@ void coarse_build(bfm_ctx *c, hipStream_t st);
 // start coarse_build on the side stream after the work queued so far on the
 // main stream (the geometry); GMRES waits for it
 void coarse_launch(bfm_ctx *c);
+// order the main stream after a coarse build in flight (no-op if none)
+void coarse_join(bfm_ctx *c);
 // in-place inverse of an SPD n x n column-major device matrix (blocked Gauss-Jordan)
 void spd_inverse(double *A, int n, DevBuf<double> &piv, DevBuf<double> &row, DevBuf<double> &col,
                  hipStream_t st);

@@ -641,7 +641,14 @@ void coarse_build(bfm_ctx *c, hipStream_t st) {
     spd_inverse(A, nb, P.gj_piv, P.gj_row, P.gj_col, st);
 }
 
+void coarse_join(bfm_ctx *c) {
+    if (!c->coarse_pending) return;
+    BFM_HIP(hipStreamWaitEvent(c->stream, c->ev_coarse, 0));
+    c->coarse_pending = false;
+}
+
 void coarse_launch(bfm_ctx *c) {
+    coarse_join(c);  // an earlier build that nobody waited for (a solve that failed)
     if (!c->side) {
         BFM_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         BFM_HIP(hipEventCreateWithFlags(&c->ev_geom, hipEventDisableTiming));

@@ -493,12 +493,10 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
         precond_build(c);
         precond_radii(c);
         if (c->opt.precond == BFM_PRECOND_SH_COARSE) {
-            if (c->coarse_pending) {  // built beside the diagonal pass
-                BFM_HIP(hipStreamWaitEvent(st, c->ev_coarse, 0));
-                c->coarse_pending = false;
-            } else {
+            if (c->coarse_pending)  // built beside the diagonal pass
+                coarse_join(c);
+            else
                 coarse_build(c, st);
-            }
         }
         Z = c->zbuf.ensure(n);
         Tv = c->tbuf.ensure(n);

@@ -257,6 +257,26 @@ def test_two_level_preconditioned_solve_cluster(c100):
     assert i3["converged"] and rel(q3, q4) < 1e-8
 
 
+def test_two_level_solve_after_a_failed_solve(c100):
+    """The coarse space is built on a second stream beside the diagonal pass.
+    A solve that stops at gmres_maxit (an error) leaves that build without a
+    waiter; moving the vertices and solving again must still be exact."""
+    cl, phi, s, n, rows = c100
+    two = _solver(cl, p=16, gmres_tol=1e-10, gmres_maxit=1, precond=bfm.PRECOND_SH_COARSE,
+                  precond_degree=12)
+    with pytest.raises(bfm.BfmError):
+        two.solve(phi)
+    xyz = cl.xyz * 0.99
+    two.set_positions(xyz)
+    two.set_options(gmres_maxit=500)
+    q1, i1 = two.solve(phi)
+    fresh = _solver(cl, p=16, gmres_tol=1e-10, precond=bfm.PRECOND_SH_COARSE, precond_degree=12)
+    fresh.set_positions(xyz)
+    q2, i2 = fresh.solve(phi)
+    assert i1["converged"] and i2["converged"]
+    assert i1["iterations"] == i2["iterations"] and rel(q1, q2) < 1e-10, (i1, i2, rel(q1, q2))
+
+
 def test_sphere_template_validation():
     cl, phi = wl.make("single")
     sv = bfm.Solver()
