@@ -75,7 +75,8 @@ static void invalidate_positions(bfm_ctx *c) {
     c->diag_valid = false;
 }
 
-// Timing with HIP events on the handle's stream.
+// Timing with HIP events on the handle's stream: stop() only records, ms()
+// waits for the stop event, so a phase boundary does not drain the stream.
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t st;
@@ -84,12 +85,16 @@ struct Timer {
         BFM_HIP(hipEventCreate(&b));
         BFM_HIP(hipEventRecord(a, st));
     }
-    double stop_ms() {
-        BFM_HIP(hipEventRecord(b, st));
+    void stop() { BFM_HIP(hipEventRecord(b, st)); }
+    double ms() {
         BFM_HIP(hipEventSynchronize(b));
-        float ms = 0.f;
-        BFM_HIP(hipEventElapsedTime(&ms, a, b));
-        return ms;
+        float v = 0.f;
+        BFM_HIP(hipEventElapsedTime(&v, a, b));
+        return v;
+    }
+    double stop_ms() {
+        stop();
+        return ms();
     }
     ~Timer() {
         if (a) (void)hipEventDestroy(a);
@@ -102,32 +107,33 @@ void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm
               "use_guess must be BFM_GUESS_ZERO, BFM_GUESS_GIVEN or BFM_GUESS_LEARNED");
     bfm_solve_info loc{};
     const int64_t n = c->nv;
-    {
-        Timer t(c->stream);
-        ensure_tree(c);
-        loc.t_tree_ms = t.stop_ms();
-    }
-    if (guess == BFM_GUESS_LEARNED) {
-        Timer t(c->stream);
-        mlp_guess(c, phi_dev, q_dev);
-        loc.t_guess_ms = t.stop_ms();
-    }
+    // phase timers only record events; their times are read once at the end
+    Timer t_tree(c->stream);
+    ensure_tree(c);
+    t_tree.stop();
+    Timer t_guess(c->stream);
+    if (guess == BFM_GUESS_LEARNED) mlp_guess(c, phi_dev, q_dev);
+    t_guess.stop();
     const bool use_guess = guess != BFM_GUESS_ZERO;
-    // the coarse space needs only the geometry: build it beside the diagonal pass
-    if (c->opt.precond == BFM_PRECOND_SH_COARSE && c->pre.nd > 0) coarse_launch(c);
-    {
-        Timer t(c->stream);
-        diagonal_pass(c, phi_dev);
-        loc.t_diag_ms = t.stop_ms();
-    }
-    {
-        Timer t(c->stream);
-        double *x = c->x_s.ensure(n);
-        if (use_guess) to_sorted(c, q_dev, x);
-        gmres_sorted(c, x, use_guess, &loc);
-        to_original(c, x, q_dev);
-        loc.t_solve_ms = t.stop_ms();
-    }
+    // the coarse space needs only the geometry: it is built on a second stream
+    // beside the diagonal pass, from the point marked here; its launches are
+    // issued after the pass's, so that the pass is queued first
+    const bool coarse = c->opt.precond == BFM_PRECOND_SH_COARSE && c->pre.nd > 0;
+    if (coarse) coarse_mark(c);
+    Timer t_diag(c->stream);
+    diagonal_pass(c, phi_dev);
+    t_diag.stop();
+    if (coarse) coarse_launch(c);
+    Timer t_solve(c->stream);
+    double *x = c->x_s.ensure(n);
+    if (use_guess) to_sorted(c, q_dev, x);
+    gmres_sorted(c, x, use_guess, &loc);
+    to_original(c, x, q_dev);
+    t_solve.stop();
+    loc.t_tree_ms = t_tree.ms();
+    loc.t_guess_ms = guess == BFM_GUESS_LEARNED ? t_guess.ms() : 0.0;
+    loc.t_diag_ms = t_diag.ms();
+    loc.t_solve_ms = t_solve.ms();
     if (info) *info = loc;
     if (!loc.converged) fail(BFM_ENOCONV, "GMRES reached gmres_maxit before the tolerance");
 }

@@ -54,6 +54,7 @@ struct bfm_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_geom = nullptr, ev_coarse = nullptr;
     bool coarse_pending = false;  // a coarse build for the current geometry is in flight on `side`
+    bool coarse_marked = false;   // ev_geom marks the geometry a coarse build will read
     hipStream_t near = nullptr;   // near-field stream of both fast multipole products (default priority)
     bool own_stream = false;
 
@@ -129,8 +130,10 @@ void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);
 // coarse correction of the two-level form on stream st (geometry of the
 // current mesh only)
 void coarse_build(bfm_ctx *c, hipStream_t st);
-// start coarse_build on the side stream after the work queued so far on the
-// main stream (the geometry); GMRES waits for it
+// coarse_mark records the point on the main stream after which the geometry
+// is ready; coarse_launch then queues coarse_build on the side stream from
+// that point (marking now if nothing is marked); GMRES waits for it
+void coarse_mark(bfm_ctx *c);
 void coarse_launch(bfm_ctx *c);
 // order the main stream after a coarse build in flight (no-op if none)
 void coarse_join(bfm_ctx *c);

@@ -647,7 +647,7 @@ void coarse_join(bfm_ctx *c) {
     c->coarse_pending = false;
 }
 
-void coarse_launch(bfm_ctx *c) {
+void coarse_mark(bfm_ctx *c) {
     coarse_join(c);  // an earlier build that nobody waited for (a solve that failed)
     if (!c->side) {
         BFM_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
@@ -655,6 +655,12 @@ void coarse_launch(bfm_ctx *c) {
         BFM_HIP(hipEventCreateWithFlags(&c->ev_coarse, hipEventDisableTiming));
     }
     BFM_HIP(hipEventRecord(c->ev_geom, c->stream));
+    c->coarse_marked = true;
+}
+
+void coarse_launch(bfm_ctx *c) {
+    if (!c->coarse_marked) coarse_mark(c);
+    c->coarse_marked = false;
     BFM_HIP(hipStreamWaitEvent(c->side, c->ev_geom, 0));
     coarse_build(c, c->side);
     BFM_HIP(hipEventRecord(c->ev_coarse, c->side));

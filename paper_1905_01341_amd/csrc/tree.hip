@@ -659,22 +659,47 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
     }
 }
 
+// Workgroup-tile prefix of one (channel count, tile width) shape:
+// tile_off[o] = sum over o' < o of ceil(cols(o') / width), cols(o) = tasks of
+// operator o times nch. One workgroup scans the operators 256 at a time.
+__global__ void __launch_bounds__(256) k_tile_off(const int *op_off, int nops, int nch, int width,
+                                                  int *tile_off) {
+    __shared__ int s[256];
+    const int tid = threadIdx.x;
+    int carry = 0;
+    for (int base = 0; base < nops; base += 256) {
+        const int o = base + tid;
+        const int v = (o < nops) ? ((op_off[o + 1] - op_off[o]) * nch + width - 1) / width : 0;
+        s[tid] = v;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int t = (tid >= d) ? s[tid - d] : 0;
+            __syncthreads();
+            s[tid] += t;
+            __syncthreads();
+        }
+        if (o < nops) tile_off[o] = carry + s[tid] - v;
+        carry += s[255];
+        __syncthreads();
+    }
+    if (tid == 0) tile_off[nops] = carry;
+}
+
 void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st) {
     BFM_CHECK(nch >= 1 && nch < 8 && (width == 64 || width == 128), BFM_EINVAL, "tile shape out of range");
     const int sl = TaskList::slot(nch, width);
     if (tl.tiles_ready[sl]) return;
+    // the tile count (the grid size) from the host copy of the operator
+    // offsets; the prefix itself is scanned on the device, in stream order, so
+    // that the first product of a new tree does not wait for the device
     int run = 0;
-    std::vector<int> pre(tl.nops + 1);
     for (int o = 0; o < tl.nops; ++o) {
-        pre[o] = run;
         const int cols = (tl.op_off_h[o + 1] - tl.op_off_h[o]) * nch;
         run += (cols + width - 1) / width;
     }
-    pre[tl.nops] = run;
     tl.tile_off[sl].ensure(tl.nops + 1);
-    BFM_HIP(hipMemcpyAsync(tl.tile_off[sl].get(), pre.data(), sizeof(int) * (tl.nops + 1),
-                           hipMemcpyHostToDevice, st));
-    BFM_HIP(hipStreamSynchronize(st));
+    k_tile_off<<<1, 256, 0, st>>>(tl.op_off.get(), tl.nops, nch, width, tl.tile_off[sl].get());
+    BFM_LAUNCHED();
     tl.ntiles[sl] = run;
     tl.tiles_ready[sl] = true;
 }
