@@ -16,6 +16,13 @@ __device__ inline double rsqrt_f64(double x) {
     return fma(0.5 * y, e, y);
 }
 
+// -2/sqrt(x): the same Newton step written as y (x y^2 - 3), one operation
+// fewer; the factor -2 is taken out of the sums once at the end.
+__device__ inline double rsqrt_m2_f64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * fma(x * y, y, -3.0);
+}
+
 constexpr int kP2PThreads = 64;
 constexpr int kXcdCount = 8;  // accelerator complex dies of an MI355X
 
@@ -282,6 +289,130 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_diag(const int4 *__restrict
     }
 }
 
+// Symmetric near field of one channel of monopoles (the kernel 1/r is
+// symmetric): every unordered pair of points is visited once and its two
+// terms go to both points. Work item (leaf, r0, s0, s1): receivers [r0, r1)
+// of the leaf (kSymChunk, four per lane) against positions s0..s1-1 of the
+// leaf's near ranges clipped to start at r0. The first r1 - r0 positions are
+// the chunk itself (pieces of the diagonal block, one-sided, j == i
+// excluded); the later ones (the leaf's later points and the neighbour leaves
+// with higher Morton keys) are summed both ways. The lower-keyed neighbours
+// reach these receivers from their own items, so each pair is summed once.
+// Sources of a two-sided piece pass in blocks of 64 through LDS: at step t
+// lane l takes source (l + t) mod 64, so the lanes hold 64 distinct sources
+// at every step and each adds its terms for that source to the source's LDS
+// slot; a block's slots then go to the output with one atomic add each.
+// (The block is kept as two arrays of 16-byte (x, y) and (z, q) pairs: 64
+// lanes reading consecutive 16-byte records touch every LDS bank once.)
+template <int R>
+__device__ inline void p2p_sym_block(const double2 *sxy, const double2 *szq, double *sacc, const double *xi,
+                                     const double *yi, const double *zi, const double *qi, double (*acc)[1]) {
+    const int lane = threadIdx.x;
+#pragma unroll 2
+    for (int t = 0; t < kP2PThreads; ++t) {
+        const int s = (lane + t) & (kP2PThreads - 1);
+        const double2 a = sxy[s], b = szq[s];
+        double c = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const double dx = xi[k] - a.x, dy = yi[k] - a.y, dz = zi[k] - b.x;
+            const double inv = rsqrt_m2_f64(dx * dx + dy * dy + dz * dz);  // -2 / r
+            acc[k][0] = fma(b.y, inv, acc[k][0]);
+            c = fma(qi[k], inv, c);
+        }
+        atomicAdd(sacc + s, c);
+    }
+}
+
+// One item with R = ceil((r1 - r0) / 64) receivers per lane, so that a short
+// chunk runs no all-idle receiver groups.
+template <int R>
+__device__ inline void p2p_sym_item(int leaf, int r0, int r1, int s0, int s1, const int2 *__restrict__ near_rng,
+                                    const int *__restrict__ near_cnt, const double *__restrict__ px,
+                                    const double *__restrict__ py, const double *__restrict__ pz, int64_t n,
+                                    const double *__restrict__ q, double *__restrict__ y, double2 *sxy,
+                                    double2 *szq, double *sacc) {
+    const int lane = threadIdx.x;
+    double xi[R], yi[R], zi[R], qi[R], acc[R][1];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = r0 + lane + k * kP2PThreads;
+        const bool ok = i < r1;
+        xi[k] = ok ? px[i] : 1e100;  // idle lanes sit far away with no weight; never stored
+        yi[k] = ok ? py[i] : 0.0;
+        zi[k] = ok ? pz[i] : 0.0;
+        qi[k] = ok ? q[i] : 0.0;
+        acc[k][0] = 0.0;
+    }
+    double scale = 1.0;
+    if (s1 <= r1 - r0) {
+        // diagonal block: one-sided over the chunk's own points
+        p2p_range<1, true, false, R, true>(r0 + s0, r0 + s1, px, py, pz, nullptr, nullptr, nullptr, n, q, nullptr,
+                                           xi, yi, zi, acc);
+    } else {
+        scale = -0.5;  // the two-sided sums hold -2 / r
+        const int2 *rng = near_rng + 27 * (int64_t)leaf;
+        const int nr = near_cnt[leaf];
+        for (int base = s0; base < s1; base += kP2PThreads) {
+            // this lane's source: position base + lane of the clipped list
+            const int p = base + lane;
+            int j = -1, cum = 0;
+            for (int g = 0; g < nr; ++g) {
+                const int2 r = rng[g];
+                const int a = max(r.x, r0), len = max(0, r.y - a);
+                if (p >= cum && p < cum + len) j = a + (p - cum);
+                cum += len;
+            }
+            const bool ok = p < s1 && j >= 0;
+            // idle sources sit far away on the other side with no weight
+            sxy[lane] = ok ? make_double2(px[j], py[j]) : make_double2(-1e100, 0.0);
+            szq[lane] = ok ? make_double2(pz[j], q[j]) : make_double2(0.0, 0.0);
+            sacc[lane] = 0.0;
+            __syncthreads();
+            p2p_sym_block<R>(sxy, szq, sacc, xi, yi, zi, qi, acc);
+            __syncthreads();
+            if (ok) unsafeAtomicAdd(y + j, -0.5 * sacc[lane]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = r0 + lane + k * kP2PThreads;
+        if (i < r1) unsafeAtomicAdd(y + i, scale * acc[k][0]);
+    }
+}
+
+__global__ void __launch_bounds__(kP2PThreads) k_p2p_sym(const int4 *__restrict__ items,
+                                                         const int *__restrict__ leaf_pt,
+                                                         const int2 *__restrict__ near_rng,
+                                                         const int *__restrict__ near_cnt,
+                                                         const double *__restrict__ px,
+                                                         const double *__restrict__ py,
+                                                         const double *__restrict__ pz, int64_t n,
+                                                         const double *__restrict__ q, double *__restrict__ y) {
+    static_assert(kSymChunk == 4 * kP2PThreads, "at most four receivers per lane");
+    __shared__ double2 sxy[kP2PThreads], szq[kP2PThreads];
+    __shared__ double sacc[kP2PThreads];
+    const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
+    const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
+    const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
+    const int leaf = it.x, r0 = it.y, s0 = it.z, s1 = it.w;
+    const int r1 = min(r0 + kSymChunk, leaf_pt[leaf + 1]);
+    switch ((r1 - r0 + kP2PThreads - 1) / kP2PThreads) {
+        case 1:
+            p2p_sym_item<1>(leaf, r0, r1, s0, s1, near_rng, near_cnt, px, py, pz, n, q, y, sxy, szq, sacc);
+            break;
+        case 2:
+            p2p_sym_item<2>(leaf, r0, r1, s0, s1, near_rng, near_cnt, px, py, pz, n, q, y, sxy, szq, sacc);
+            break;
+        case 3:
+            p2p_sym_item<3>(leaf, r0, r1, s0, s1, near_rng, near_cnt, px, py, pz, n, q, y, sxy, szq, sacc);
+            break;
+        default:
+            p2p_sym_item<4>(leaf, r0, r1, s0, s1, near_rng, near_cnt, px, py, pz, n, q, y, sxy, szq, sacc);
+            break;
+    }
+}
+
 __global__ void k_clear(double *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -319,6 +450,17 @@ static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 template <int NCH, bool MONO, bool DIP>
 void launch_p2p(const Tree &t, const Sources &src, double *y, hipStream_t st) {
     if (t.n_near_items <= 0) return;
+    if constexpr (NCH == 1 && MONO && !DIP) {
+        // one channel of monopoles: each pair once, added to both points
+        BFM_CHECK(t.n_sym_items > 0, BFM_EINVAL, "symmetric near-field items missing");
+        k_clear<<<1024, 256, 0, st>>>(y, t.n);
+        BFM_LAUNCHED();
+        k_p2p_sym<<<(unsigned)t.n_sym_items, kP2PThreads, 0, st>>>(t.sym_items.get(), t.leaf_pt.get(),
+                                                                   t.near_rng.get(), t.near_cnt.get(), t.px.get(),
+                                                                   t.py.get(), t.pz.get(), t.n, src.q, y);
+        BFM_LAUNCHED();
+        return;
+    }
     if (t.near_split) {
         k_clear<<<1024, 256, 0, st>>>(y, (int64_t)NCH * t.n);
         BFM_LAUNCHED();

@@ -15,6 +15,12 @@ constexpr int kP2PChunk = 128;   // receivers per near-field work item (two per 
 constexpr int kLeafChunk = 128;  // points per leaf work item of P2M and L2P
 constexpr int kP2PPiece = 384;   // near-field sources per work item at most (a leaf's source
                                  // list longer than this is split into balanced pieces)
+// symmetric near field (one channel of monopoles): receivers per chunk (four
+// per lane), and the positions per work item at most in the chunk's diagonal
+// block and in the two-sided rest of its list
+constexpr int kSymChunk = 256;
+constexpr int kSymDiagPiece = 128;
+constexpr int kSymPiece = 192;
 
 // Translation tasks grouped by operator: tasks op_off[o]..op_off[o+1] use
 // operator o; task t moves expansion src[t] into expansion dst[t] (global
@@ -76,6 +82,11 @@ struct Tree {
     DevBuf<int4> near_items;
     int64_t n_near_items = 0;
     bool near_split = false;
+    // symmetric near-field items (leaf, r0, s0, s1): receivers [r0, r0 +
+    // kSymChunk) of the leaf against positions s0..s1-1 of its near ranges
+    // clipped to start at r0 (the chunk itself first), in leaf order
+    DevBuf<int4> sym_items;
+    int64_t n_sym_items = 0;
 
     // sorted point data (per tree): positions, weights, normals
     DevBuf<double> px, py, pz;  // [n]

@@ -511,6 +511,33 @@ __global__ void k_piece_fill(int64_t nleaf, const int *leaf_pt, const int *off, 
         for (int p = 0; p < pieces; ++p, ++o) items[o] = make_int4((int)i, r, min(src, p * ps), min(src, (p + 1) * ps));
 }
 
+// Symmetric near-field items: chunk [r0, r1) of leaf i takes its near ranges
+// clipped to start at r0; positions [0, r1 - r0) are the chunk itself (split
+// into pieces of kSymDiagPiece), the rest into pieces of kSymPiece.
+__device__ inline int sym_list_len(int64_t i, int r0, const int2 *rng, const int *rcnt) {
+    int len = 0;
+    for (int k = 0; k < rcnt[i]; ++k) len += max(0, rng[27 * i + k].y - max(rng[27 * i + k].x, r0));
+    return len;
+}
+
+template <bool FILL>
+__global__ void k_sym_items(int64_t nleaf, const int *leaf_pt, const int2 *rng, const int *rcnt, int *cnt,
+                            const int *off, int4 *items) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    const int p0 = leaf_pt[i], p1 = leaf_pt[i + 1];
+    int o = FILL ? off[i] : 0;
+    for (int r0 = p0; r0 < p1; r0 += kSymChunk) {
+        const int d = min(r0 + kSymChunk, p1) - r0;
+        const int len = sym_list_len(i, r0, rng, rcnt);
+        for (int s = 0; s < d; s += kSymDiagPiece, ++o)
+            if (FILL) items[o] = make_int4((int)i, r0, s, min(d, s + kSymDiagPiece));
+        for (int s = d; s < len; s += kSymPiece, ++o)
+            if (FILL) items[o] = make_int4((int)i, r0, s, min(len, s + kSymPiece));
+    }
+    if (!FILL) cnt[i] = o;
+}
+
 // ---------------------------------------------------------------------------
 // Interaction lists
 
@@ -878,6 +905,16 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                         t.near_cnt.get(), t.near_items.get());
         BFM_LAUNCHED();
         t.n_near_items = nn;
+        // symmetric near-field items
+        k_sym_items<false><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
+                                                               t.near_cnt.get(), icnt.get(), nullptr, nullptr);
+        BFM_LAUNCHED();
+        const int64_t ns = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);
+        t.sym_items.ensure(ns > 0 ? ns : 1);
+        k_sym_items<true><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
+                                                              t.near_cnt.get(), nullptr, ioff.get(), t.sym_items.get());
+        BFM_LAUNCHED();
+        t.n_sym_items = ns;
         t.near_split = split != 0;
     }
 
