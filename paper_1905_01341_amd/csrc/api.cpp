@@ -109,21 +109,24 @@ void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm
     const int64_t n = c->nv;
     // phase timers only record events; their times are read once at the end
     Timer t_tree(c->stream);
+    ensure_geometry(c);
+    // the coarse space needs only the geometry: it is built on a second stream
+    // beside the octree build, whose short kernels and host round trips leave
+    // most of the device free (beside the diagonal pass its serial chain of
+    // small kernels would wait for every wave of the pass's large launches)
+    if (c->opt.precond == BFM_PRECOND_SH_COARSE && c->pre.nd > 0) {
+        coarse_mark(c);
+        coarse_launch(c);
+    }
     ensure_tree(c);
     t_tree.stop();
     Timer t_guess(c->stream);
     if (guess == BFM_GUESS_LEARNED) mlp_guess(c, phi_dev, q_dev);
     t_guess.stop();
     const bool use_guess = guess != BFM_GUESS_ZERO;
-    // the coarse space needs only the geometry: it is built on a second stream
-    // beside the diagonal pass, from the point marked here; its launches are
-    // issued after the pass's, so that the pass is queued first
-    const bool coarse = c->opt.precond == BFM_PRECOND_SH_COARSE && c->pre.nd > 0;
-    if (coarse) coarse_mark(c);
     Timer t_diag(c->stream);
     diagonal_pass(c, phi_dev);
     t_diag.stop();
-    if (coarse) coarse_launch(c);
     Timer t_solve(c->stream);
     double *x = c->x_s.ensure(n);
     if (use_guess) to_sorted(c, q_dev, x);

@@ -126,7 +126,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     fetch(min(1, NC - 1) * kTKC, pb, bb);
     __syncthreads();
     // the fetches are unconditional (past the end they repeat the last
-    // chunk) so that the memory-counter waits are the same on every path
+    // chunk) so that the memory-counter waits are the same on every path;
+    // fully unrolled, so that the accumulators keep their registers across
+    // the loop's exits (a rolled loop copies them at every pass)
+#pragma unroll
     for (int c = 0; c < NC; c += 3) {
         // chunk c in LDS buffer c & 1, c + 1 in (pb, bb); load c + 2 into (pc, bc)
         fetch(min(c + 2, NC - 1) * kTKC, pc, bc);
