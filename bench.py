@@ -274,9 +274,8 @@ def main():
         avg_ms = d["ms"] / max(d["launches"], 1)
         ach = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
         if dom == "p2p":
-            # the instantiation that accumulates atomically runs when some
-            # leaf's source list is split into pieces (true at this size)
-            kname = "bfm::k_p2p<1, true, false, true>"
+            # the one-channel monopole product's near field (each pair once)
+            kname = "bfm::k_p2p_sym"
             # compulsory bytes: positions (24 B) and strength (8 B) of every
             # point read once, its sum (8 B) written once
             alg_bytes = 40.0 * cl.nv
