@@ -81,10 +81,15 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
     constexpr int PP = P_ * P_;
     constexpr int NT = P_ * (P_ + 1) / 2;
     constexpr int NCOL = PP * NCH;
-    constexpr int COLS = NCH == 1 ? 32 : 4 * NCH;  // flush threshold
-    constexpr int CAP = COLS + 4 * NCH;              // a loop trip adds at most 4 NCH columns
-    static_assert(CAP <= 64, "one lane per buffered column");
-    __shared__ double red[CAP][65];
+    // buffered columns at most (a power of two dividing 64); a loop trip adds
+    // at most 4 NCH columns, so the buffer is flushed once it holds COLS
+    constexpr int CAP = NCH == 1 ? 16 : 32;
+    constexpr int COLS = CAP - 4 * NCH;
+    static_assert(COLS >= 1 && 64 % CAP == 0, "flush shape");
+    // a flush gives each buffered column G lanes, each summing every G-th of
+    // its 64 values; rows of 64 + G doubles put those reads in distinct banks
+    constexpr int G = 64 / CAP;
+    __shared__ double red[CAP][64 + G];
     __shared__ double2 rec[NT];
     __shared__ double sect[P_];
     __shared__ int outi[PP];
@@ -137,18 +142,22 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
     // buffered column sums -> the leaf's expansion
     auto flush = [&]() {
         __syncthreads();
-        if (lane < fill) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        const int cl = lane / G, part = lane % G;
+        double s0 = 0.0, s1 = 0.0;
+        if (cl < fill) {
 #pragma unroll
-            for (int l = 0; l < 64; l += 4) {
-                s0 += red[lane][l];
-                s1 += red[lane][l + 1];
-                s2 += red[lane][l + 2];
-                s3 += red[lane][l + 3];
+            for (int l = 0; l < 64 / G; l += 2) {
+                s0 += red[cl][l * G + part];
+                s1 += red[cl][(l + 1) * G + part];
             }
-            const int cc = col - fill + lane;
+        }
+        double sum = s0 + s1;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) sum += __shfl_xor(sum, o);
+        if (cl < fill && part == 0) {
+            const int cc = col - fill + cl;
             const int sl = cc / NCH, c = cc - sl * NCH;
-            unsafeAtomicAdd(mbox + c * PP + outi[sl], (s0 + s1) + (s2 + s3));
+            unsafeAtomicAdd(mbox + c * PP + outi[sl], sum);
         }
         __syncthreads();
         fill = 0;
