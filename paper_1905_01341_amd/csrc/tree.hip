@@ -277,6 +277,16 @@ __global__ void k_scan_total(const int *out, int64_t n, int *total) {
     if (threadIdx.x == 0 && blockIdx.x == 0) total[0] += out[n - 1];
 }
 
+// totals of three exclusive scans of n >= 1 counts: last offset + last count
+__global__ void k_scan_totals3(const int *c0, const int *o0, const int *c1, const int *o1, const int *c2,
+                               const int *o2, int64_t n, int *out) {
+    if (threadIdx.x == 0) {
+        out[0] = o0[n - 1] + c0[n - 1];
+        out[1] = o1[n - 1] + c1[n - 1];
+        out[2] = o2[n - 1] + c2[n - 1];
+    }
+}
+
 // scratch of the recursion (the sums of every level) plus one slot for the
 // total at index *total_slot
 static int *scan_scratch(int64_t n, DevBuf<int> &tmp, int64_t *total_slot = nullptr) {
@@ -837,7 +847,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
         const int shift = 3 * (kKeyBits - l);
         k_level_flags<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, shift, flag.get());
         BFM_LAUNCHED();
-        exclusive_scan(flag.get(), pos.get(), n, st, tmp);
+        exclusive_scan_async(flag.get(), pos.get(), n, st, tmp);  // the level's box count is known
         k_level_scatter<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, shift, flag.get(), pos.get(),
                                                       t.lvl_off[l], l, t.box_key.get(),
                                                       t.box_level.get(), t.box_pt0.get());
@@ -853,69 +863,80 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                   t.box_parent.get(), t.box_centre.get(), t.nbr.get(),
                                                   nullptr);
     BFM_LAUNCHED();
-    // leaves
+    // leaves: point ranges, near-field pair count and ranges, and the work
+    // item lists of P2M/L2P, the one-sided and the symmetric near field; the
+    // sizes the host needs (pair count, largest leaf, item counts) come back
+    // together after one wait
     t.leaf_pt.ensure(t.nleaf + 1);
     DevBuf<unsigned long long> &np = scr.np;
     np.ensure(1);
     DevBuf<int> &mo = scr.mo;
-    mo.ensure(1);
+    mo.ensure(5);  // largest leaf, some leaf's sources split, three item counts
     k_fill_u64<<<1, 64, 0, st>>>(np.get(), 1, 0ull);
     BFM_LAUNCHED();
-    k_fill_int<<<1, 64, 0, st>>>(mo.get(), 1, 0);
+    k_fill_int<<<1, 64, 0, st>>>(mo.get(), 5, 0);
     BFM_LAUNCHED();
     k_leaf_near<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.box_pt0.get(), n,
                                                     t.nbr.get(), t.leaf_pt.get(), np.get(), mo.get());
     BFM_LAUNCHED();
-    unsigned long long npairs = 0;
-    int maxocc = 0;
-    BFM_HIP(hipMemcpyAsync(&npairs, np.get(), sizeof(npairs), hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipMemcpyAsync(&maxocc, mo.get(), sizeof(int), hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipStreamSynchronize(st));
-    t.npairs_near = (int64_t)npairs;
-    t.max_leaf = maxocc;
     t.near_rng.ensure(27 * t.nleaf);
     t.near_cnt.ensure(t.nleaf);
     k_leaf_ranges<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.leaf_pt.get(), t.nbr.get(),
                                                       t.near_rng.get(), t.near_cnt.get());
     BFM_LAUNCHED();
     {
-        DevBuf<int> &icnt = scr.icnt, &ioff = scr.ioff;
+        // counts and offsets: leaf items (icnt, ioff), one-sided near-field
+        // pieces (flag, pos; free after the levels, n >= nleaf entries) and
+        // symmetric items (count, offs)
+        DevBuf<int> &icnt = scr.icnt, &ioff = scr.ioff, &ccnt = scr.count, &coff = scr.offs;
         icnt.ensure(t.nleaf);
         ioff.ensure(t.nleaf);
+        // (count and offs later hold the M2L pair counts: sized for both now)
+        const int64_t ncw = std::max<int64_t>(t.nleaf, 27 * (t.lvl_off[lmax + 1] - t.lvl_off[2]));
+        ccnt.ensure(ncw);
+        coff.ensure(ncw);
+        int *pcnt = flag.get(), *poff = pos.get();
         k_item_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), icnt.get());
         BFM_LAUNCHED();
-        const int64_t ni = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);
-        t.leaf_items.ensure(ni);
+        k_piece_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
+                                                         t.near_cnt.get(), pcnt, mo.get() + 1);
+        BFM_LAUNCHED();
+        k_sym_items<false><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
+                                                               t.near_cnt.get(), ccnt.get(), nullptr, nullptr);
+        BFM_LAUNCHED();
+        exclusive_scan_async(icnt.get(), ioff.get(), t.nleaf, st, tmp);
+        exclusive_scan_async(pcnt, poff, t.nleaf, st, tmp);
+        exclusive_scan_async(ccnt.get(), coff.get(), t.nleaf, st, tmp);
+        k_scan_totals3<<<1, 64, 0, st>>>(icnt.get(), ioff.get(), pcnt, poff, ccnt.get(), coff.get(), t.nleaf,
+                                         mo.get() + 2);
+        BFM_LAUNCHED();
+        unsigned long long npairs = 0;
+        int hm[5] = {0, 0, 0, 0, 0};
+        BFM_HIP(hipMemcpyAsync(&npairs, np.get(), sizeof(npairs), hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipMemcpyAsync(hm, mo.get(), sizeof(hm), hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
+        t.npairs_near = (int64_t)npairs;
+        t.max_leaf = hm[0];
+        t.near_split = hm[1] != 0;
+        const int64_t ni = hm[2], nn = hm[3], ns = hm[4];
+        // leaf chunks of at most kLeafChunk points (P2M, L2P)
+        t.leaf_items.ensure(ni > 0 ? ni : 1);
         k_item_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.leaf_items.get());
         BFM_LAUNCHED();
         t.n_leaf_items = ni;
         // near-field items: leaf chunks x balanced pieces of the source list,
         // in leaf (Morton) order
-        int *dsplit = scr.mo.ensure(1);
-        k_fill_int<<<1, 64, 0, st>>>(dsplit, 1, 0);
-        BFM_LAUNCHED();
-        k_piece_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                         t.near_cnt.get(), icnt.get(), dsplit);
-        BFM_LAUNCHED();
-        int split = 0;
-        BFM_HIP(hipMemcpyAsync(&split, dsplit, sizeof(int), hipMemcpyDeviceToHost, st));
-        const int64_t nn = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);  // waits for split too
-        t.near_items.ensure(nn);
-        k_piece_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.near_rng.get(),
+        t.near_items.ensure(nn > 0 ? nn : 1);
+        k_piece_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), poff, t.near_rng.get(),
                                                         t.near_cnt.get(), t.near_items.get());
         BFM_LAUNCHED();
         t.n_near_items = nn;
         // symmetric near-field items
-        k_sym_items<false><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                               t.near_cnt.get(), icnt.get(), nullptr, nullptr);
-        BFM_LAUNCHED();
-        const int64_t ns = exclusive_scan(icnt.get(), ioff.get(), t.nleaf, st, tmp);
         t.sym_items.ensure(ns > 0 ? ns : 1);
         k_sym_items<true><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                              t.near_cnt.get(), nullptr, ioff.get(), t.sym_items.get());
+                                                              t.near_cnt.get(), nullptr, coff.get(), t.sym_items.get());
         BFM_LAUNCHED();
         t.n_sym_items = ns;
-        t.near_split = split != 0;
     }
 
     // M2L lists over levels 2..lmax
