@@ -292,12 +292,13 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_diag(const int4 *__restrict
 // Symmetric near field of one channel of monopoles (the kernel 1/r is
 // symmetric): every unordered pair of points is visited once and its two
 // terms go to both points. Work item (leaf, r0, s0, s1): receivers [r0, r1)
-// of the leaf (kSymChunk, four per lane) against positions s0..s1-1 of the
-// leaf's near ranges clipped to start at r0. The first r1 - r0 positions are
-// the chunk itself (pieces of the diagonal block, one-sided, j == i
-// excluded); the later ones (the leaf's later points and the neighbour leaves
-// with higher Morton keys) are summed both ways. The lower-keyed neighbours
-// reach these receivers from their own items, so each pair is summed once.
+// of the leaf (at most kSymChunk: one to four per lane, by the chunk's size)
+// against positions s0..s1-1 of the leaf's near ranges clipped to start at
+// r0. The first r1 - r0 positions are the chunk itself (pieces of the
+// diagonal block, one-sided, j == i excluded); the later ones (the leaf's
+// later points and the neighbour leaves with higher Morton keys) are summed
+// both ways. The lower-keyed neighbours reach these receivers from their own
+// items, so each pair is summed once.
 // Sources of a two-sided piece pass in blocks of 64 through LDS: at step t
 // lane l takes source (l + t) mod 64, so the lanes hold 64 distinct sources
 // at every step and each adds its terms for that source to the source's LDS

@@ -15,9 +15,9 @@ constexpr int kP2PChunk = 128;   // receivers per near-field work item (two per 
 constexpr int kLeafChunk = 128;  // points per leaf work item of P2M and L2P
 constexpr int kP2PPiece = 384;   // near-field sources per work item at most (a leaf's source
                                  // list longer than this is split into balanced pieces)
-// symmetric near field (one channel of monopoles): receivers per chunk (four
-// per lane), and the positions per work item at most in the chunk's diagonal
-// block and in the two-sided rest of its list
+// symmetric near field (one channel of monopoles): receivers per chunk (up
+// to four per lane), and the positions per work item at most in the chunk's
+// diagonal block and in the two-sided rest of its list
 constexpr int kSymChunk = 256;
 constexpr int kSymDiagPiece = 128;
 constexpr int kSymPiece = 192;
