@@ -377,39 +377,38 @@ struct LevelInfo {
     double h[kKeyBits + 1];
 };
 
+// One thread per (box, neighbour slot): the slot's neighbour by binary search
+// in the box's level; the thread of slot 13 (the box itself) also writes the
+// box's centre and parent.
 __global__ void k_box_meta(int64_t nbox, int lmax, LevelInfo li, double ox, double oy, double oz,
-                           const uint64_t *box_key, const int *box_level, int64_t npts,
-                           int *box_parent, double *centre, int *nbr, int *box_pt1_unused) {
-    int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= nbox) return;
+                           const uint64_t *box_key, const int *box_level, int *box_parent, double *centre,
+                           int *nbr) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= 27 * nbox) return;
+    const int64_t b = g / 27;
+    const int s = (int)(g - 27 * b);
     const int l = box_level[b];
     const uint64_t k = box_key[b];
     int ix, iy, iz;
     demorton(k, ix, iy, iz);
-    const double h = li.h[l];
-    centre[3 * b] = ox + (ix + 0.5) * h;
-    centre[3 * b + 1] = oy + (iy + 0.5) * h;
-    centre[3 * b + 2] = oz + (iz + 0.5) * h;
-    if (l == 0) {
-        box_parent[b] = -1;
-    } else {
-        int64_t pb = lower_bound_u64(box_key, li.off[l - 1], li.off[l], k >> 3);
-        box_parent[b] = (int)pb;
+    if (s == 13) {
+        const double h = li.h[l];
+        centre[3 * b] = ox + (ix + 0.5) * h;
+        centre[3 * b + 1] = oy + (iy + 0.5) * h;
+        centre[3 * b + 2] = oz + (iz + 0.5) * h;
+        box_parent[b] = (l == 0) ? -1 : (int)lower_bound_u64(box_key, li.off[l - 1], li.off[l], k >> 3);
     }
     const int lim = 1 << l;
-    for (int s = 0; s < 27; ++s) {
-        const int dx = s / 9 - 1, dy = (s / 3) % 3 - 1, dz = s % 3 - 1;
-        const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
-        int res = -1;
-        if (jx >= 0 && jy >= 0 && jz >= 0 && jx < lim && jy < lim && jz < lim) {
-            const uint64_t nk = morton(jx, jy, jz);
-            int64_t q = lower_bound_u64(box_key, li.off[l], li.off[l + 1], nk);
-            if (q < li.off[l + 1] && box_key[q] == nk) res = (int)q;
-        }
-        nbr[27 * b + s] = res;
+    const int dx = s / 9 - 1, dy = (s / 3) % 3 - 1, dz = s % 3 - 1;
+    const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+    int res = -1;
+    if (jx >= 0 && jy >= 0 && jz >= 0 && jx < lim && jy < lim && jz < lim) {
+        const uint64_t nk = morton(jx, jy, jz);
+        const int64_t q = lower_bound_u64(box_key, li.off[l], li.off[l + 1], nk);
+        if (q < li.off[l + 1] && box_key[q] == nk) res = (int)q;
     }
-    (void)npts;
-    (void)box_pt1_unused;
+    nbr[27 * b + s] = res;
+    (void)lmax;
 }
 
 // Number of near-field pairs per leaf, and leaf point ranges.
@@ -605,9 +604,17 @@ __global__ void k_tree_pairs(int64_t b0, int64_t b1, const uint64_t *box_key, co
     top[b - b0] = (int)(box_key[b] & 7);
 }
 
-__global__ void k_op_hist(const int *top, int64_t n, int *hist) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&hist[top[i]], 1);
+// Tasks per operator: counted in LDS per workgroup (nops ints of dynamic
+// shared memory), then one global atomic per (workgroup, non-empty bin).
+__global__ void __launch_bounds__(1024) k_op_hist(const int *top, int64_t n, int nops, int *hist) {
+    extern __shared__ int lh[];
+    for (int o = threadIdx.x; o < nops; o += blockDim.x) lh[o] = 0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&lh[top[i]], 1);
+    __syncthreads();
+    for (int o = threadIdx.x; o < nops; o += blockDim.x)
+        if (lh[o]) atomicAdd(&hist[o], lh[o]);
 }
 
 // Group by operator keeping the input order within each group: one block
@@ -669,7 +676,9 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
     k_fill_int<<<nblk(nops, 256), 256, 0, st>>>(hist.get(), nops, 0);
     BFM_LAUNCHED();
     if (n > 0) {
-        k_op_hist<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(top, n, hist.get());
+        BFM_CHECK(nops <= 8192, BFM_EINVAL, "too many translation operators");
+        const unsigned nb = (unsigned)std::min<int64_t>(64, (n + 1023) / 1024);
+        k_op_hist<<<nb, 1024, sizeof(int) * nops, st>>>(top, n, nops, hist.get());
         BFM_LAUNCHED();
     }
     std::vector<int> h(nops);
@@ -858,10 +867,9 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
             BFM_LAUNCHED();
         }
     }
-    k_box_meta<<<nblk(t.nbox, 128), 128, 0, st>>>(t.nbox, lmax, li, t.origin[0], t.origin[1],
-                                                  t.origin[2], t.box_key.get(), t.box_level.get(), n,
-                                                  t.box_parent.get(), t.box_centre.get(), t.nbr.get(),
-                                                  nullptr);
+    k_box_meta<<<nblk(27 * t.nbox, 256), 256, 0, st>>>(t.nbox, lmax, li, t.origin[0], t.origin[1],
+                                                       t.origin[2], t.box_key.get(), t.box_level.get(),
+                                                       t.box_parent.get(), t.box_centre.get(), t.nbr.get());
     BFM_LAUNCHED();
     // leaves: point ranges, near-field pair count and ranges, and the work
     // item lists of P2M/L2P, the one-sided and the symmetric near field; the
