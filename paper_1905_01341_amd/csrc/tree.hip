@@ -192,8 +192,9 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, 
     }
 }
 
-void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits, Tree::Scratch &scr,
-                hipStream_t st) {
+// Stable LSD sort of (keys, vals) by key bits [lo, lo + bits), 8 bits a pass.
+static void radix_sort_range(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int lo,
+                             int bits, Tree::Scratch &scr, hipStream_t st) {
     if (n <= 1) return;
     const int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
     DevBuf<int> &hist = scr.rs_hist, &scanned = scr.rs_scanned, &tmp = scr.rs_tmp;
@@ -204,7 +205,7 @@ void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, in
     int passes = (bits + 7) / 8;
     if (passes & 1) ++passes;  // even pass count: the result lands back in keys / vals
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = 8 * pass;
+        const int shift = lo + 8 * pass;
         k_rs_hist<<<nblocks, RS_THREADS, 0, st>>>(kin, n, shift, hist.get(), nblocks);
         BFM_LAUNCHED();
         exclusive_scan_async(hist.get(), scanned.get(), (int64_t)256 * nblocks, st, tmp);
@@ -213,6 +214,11 @@ void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, in
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
+}
+
+void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits, Tree::Scratch &scr,
+                hipStream_t st) {
+    radix_sort_range(keys, vals, keys_tmp, vals_tmp, n, 0, bits, scr, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -813,25 +819,46 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                            t.key_a.get(), t.idx_a.get());
     BFM_LAUNCHED();
     Tree::Scratch &scr = t.scratch;
-    radix_sort(t.key_a.get(), t.idx_a.get(), t.key_b.get(), t.idx_b.get(), n, 3 * kKeyBits, scr, st);
+    // Sort by the keys' top 30 bits first (levels 1..10: four 8-bit passes
+    // instead of six). The boxes of every level <= 10 are then contiguous,
+    // which is all an octree of depth <= 10 needs (points inside a level-10
+    // box keep their input order); a deeper octree sorts all 45 bits.
+    constexpr int kSortedLevels = 10;
+    radix_sort_range(t.key_a.get(), t.idx_a.get(), t.key_b.get(), t.idx_b.get(), n,
+                     3 * (kKeyBits - kSortedLevels), 3 * kSortedLevels, scr, st);
+    int sorted_levels = kSortedLevels;
     DevBuf<int> &tmp = scr.tmp;
 
-    // boxes per level
+    // boxes per level (exact for the sorted levels)
     DevBuf<unsigned long long> &cnt = scr.cnt;
     cnt.ensure(kKeyBits + 1);
-    k_fill_u64<<<1, 64, 0, st>>>(cnt.get(), kKeyBits + 1, 0ull);
-    BFM_LAUNCHED();
-    k_level_counts<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, kKeyBits, cnt.get());
-    BFM_LAUNCHED();
     std::vector<unsigned long long> ch(kKeyBits + 1);
-    BFM_HIP(hipMemcpyAsync(ch.data(), cnt.get(), sizeof(unsigned long long) * (kKeyBits + 1),
-                           hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipStreamSynchronize(st));
-    int lmax = lmax_req;
-    if (lmax <= 0) {
-        lmax = 2;
-        for (int l = 2; l <= kKeyBits; ++l)
-            if ((double)n / (double)ch[l] >= (double)std::max(leaf_target, 1)) lmax = l;
+    auto count_levels = [&]() {
+        k_fill_u64<<<1, 64, 0, st>>>(cnt.get(), kKeyBits + 1, 0ull);
+        BFM_LAUNCHED();
+        k_level_counts<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, kKeyBits, cnt.get());
+        BFM_LAUNCHED();
+        BFM_HIP(hipMemcpyAsync(ch.data(), cnt.get(), sizeof(unsigned long long) * (kKeyBits + 1),
+                               hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipStreamSynchronize(st));
+    };
+    // the requested depth, else the deepest sorted level whose mean leaf
+    // occupancy is >= leaf_target (at least 2)
+    auto pick = [&]() {
+        if (lmax_req > 0) return lmax_req;
+        int d = 2;
+        for (int l = 2; l <= sorted_levels; ++l)
+            if ((double)n / (double)ch[l] >= (double)std::max(leaf_target, 1)) d = l;
+        return d;
+    };
+    count_levels();
+    int lmax = pick();
+    if (lmax > kSortedLevels || (lmax_req <= 0 && lmax == kSortedLevels)) {
+        // a deeper octree is asked for, or the occupancy rule may go deeper
+        radix_sort(t.key_a.get(), t.idx_a.get(), t.key_b.get(), t.idx_b.get(), n, 3 * kKeyBits, scr, st);
+        sorted_levels = kKeyBits;
+        count_levels();
+        lmax = pick();
     }
     BFM_CHECK(lmax >= 2 && lmax <= kKeyBits, BFM_EINVAL, "octree depth must be in [2, 15]");
     t.lmax = lmax;
