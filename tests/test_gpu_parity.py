@@ -128,6 +128,21 @@ def test_fmm_product_tiny_leaves(single):
     assert e_l < 3e-6 and e_m < 2e-5, (e_l, e_m)
 
 
+def test_fmm_product_deep_octree(single):
+    """One sphere at lmax = 11, deeper than the levels the first key sort
+    orders (10): the points are sorted by all 45 key bits and every leaf
+    holds at most a few points. The product must still match the oracle to
+    the expansion accuracy (limits as for the tiny leaves above)."""
+    cl, phi, s, n = single
+    sv = _solver(cl, p=16, lmax=11)
+    assert sv.tree_stats()["lmax"] == 11
+    x = np.cos(np.arange(cl.nv) * 0.37)
+    e_l = rel(sv.matvec(1.0, x), oracle.offdiag_mvp(cl.xyz, s, n, 1.0, x))
+    e_m = rel(sv.matvec(0.0, None, 1.0, phi), oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi))
+    print(f"L={e_l:.3e} M={e_m:.3e}")
+    assert e_l < 3e-6 and e_m < 2e-5, (e_l, e_m)
+
+
 def test_diagonals_and_rhs(single, c100):
     """M_ii = -1/2 - sum M_ij is a small difference of O(1/2) terms, so its
     error is judged against 1/2 (the size of the sum it comes from)."""
