@@ -625,28 +625,33 @@ __global__ void __launch_bounds__(1024) k_op_hist(const int *top, int64_t n, int
 
 // Group by operator keeping the input order within each group: one block
 // per operator scans all tasks in order (operator counts are small).
-__global__ void k_op_group(const int *top, const int *src, const int *dst, int64_t n,
-                           const int *op_off, int *osrc, int *odst) {
+// Tasks of operator blockIdx.x in input order: each thread takes a
+// contiguous run of the task list, the runs' match counts are scanned in
+// LDS, and every thread writes its matches from its run's offset.
+__global__ void __launch_bounds__(1024) k_op_group(const int *top, const int *src, const int *dst, int64_t n,
+                                                   const int *op_off, int *osrc, int *odst) {
+    __shared__ int cnt[1024];
     const int op = blockIdx.x;
-    __shared__ int base;
-    if (threadIdx.x == 0) base = op_off[op];
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int64_t per = (n + T - 1) / T;
+    const int64_t i0 = tid * per, i1 = min(n, i0 + per);
+    int c = 0;
+    for (int64_t i = i0; i < i1; ++i) c += (top[i] == op) ? 1 : 0;
+    cnt[tid] = c;
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    // single wave per block keeps the order simple
-    if (threadIdx.x >= 64) return;
-    int run = base;
-    for (int64_t i0 = 0; i0 < n; i0 += 64) {
-        const int64_t i = i0 + lane;
-        const bool hit = (i < n) && top[i] == op;
-        const uint64_t m = __ballot(hit);
-        if (hit) {
-            const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-            const int r = run + __popcll(m & lt);
+    for (int d = 1; d < T; d <<= 1) {  // inclusive scan of the counts
+        const int v = (tid >= d) ? cnt[tid - d] : 0;
+        __syncthreads();
+        cnt[tid] += v;
+        __syncthreads();
+    }
+    int r = op_off[op] + cnt[tid] - c;
+    for (int64_t i = i0; i < i1; ++i)
+        if (top[i] == op) {
             osrc[r] = src[i];
             odst[r] = dst[i];
+            ++r;
         }
-        run += __popcll(m);
-    }
 }
 
 __global__ void k_op_keys(const int *top, int64_t n, uint64_t *key, int *idx) {
@@ -696,7 +701,7 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
     tl.src.ensure(n > 0 ? n : 1);
     tl.dst.ensure(n > 0 ? n : 1);
     if (n > 0 && nops <= 16) {
-        k_op_group<<<nops, 64, 0, st>>>(top, tsrc, tdst, n, tl.op_off.get(), tl.src.get(), tl.dst.get());
+        k_op_group<<<nops, 1024, 0, st>>>(top, tsrc, tdst, n, tl.op_off.get(), tl.src.get(), tl.dst.get());
         BFM_LAUNCHED();
     } else if (n > 0) {
         uint64_t *k0 = scr.ikey.ensure(n), *k1 = scr.ikey2.ensure(n);
