@@ -295,9 +295,10 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_diag(const int4 *__restrict
 // of the leaf (at most kSymChunk: one to four per lane, by the chunk's size)
 // against positions s0..s1-1 of the leaf's near ranges clipped to start at
 // r0. The first r1 - r0 positions are the chunk itself (pieces of the
-// diagonal block, one-sided, j == i excluded); the later ones (the leaf's
-// later points and the neighbour leaves with higher Morton keys) are summed
-// both ways. The lower-keyed neighbours reach these receivers from their own
+// diagonal block, in blocks of 64 against the receiver groups: the groups
+// below a block both ways, the block's own group one-sided with j == i
+// excluded); the later ones (the leaf's later points and the neighbour leaves
+// with higher Morton keys) are summed both ways. The lower-keyed neighbours reach these receivers from their own
 // items, so each pair is summed once.
 // Sources of a two-sided piece pass in blocks of 64 through LDS: at step t
 // lane l takes source (l + t) mod 64, so the lanes hold 64 distinct sources
@@ -325,6 +326,33 @@ __device__ inline void p2p_sym_block(const double2 *sxy, const double2 *szq, dou
     }
 }
 
+// A block of the chunk's own points as sources: source slot l is receiver
+// l of group b. Group k < b is summed both ways (its pairs with group b are
+// met only here), group b one-sided over every ordered pair but the
+// diagonal (step 0, where each lane meets its own point), groups k > b not
+// at all (their pairs with group b are met when block k is the source).
+template <int R>
+__device__ inline void p2p_diag_block(const double2 *sxy, const double2 *szq, double *sacc, const double *xi,
+                                      const double *yi, const double *zi, const double *qi, double (*acc)[1],
+                                      int b) {
+    const int lane = threadIdx.x;
+#pragma unroll 2
+    for (int t = 0; t < kP2PThreads; ++t) {
+        const int s = (lane + t) & (kP2PThreads - 1);
+        const double2 a = sxy[s], w = szq[s];
+        double c = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            if (k > b || (k == b && t == 0)) continue;  // wave-uniform
+            const double dx = xi[k] - a.x, dy = yi[k] - a.y, dz = zi[k] - w.x;
+            const double inv = rsqrt_m2_f64(dx * dx + dy * dy + dz * dz);  // -2 / r
+            acc[k][0] = fma(w.y, inv, acc[k][0]);
+            if (k < b) c = fma(qi[k], inv, c);
+        }
+        if (b > 0) atomicAdd(sacc + s, c);
+    }
+}
+
 // One item with R = ceil((r1 - r0) / 64) receivers per lane, so that a short
 // chunk runs no all-idle receiver groups.
 template <int R>
@@ -345,13 +373,23 @@ __device__ inline void p2p_sym_item(int leaf, int r0, int r1, int s0, int s1, co
         qi[k] = ok ? q[i] : 0.0;
         acc[k][0] = 0.0;
     }
-    double scale = 1.0;
+    const double scale = -0.5;  // the sums hold -2 / r
     if (s1 <= r1 - r0) {
-        // diagonal block: one-sided over the chunk's own points
-        p2p_range<1, true, false, R, true>(r0 + s0, r0 + s1, px, py, pz, nullptr, nullptr, nullptr, n, q, nullptr,
-                                           xi, yi, zi, acc);
+        // the chunk's own points, in blocks of 64 aligned with the receiver
+        // groups (pieces start at multiples of kSymDiagPiece)
+        for (int base = s0; base < s1; base += kP2PThreads) {
+            const int j = r0 + base + lane;
+            const bool ok = base + lane < s1;
+            sxy[lane] = ok ? make_double2(px[j], py[j]) : make_double2(-1e100, 0.0);
+            szq[lane] = ok ? make_double2(pz[j], q[j]) : make_double2(0.0, 0.0);
+            sacc[lane] = 0.0;
+            __syncthreads();
+            const int b = base / kP2PThreads;
+            p2p_diag_block<R>(sxy, szq, sacc, xi, yi, zi, qi, acc, b);
+            __syncthreads();
+            if (ok && b > 0) unsafeAtomicAdd(y + j, -0.5 * sacc[lane]);
+        }
     } else {
-        scale = -0.5;  // the two-sided sums hold -2 / r
         const int2 *rng = near_rng + 27 * (int64_t)leaf;
         const int nr = near_cnt[leaf];
         for (int base = s0; base < s1; base += kP2PThreads) {
@@ -391,6 +429,7 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_sym(const int4 *__restrict_
                                                          const double *__restrict__ pz, int64_t n,
                                                          const double *__restrict__ q, double *__restrict__ y) {
     static_assert(kSymChunk == 4 * kP2PThreads, "at most four receivers per lane");
+    static_assert(kSymDiagPiece % kP2PThreads == 0, "diagonal pieces start at receiver-group bounds");
     __shared__ double2 sxy[kP2PThreads], szq[kP2PThreads];
     __shared__ double sacc[kP2PThreads];
     const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
