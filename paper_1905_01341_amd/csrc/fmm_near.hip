@@ -228,22 +228,13 @@ __device__ inline void p2p_diag_range(int j0, int j1, const double *__restrict__
     }
 }
 
-// The five-channel counterpart of k_p2p (same items, pieces and order).
-template <bool ATOMIC>
-__global__ void __launch_bounds__(kP2PThreads) k_p2p_diag(const int4 *__restrict__ items,
-                                                          const int *__restrict__ leaf_pt,
-                                                          const int2 *__restrict__ near_rng,
-                                                          const int *__restrict__ near_cnt,
-                                                          const double *__restrict__ px,
-                                                          const double *__restrict__ py,
-                                                          const double *__restrict__ pz,
-                                                          const double *__restrict__ pk, int64_t n,
-                                                          double *__restrict__ y) {
-    constexpr int R = kP2PChunk / kP2PThreads;
-    const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
-    const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
-    const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
-    const int leaf = it.x, rc = it.y, s0 = it.z, s1 = it.w;
+// One item of the five-channel pass with R receivers per lane.
+template <int R, bool ATOMIC>
+__device__ inline void p2p_diag_item(int leaf, int rc, int s0, int s1, const int *__restrict__ leaf_pt,
+                                     const int2 *__restrict__ near_rng, const int *__restrict__ near_cnt,
+                                     const double *__restrict__ px, const double *__restrict__ py,
+                                     const double *__restrict__ pz, const double *__restrict__ pk, int64_t n,
+                                     double *__restrict__ y) {
     const int l0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
     const int nr = near_cnt[leaf];
     const int2 *rng = near_rng + 27 * (int64_t)leaf;
@@ -287,6 +278,29 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_diag(const int4 *__restrict
                     y[(int64_t)c * n + i] = acc[k][c];
             }
     }
+}
+
+// The five-channel counterpart of k_p2p (same items, pieces and order); a
+// chunk of at most 64 receivers runs with one receiver per lane.
+template <bool ATOMIC>
+__global__ void __launch_bounds__(kP2PThreads) k_p2p_diag(const int4 *__restrict__ items,
+                                                          const int *__restrict__ leaf_pt,
+                                                          const int2 *__restrict__ near_rng,
+                                                          const int *__restrict__ near_cnt,
+                                                          const double *__restrict__ px,
+                                                          const double *__restrict__ py,
+                                                          const double *__restrict__ pz,
+                                                          const double *__restrict__ pk, int64_t n,
+                                                          double *__restrict__ y) {
+    static_assert(kP2PChunk == 2 * kP2PThreads, "one or two receivers per lane");
+    const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
+    const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
+    const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
+    const int leaf = it.x, rc = it.y;
+    if (leaf_pt[leaf + 1] - rc <= kP2PThreads)
+        p2p_diag_item<1, ATOMIC>(leaf, rc, it.z, it.w, leaf_pt, near_rng, near_cnt, px, py, pz, pk, n, y);
+    else
+        p2p_diag_item<2, ATOMIC>(leaf, rc, it.z, it.w, leaf_pt, near_rng, near_cnt, px, py, pz, pk, n, y);
 }
 
 // Symmetric near field of one channel of monopoles (the kernel 1/r is
