@@ -33,34 +33,37 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and FP64 matrix (dense)
 # to the value it was measured with.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c1000.txt")
 KERNEL_SOURCES = {"p2p": ("fmm_near.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h"),
-                  "m2l": ("fmm.hip", "fmm.h", "common.h")}
+                  "m2l": ("fmm.hip", "fmm.h", "common.h"),
+                  "leaf": ("fmm_leaf.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h")}
 
 
 def parse():
+    """Command line. Solver options left unset take the values of the form
+    (paper_1905_01341_amd/forms.py), which the oracle tests use too."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1000")
-    ap.add_argument("--p", type=int, default=16)
-    ap.add_argument("--p-diag", type=int, default=0)
-    ap.add_argument("--leaf", type=int, default=64)
-    ap.add_argument("--lmax", type=int, default=0)
-    ap.add_argument("--m2l-shape", type=int, default=-1, help="M2L launch shape 0..2 (-1: by size)")
-    ap.add_argument("--tol", type=float, default=1e-7, help="GMRES tolerance of the tuned form")
-    ap.add_argument("--plain-tol", type=float, default=1e-8,
+    ap.add_argument("--p", type=int, default=None)
+    ap.add_argument("--p-diag", type=int, default=None)
+    ap.add_argument("--leaf", type=int, default=None)
+    ap.add_argument("--lmax", type=int, default=None)
+    ap.add_argument("--m2l-shape", type=int, default=None, help="M2L launch shape 0..2 (-1: by size)")
+    ap.add_argument("--tol", type=float, default=None, help="GMRES tolerance of the tuned form")
+    ap.add_argument("--plain-tol", type=float, default=None,
                     help="GMRES tolerance of the plain form (unpreconditioned GMRES needs 1e-8 to bring "
                          "the solution within 1e-6 of the oracle's; at 1e-7 it stops at 2.5e-6)")
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--form", choices=["tuned", "plain"], default="tuned")
-    ap.add_argument("--precond-degree", type=int, default=12)
+    ap.add_argument("--precond-degree", type=int, default=None)
     ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--graph", type=int, default=1, help="tuned form: replay GMRES products from a HIP graph")
+    ap.add_argument("--graph", type=int, default=None, help="tuned form: replay GMRES products from a HIP graph")
     ap.add_argument("--autotune", type=int, default=1, help="tuned form: autotune p, octree depth, M2L shape")
-    ap.add_argument("--tune-tol", type=float, default=1e-7)
+    ap.add_argument("--tune-tol", type=float, default=None)
     ap.add_argument("--learned-steps", type=int, default=0,
                     help="run the learned-guess study instead: this many time steps collect training "
                          "pairs, then the same number of steps are run with zero, previous-step and "
@@ -129,7 +132,7 @@ def cpu_baseline(cl, phi, matvecs, rows_n):
     per_row_mvp = (t2 - t1) / len(rows)
     est = cl.nv * (per_row_sums + matvecs * per_row_mvp)
     return {
-        "value": est, "unit": "s/step", "cores": oracle.num_threads(), "kind": "oracle",
+        "value": est, "unit": "s/step", "cores": oracle.num_threads(), "cpu": cpu_model(), "kind": "oracle",
         "sample": (f"direct sums and one direct product for {len(rows)} evenly spaced receivers x "
                    f"{cl.nv} sources ({t2 - t0:.1f} s), scaled to {cl.nv} receivers and "
                    f"{matvecs} products (the GPU solve's count)"),
@@ -152,8 +155,10 @@ def learned_study(a):
     edges = np.concatenate([np.linalg.norm(cl.xyz[cl.tri[:, i]] - cl.xyz[cl.tri[:, (i + 1) % 3]], axis=1)
                             for i in range(3)])
     dt = 0.1 * float(edges.min()) * (1.0 / 0.5) ** 0.5
-    sv = bfm.Solver(device=0, p=a.p, leaf_target=a.leaf, gmres_tol=a.tol, gmres_restart=a.restart,
-                    gmres_maxit=1000, precond=bfm.PRECOND_SH_COARSE, precond_degree=a.precond_degree)
+    from paper_1905_01341_amd import forms
+    sv = bfm.Solver(device=0, **forms.options("tuned", p=a.p, leaf_target=a.leaf, gmres_tol=a.tol,
+                                              gmres_restart=a.restart, precond_degree=a.precond_degree,
+                                              use_graph=0))
     sv.set_cluster(cl)
     phys = dict(sigma=0.073, kappa=1.4, p0=1.0, pa=0.5, period=5.0, forcing_sign=1.0, filter_degree=9)
     sv.set_physics(guess=bfm.GUESS_GIVEN, collect=1, **phys)
@@ -183,6 +188,69 @@ def learned_study(a):
     print(json.dumps(out), flush=True)
 
 
+def cpu_model():
+    """CPU model name of the host (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# Kernel classes whose launches are one kernel (so a roofline line can name
+# it): class -> (kernel-name function, bound, traffic-table class).
+def p2p_kernel_name(p, shape, group):
+    return {"": "bfm::k_p2p_sym", "diag_": "bfm::k_p2p_diag<true>"}.get(group)
+
+
+def roofline_entry(cls, prof, prof_steps, stats, opt_p, p_diag, nv, workload):
+    """Roofline line of one kernel class: algorithmic flops of its launches
+    over their summed event time against the FP64 peak (the FP64 MFMA peak for
+    M2L, the FP64 vector peak for the near field, which is bound by plain ALU
+    work), with the HBM traffic measured for that kernel where the traffic
+    table holds a line for it on the current sources."""
+    d = prof[cls]
+    if d["launches"] == 0 or d["ms"] <= 0:
+        return None
+    group = "diag_" if cls.startswith("diag_") else ""
+    kind = cls[len(group):]
+    p = p_diag if group else opt_p
+    if kind == "m2l":
+        shape = stats["diag_m2l_shape" if group else "m2l_shape"]
+        kname = m2l_kernel_name(p, shape) if shape >= 0 else None
+        bound, tcls = "mfma", "m2l"
+        pp = p * p
+        nch = 5 if group else 1
+        # every operator read once, every box's multipole read and local
+        # expansion written once
+        alg_bytes = 8.0 * (316 * pp * pp + 2 * stats["boxes"] * pp * nch)
+    elif kind == "p2p":
+        kname = p2p_kernel_name(p, None, group)
+        bound, tcls = "alu", "p2p"
+        # positions (24 B) and strengths of every point read once, its sums
+        # written once (one channel: 8 + 8 B; five packed channels: a 128-byte
+        # record read, five sums written)
+        alg_bytes = (40.0 if not group else 168.0) * nv
+    else:
+        return None
+    avg_ms = d["ms"] / d["launches"]
+    ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    tr = measured_traffic(tcls, kname, workload, stats["lmax"], p) if kname else None
+    return {"kernel": kname or cls, "class": cls, "bound": bound,
+            "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+            "traffic": None if tr is None else round(tr[0]),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
+            "traffic_GBps": None if tr is None else round(tr[0] / (avg_ms * 1e-3) / 1e9, 1),
+            "algorithmic_bytes": alg_bytes,
+            "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
+            "ms_per_step": round(d["ms"] / prof_steps, 4),
+            "flops_per_launch": d["flops"] / d["launches"]}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -193,6 +261,7 @@ def main():
         return learned_study(a)
     import torch
     from paper_1905_01341_amd import bfm
+    from paper_1905_01341_amd import forms
     from paper_1905_01341_amd import workload as wl
 
     cl, phi = wl.make(a.workload)
@@ -206,13 +275,8 @@ def main():
     xyz_t = torch.tensor(cl.xyz, dtype=torch.float64, device=dev).contiguous()
     phi_t = torch.tensor(phi, dtype=torch.float64, device=dev).contiguous()
     q_t = torch.zeros_like(phi_t)
-    def make_solver(precond, graph=0):
-        tol = a.plain_tol if precond == bfm.PRECOND_NONE else a.tol
-        sv = bfm.Solver(device=0, p=a.p, p_diag=a.p_diag, leaf_target=a.leaf, lmax=a.lmax,
-                        m2l_shape=a.m2l_shape, gmres_tol=tol, gmres_restart=a.restart, gmres_maxit=1000,
-                        precond=precond, precond_degree=a.precond_degree, use_graph=graph)
-        sv.set_cluster(cl)
-        return sv
+    overrides = dict(p=a.p, p_diag=a.p_diag, leaf_target=a.leaf, lmax=a.lmax, m2l_shape=a.m2l_shape,
+                     gmres_restart=a.restart, precond_degree=a.precond_degree)
 
     def run(sv, steps, warmup, profile):
         def step():
@@ -233,6 +297,8 @@ def main():
         return (t1 - t0) * 1e3 / steps, infos[-1], prof
 
     def error_vs_oracle():
+        """Relative 2-norm error of the solution now in q_t against the
+        oracle's stored solution of this workload (None if there is none)."""
         gold = os.path.join(ROOT, "tests", "golden", f"{a.workload}_q_oracle.npy")
         if not os.path.exists(gold):
             return None
@@ -242,62 +308,48 @@ def main():
     # plain FP64 (the paper's unpreconditioned GMRES from a zero guess)
     ms_plain, info_plain, err_plain = None, None, None
     if a.plain_steps > 0:
-        sv_plain = make_solver(bfm.PRECOND_NONE)
+        sv_plain, _ = forms.make_solver(cl, "plain", gmres_tol=a.plain_tol, **overrides)
+        plain_tol = sv_plain.opt.gmres_tol
         ms_plain, info_plain, _ = run(sv_plain, a.plain_steps, a.warmup, False)
         err_plain = error_vs_oracle()
         sv_plain.close()
-    # tuned form: timed for the reported value
+    # the reported form, timed for the value
     tuned = a.form == "tuned"
-    sv = make_solver(bfm.PRECOND_SH_COARSE if tuned else bfm.PRECOND_NONE, a.graph if tuned else 0)
-    tune = None
-    if tuned and a.autotune:
-        t0 = time.perf_counter()
-        tune = sv.autotune(a.tune_tol)
+    t0 = time.perf_counter()
+    if tuned:
+        sv, tune = forms.make_solver(cl, "tuned", autotune=bool(a.autotune),
+                                     tune_tol=forms.TUNE_TOL if a.tune_tol is None else a.tune_tol,
+                                     gmres_tol=a.tol, use_graph=a.graph, **overrides)
+    else:
+        sv, tune = forms.make_solver(cl, "plain", gmres_tol=a.plain_tol, **overrides)
+    if tune is not None:
         tune["seconds"] = round(time.perf_counter() - t0, 3)
-    graph_on = tuned and a.graph
-    # kernel classes are timed with HIP events around every launch inside the
-    # timed region; graph replays carry no per-kernel events, so with graphs
-    # the same solve is profiled again afterwards, eagerly
+    graph_on = bool(sv.opt.use_graph)
+    # kernel classes are timed with HIP events around every launch; graph
+    # replays carry no per-kernel events and the timing runs the near field
+    # in line, so with graphs the same solve is profiled again afterwards
     ms, info, prof = run(sv, a.steps, a.warmup, not a.no_profile and not graph_on)
+    # the error of the timed solve's result, before any profiling re-run
+    err = error_vs_oracle()
     prof_steps = a.steps
     if graph_on and not a.no_profile:
         prof_steps = max(1, min(a.steps, 3))
         _, _, prof = run(sv, prof_steps, 0, True)
     stats = sv.tree_stats()
-    err = error_vs_oracle()
+    p_diag = sv.opt.p_diag or min(20, sv.opt.p + 4)
 
-    roof = None
+    roof, roof_p2p = None, None
     if prof:
-        cand = {k: prof[k] for k in ("p2p", "m2l", "m2m_l2l")}
-        dom = max(cand, key=lambda k: cand[k]["ms"])
-        d = prof[dom]
-        avg_ms = d["ms"] / max(d["launches"], 1)
-        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
-        if dom == "p2p":
-            # the one-channel monopole product's near field (each pair once)
-            kname = "bfm::k_p2p_sym"
-            # compulsory bytes: positions (24 B) and strength (8 B) of every
-            # point read once, its sum (8 B) written once
-            alg_bytes = 40.0 * cl.nv
-        elif dom == "m2l":
-            kname = m2l_kernel_name(sv.opt.p, stats["m2l_shape"]) if stats["m2l_shape"] >= 0 else None
-            # every M2L operator read once, every box's multipole read and
-            # local expansion written once
-            pp = sv.opt.p * sv.opt.p
-            alg_bytes = 8.0 * (316 * pp * pp + 2 * stats["boxes"] * pp)
-        else:
-            kname, alg_bytes = None, None
-        tr = measured_traffic(dom, kname, a.workload, stats["lmax"], sv.opt.p) if kname else None
-        roof = {"kernel": kname or dom,
-                "bound": "alu" if dom == "p2p" else "mfma",
-                "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP64_TFLOPS, 4),
-                "traffic": None if tr is None else round(tr[0]),
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
-                "traffic_GBps": None if tr is None else round(tr[0] / (avg_ms * 1e-3) / 1e9, 1),
-                "algorithmic_bytes": alg_bytes,
-                "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
-                "flops_per_launch": d["flops"] / max(d["launches"], 1)}
+        named = [c for c in ("m2l", "p2p", "diag_m2l", "diag_p2p") if prof[c]["launches"] > 0]
+        entries = {c: roofline_entry(c, prof, prof_steps, stats, sv.opt.p, p_diag, cl.nv, a.workload)
+                   for c in named}
+        entries = {c: e for c, e in entries.items() if e is not None}
+        if entries:
+            # the kernel with the largest time per step across every product
+            # group (GMRES products and the diagonal/right-hand-side pass)
+            dom = max(entries, key=lambda c: prof[c]["ms"])
+            roof = entries[dom]
+            roof_p2p = entries.get("p2p")
     out = {
         "metric": METRIC, "value": round(ms / 1e3, 6), "unit": "s/step", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
@@ -306,26 +358,28 @@ def main():
         "config": {
             "workload": (f"{a.workload}: {cl.nb} icosphere bubbles, {cl.nv} nodes, {cl.nt} triangles"),
             "form": ("tuned: FP64 FMM products, GMRES right-preconditioned by a two-level method "
-                     f"(per-bubble spherical harmonics to degree {a.precond_degree}, then a coarse "
+                     f"(per-bubble spherical harmonics to degree {sv.opt.precond_degree}, then a coarse "
                      "correction with one unknown per bubble)") if tuned else "plain FP64",
-            "p": sv.opt.p, "p_diag": sv.opt.p_diag or min(20, a.p + 4),
-            "graph": bool(graph_on), "autotune": tune,
+            "p": sv.opt.p, "p_diag": p_diag,
+            "graph": graph_on, "autotune": tune,
             "lmax": stats["lmax"], "leaves": stats["leaves"], "near_pairs": stats["near_pairs"],
-            "m2l_pairs": stats["m2l_pairs"], "gmres_tol": a.tol, "gmres_restart": a.restart,
+            "m2l_pairs": stats["m2l_pairs"], "gmres_tol": sv.opt.gmres_tol, "gmres_restart": sv.opt.gmres_restart,
             "iterations": info["iterations"], "matvecs": info["matvecs"],
             "rel_residual": info["rel_residual"], "err_vs_oracle": err,
             "phase_ms": {"tree": round(info["t_tree_ms"], 3), "diag": round(info["t_diag_ms"], 3),
                          "gmres": round(info["t_solve_ms"], 3)},
             "plain_fp64": None if info_plain is None else {
-                "s_per_step": round(ms_plain / 1e3, 6), "gmres_tol": a.plain_tol,
+                "s_per_step": round(ms_plain / 1e3, 6), "gmres_tol": plain_tol,
                 "iterations": info_plain["iterations"],
                 "matvecs": info_plain["matvecs"], "err_vs_oracle": err_plain, "steps": a.plain_steps},
             "speedup_vs_plain": None if ms_plain is None else round(ms_plain / ms, 3),
         },
         "roofline": roof,
+        "roofline_p2p": roof_p2p,
     }
     if prof:
-        out["kernels_ms_per_step"] = {k: round(v["ms"] / prof_steps, 3) for k, v in prof.items()}
+        out["kernels_ms_per_step"] = {k: round(v["ms"] / prof_steps, 3) for k, v in prof.items()
+                                      if v["launches"] > 0}
     if not a.no_cpu_baseline:
         mv = info_plain["matvecs"] if info_plain is not None else info["matvecs"]
         out["cpu_baseline"] = cpu_baseline(cl, phi, mv, a.cpu_rows)

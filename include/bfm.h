@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BFM_ABI_VERSION 3
+#define BFM_ABI_VERSION 4
 
 enum {
     BFM_OK = 0,
@@ -73,10 +73,20 @@ enum {
                               surface and phi; needs bfm_set_sphere_template */
 };
 
-/* Arithmetic of the fast multipole product. */
+/* Arithmetic of a fast multipole product (the paper compares single- and
+ * double-precision products, Section 3.11, Table 1). The low-precision
+ * modes compute the near field in FP32 with coordinates relative to the
+ * receiver's leaf centre (sums added into FP64), the leaf expansions (P2M,
+ * L2P) in FP32, and the translations on the matrix cores with FP32
+ * expansions; the result vector stays FP64. Low-precision products carry one
+ * channel (the single or the double layer). */
 enum {
-    BFM_PREC_FP64 = 0, /* FP64 near field and FP64 translations */
-    BFM_PREC_FP32 = 1  /* FP32 near field (leaf-relative coordinates), FP32 translations */
+    BFM_PREC_FP64 = 0,  /* FP64 everywhere (FP64 VALU near field, FP64 MFMA translations) */
+    BFM_PREC_FP32 = 1,  /* FP32 translations (v_mfma_f32_16x16x4f32) */
+    BFM_PREC_BF16X3 = 2 /* split-BF16 translations: operator and input split as a = hi + lo
+                           (hi = bf16(a), lo = bf16(a - hi), round to nearest even), three
+                           products hi*hi + hi*lo + lo*hi (v_mfma_f32_16x16x32_bf16), FP32
+                           accumulation */
 };
 
 typedef struct bfm_options {
@@ -89,7 +99,16 @@ typedef struct bfm_options {
                           diagonals and b; 0 = min(20, p + 4) */
     int lmax;          /* octree depth; 0 = choose from leaf_target */
     int leaf_target;   /* mean points per non-empty leaf aimed at when lmax = 0 */
-    int precision;     /* BFM_PREC_* for the products inside GMRES */
+    int precision;     /* BFM_PREC_* of the products inside GMRES. FP64: plain restarted
+                          GMRES. FP32 or BF16X3: mixed-precision iterative refinement -
+                          each restart cycle is one refinement step: its Arnoldi process
+                          uses low-precision products of order p_lo, and it ends once its
+                          residual estimate has fallen by ir_tol (or at gmres_restart
+                          iterations); the correction is added in FP64 and the true
+                          residual b - L q is formed with an FP64 product of order p */
+    int p_lo;          /* expansion order of the low-precision products (multiple of 4,
+                          4..20); 0 = p */
+    double ir_tol;     /* relative residual reduction that ends a refinement cycle; 0 = 1e-4 */
     double gmres_tol;  /* stop when ||b - L q||_2 <= gmres_tol ||b||_2 */
     int gmres_restart; /* Krylov dimension before restart (1..128) */
     int gmres_maxit;   /* total iteration limit */
@@ -116,8 +135,9 @@ typedef struct bfm_solve_info {
 typedef struct bfm_ctx bfm_ctx;
 
 /* Fill *opt with defaults: p = 16, p_diag = 0, lmax = 0, leaf_target = 64,
- * FP64, tol 1e-10, restart 30, maxit 300, device 0, stream NULL, no
- * preconditioner (precond_degree 12), no graph, M2L shape by size. */
+ * FP64 (p_lo = 0, ir_tol = 0), tol 1e-10, restart 30, maxit 300, device 0,
+ * stream NULL, no preconditioner (precond_degree 12), no graph, M2L shape
+ * by size. */
 int bfm_default_options(bfm_options *opt);
 
 /* Create a handle on opt->device. The handle owns every device buffer
@@ -182,7 +202,8 @@ int bfm_diagonals(bfm_ctx *ctx, const double *phi, double *Mii, double *Lii, dou
  * Product with A = f L + g M (eq3_27) by the fast multipole method:
  *   out_i = sum_{j != i} (f L_ij x_j + g M_ij y_j) [+ f L_ii x_i + g M_ii y_i if add_diag]
  * x, y, out host [nv] (x may be NULL if f == 0, y if g == 0). precision
- * selects BFM_PREC_*; the product uses the handle's p. add_diag needs the
+ * selects BFM_PREC_*; an FP64 product uses the handle's p, a low-precision
+ * one its p_lo (p when 0). add_diag needs the
  * diagonals of the current mesh (computed on demand, at p_diag). direct = 1 replaces the fast multipole method by
  * the all-pairs sum on the GPU (FP64), for checking.
  */
@@ -204,6 +225,27 @@ int bfm_solve(bfm_ctx *ctx, const double *phi, double *q, int use_guess, bfm_sol
 int bfm_solve_dev(bfm_ctx *ctx, const double *phi_dev, double *q_dev, int use_guess,
                   bfm_solve_info *info);
 
+/*
+ * Direct (all-pairs) off-diagonal product on device arrays, without a
+ * handle (Section 3.2, ns1; kernels of eq2_13):
+ *   out[k] = sum_{j != i} s_j [ f x_j G(r_i, r_j) + g y_j dG/dn_j(r_i, r_j) ],
+ *   G = 1/(4 pi |r_i - r_j|),  dG/dn_j = n_j . (r_i - r_j) / (4 pi |r_i - r_j|^3),
+ *   i = rows[k] for k < nr (rows == NULL: i = k, nr <= n).
+ * All arrays are FP64 device memory on the calling thread's current HIP
+ * device, caller-owned: xyz [n][3] and nrm [n][3] row-major, s [n], x [n]
+ * (read when f != 0), y and nrm (read when g != 0), rows int64 [nr], out
+ * [nr]. Runs on `stream` (hipStream_t; NULL = the null stream) and returns
+ * without synchronising; the pointers must stay valid until the stream has
+ * passed the call. j == i is excluded by index (coincident distinct points
+ * are an invalid mesh). A row index outside [0, n) gives NaN in its out
+ * entry. The library allocates a partial-sum buffer of
+ * (source splits x nr) doubles per call, stream-ordered.
+ * Errors: BFM_EINVAL (n < 1, nr < 0, a null pointer that is needed),
+ * BFM_ENOMEM, BFM_EDEVICE.
+ */
+int bfm_direct_dev(int64_t n, const double *xyz, const double *s, const double *nrm, double f, const double *x,
+                   double g, const double *y, int64_t nr, const int64_t *rows, double *out, void *stream);
+
 /* Autotuning of the fast multipole product for the current mesh (not in the
  * paper, which tunes the octree depth by hand, Section 4): p = the smallest
  * of 8, 12, 16, 20 whose product with a fixed pseudo-random vector is within
@@ -221,27 +263,39 @@ typedef struct bfm_tune_result {
 } bfm_tune_result;
 int bfm_autotune(bfm_ctx *ctx, double mvp_tol, bfm_tune_result *out);
 
-/* Octree statistics of the current mesh (builds the tree if needed):
- * stats[0] = lmax, [1] = leaves, [2] = boxes (all levels), [3] = near-field
- * pairs, [4] = M2L pairs, [5] = M2M+L2L pairs, [6] = max points per leaf,
- * [7] = launch shape (0, 1, 2 as bfm_options.m2l_shape) of the last M2L
- * launch of a GMRES product, -1 before the first product. */
-int bfm_tree_stats(bfm_ctx *ctx, int64_t stats[8]);
+/* Octree statistics of the current mesh (builds the tree if needed), the
+ * first n of: stats[0] = lmax, [1] = leaves, [2] = boxes (all levels),
+ * [3] = near-field pairs, [4] = M2L pairs, [5] = M2M+L2L pairs, [6] = max
+ * points per leaf, [7] = launch shape (0, 1, 2 as bfm_options.m2l_shape) of
+ * the last M2L launch of an FP64 GMRES product, [8] = the same for the
+ * diagonal/right-hand-side pass (-1 before the first launch); entries past
+ * BFM_TREE_STATS are set to 0. stats is a host array of n entries. */
+#define BFM_TREE_STATS 9
+int bfm_tree_stats(bfm_ctx *ctx, int n, int64_t *stats);
 
 /*
- * Kernel timing (measurement support). Classes: 0 near-field P2P, 1 M2L
- * translations, 2 M2M + L2L translations, 3 P2M, 4 L2P, 5 GMRES vector
- * kernels, 6 octree build (whole), 7 diagonal/right-hand-side pass (whole).
+ * Kernel timing (measurement support). The five kernels of a fast multipole
+ * product are counted per product group, the group's P2P first:
+ *   0..4   FP64 products of GMRES: 0 near-field P2P, 1 M2L, 2 M2M + L2L,
+ *          3 P2M, 4 L2P
+ *   5      GMRES vector kernels,  6 octree build (whole),
+ *   7      diagonal/right-hand-side pass (whole)
+ *   8..12  the diagonal/right-hand-side pass's P2P, M2L, M2M + L2L, P2M, L2P
+ *   13..17 low-precision products (iterative refinement), same order
  * bfm_profile(ctx, 1) clears and starts recording HIP events around every
- * launch of these classes on the handle's stream; bfm_profile(ctx, 0) stops.
- * bfm_profile_read synchronises the stream and returns, per class, the summed
- * event time in ms, the number of launches, and the summed algorithmic work
- * of those launches (flops for 0..4: near-field pairs x flops per pair, and
- * 2 p^4 per translated expansion column; 0 for 5..7). Arrays have 8 entries.
+ * launch of these classes on the stream it is launched on; while recording,
+ * the near field runs in line on the handle's stream (not beside the far
+ * field) so that each kernel's events measure it alone, and GMRES does not
+ * replay graphs. bfm_profile(ctx, 0) stops. bfm_profile_read synchronises
+ * and returns, for the first nclass classes (host arrays of nclass entries),
+ * the summed event time in ms, the number of launches and the summed
+ * algorithmic work of those launches (flops for the product kernels:
+ * near-field pairs x flops per pair, 2 p^4 per translated expansion column;
+ * 0 for P2M, L2P and classes 5..7).
  */
-#define BFM_KERNEL_CLASSES 8
+#define BFM_KERNEL_CLASSES 18
 int bfm_profile(bfm_ctx *ctx, int enable);
-int bfm_profile_read(bfm_ctx *ctx, double ms[8], int64_t launches[8], double flops[8]);
+int bfm_profile_read(bfm_ctx *ctx, int nclass, double *ms, int64_t *launches, double *flops);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *bfm_last_error(void);

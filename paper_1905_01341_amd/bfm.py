@@ -18,13 +18,14 @@ BFM_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "EMESH", -6: "EUNSUPPORTED"}
 PREC_FP64 = 0
 PREC_FP32 = 1
+PREC_BF16X3 = 2
 PRECOND_NONE = 0
 PRECOND_SH = 1
 PRECOND_SH_COARSE = 2
 GUESS_ZERO = 0
 GUESS_GIVEN = 1
 GUESS_LEARNED = 2
-ABI_VERSION = 3
+ABI_VERSION = 4
 MLP_INPUTS = 174
 MLP_OUTPUTS = 81
 MLP_NUM_PARAMS = 656465
@@ -91,6 +92,8 @@ class Options(ctypes.Structure):
         ("lmax", ctypes.c_int),
         ("leaf_target", ctypes.c_int),
         ("precision", ctypes.c_int),
+        ("p_lo", ctypes.c_int),
+        ("ir_tol", ctypes.c_double),
         ("gmres_tol", ctypes.c_double),
         ("gmres_restart", ctypes.c_int),
         ("gmres_maxit", ctypes.c_int),
@@ -157,14 +160,15 @@ def load(path: str = LIB_PATH):
         "bfm_matvec": ([P, D, P, D, P, P, I, I, I], I),
         "bfm_solve": ([P, P, P, I, ctypes.POINTER(SolveInfo)], I),
         "bfm_solve_dev": ([P, P, P, I, ctypes.POINTER(SolveInfo)], I),
-        "bfm_tree_stats": ([P, ctypes.POINTER(I64)], I),
+        "bfm_tree_stats": ([P, I, ctypes.POINTER(I64)], I),
         "bfm_last_error": ([], ctypes.c_char_p),
         "bfm_debug_operator": ([I, I, I, P, P], I),
         "bfm_debug_dgemm": ([I, I, I, I, P, P, P], I),
         "bfm_debug_spd_inverse": ([I, I, P, P], I),
         "bfm_profile": ([P, I], I),
-        "bfm_profile_read": ([P, P, P, P], I),
+        "bfm_profile_read": ([P, I, P, P, P], I),
         "bfm_autotune": ([P, D, ctypes.POINTER(TuneResult)], I),
+        "bfm_direct_dev": ([I64, P, P, P, D, P, D, P, I64, P, P, P], I),
         "bfm_default_physics": ([ctypes.POINTER(Physics)], I),
         "bfm_set_physics": ([P, ctypes.POINTER(Physics)], I),
         "bfm_state_set": ([P, P, P, D], I),
@@ -242,6 +246,26 @@ def debug_spd_inverse(A, device=0):
     out = np.empty((n, n), dtype=np.float64, order="F")
     _check(load().bfm_debug_spd_inverse(device, n, _ptr(A), _ptr(out)))
     return out
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def direct_dev(xyz_t, s_t, nrm_t, f=1.0, x_t=None, g=0.0, y_t=None, rows_t=None, out_t=None, nr=None):
+    """All-pairs off-diagonal product on torch device tensors (FP64, caller
+    order; rows_t int64 or None); returns out_t. Runs on torch's current
+    stream."""
+    import torch
+    n = xyz_t.shape[0]
+    if nr is None:
+        nr = n if rows_t is None else rows_t.numel()
+    if out_t is None:
+        out_t = torch.empty(nr, dtype=torch.float64, device=xyz_t.device)
+    st = torch.cuda.current_stream(xyz_t.device).cuda_stream
+    _check(load().bfm_direct_dev(n, _dptr(xyz_t), _dptr(s_t), _dptr(nrm_t), float(f), _dptr(x_t), float(g),
+                                 _dptr(y_t), nr, _dptr(rows_t), _dptr(out_t), ctypes.c_void_p(st)))
+    return out_t
 
 
 class Solver:
@@ -346,16 +370,20 @@ class Solver:
                                       ctypes.byref(info)))
         return info.as_dict()
 
-    KERNEL_CLASSES = ["p2p", "m2l", "m2m_l2l", "p2m", "l2p", "gmres", "tree", "diag"]
+    # kernel classes of bfm_profile_read (include/bfm.h)
+    PRODUCT_KERNELS = ["p2p", "m2l", "m2m_l2l", "p2m", "l2p"]
+    KERNEL_CLASSES = (PRODUCT_KERNELS + ["gmres", "tree", "diag"] + ["diag_" + k for k in PRODUCT_KERNELS]
+                      + ["lo_" + k for k in PRODUCT_KERNELS])
 
     def profile(self, enable: bool):
         _check(self.lib.bfm_profile(self.h, int(enable)))
 
     def profile_read(self):
-        ms = np.zeros(8)
-        n = np.zeros(8, dtype=np.int64)
-        fl = np.zeros(8)
-        _check(self.lib.bfm_profile_read(self.h, _ptr(ms), _ptr(n), _ptr(fl)))
+        k = len(self.KERNEL_CLASSES)
+        ms = np.zeros(k)
+        n = np.zeros(k, dtype=np.int64)
+        fl = np.zeros(k)
+        _check(self.lib.bfm_profile_read(self.h, k, _ptr(ms), _ptr(n), _ptr(fl)))
         return {k: dict(ms=float(ms[i]), launches=int(n[i]), flops=float(fl[i]))
                 for i, k in enumerate(self.KERNEL_CLASSES)}
 
@@ -366,9 +394,10 @@ class Solver:
         return r.as_dict()
 
     def tree_stats(self):
-        st = (ctypes.c_int64 * 8)()
-        _check(self.lib.bfm_tree_stats(self.h, st))
-        keys = ["lmax", "leaves", "boxes", "near_pairs", "m2l_pairs", "tree_pairs", "max_leaf", "m2l_shape"]
+        keys = ["lmax", "leaves", "boxes", "near_pairs", "m2l_pairs", "tree_pairs", "max_leaf", "m2l_shape",
+                "diag_m2l_shape"]
+        st = (ctypes.c_int64 * len(keys))()
+        _check(self.lib.bfm_tree_stats(self.h, len(keys), st))
         return {k: int(st[i]) for i, k in enumerate(keys)}
 
     # -- learned initial guess (include/bfm_mlp.h) ---------------------------

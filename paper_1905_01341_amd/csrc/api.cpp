@@ -11,6 +11,7 @@
 #include "../../include/bfm_mlp.h"
 #include "../../include/bfm_step.h"
 #include "ctx.h"
+#include "direct.h"
 #include "learn.h"
 #include "ops.h"
 
@@ -45,8 +46,11 @@ static void check_options(const bfm_options &o) {
               "p_diag must be 0 or a multiple of 4 in [4, 20]");
     BFM_CHECK(o.lmax == 0 || (o.lmax >= 2 && o.lmax <= 15), BFM_EINVAL, "lmax must be 0 or in [2, 15]");
     BFM_CHECK(o.leaf_target >= 1, BFM_EINVAL, "leaf_target must be >= 1");
-    BFM_CHECK(o.precision == BFM_PREC_FP64 || o.precision == BFM_PREC_FP32, BFM_EINVAL,
-              "unknown precision");
+    BFM_CHECK(o.precision == BFM_PREC_FP64 || o.precision == BFM_PREC_FP32 || o.precision == BFM_PREC_BF16X3,
+              BFM_EINVAL, "unknown precision");
+    BFM_CHECK(o.p_lo == 0 || (o.p_lo >= 4 && o.p_lo <= kMaxP && o.p_lo % 4 == 0), BFM_EINVAL,
+              "p_lo must be 0 or a multiple of 4 in [4, 20]");
+    BFM_CHECK(o.ir_tol >= 0.0 && o.ir_tol < 1.0, BFM_EINVAL, "ir_tol must be in [0, 1)");
     BFM_CHECK(o.gmres_tol > 0.0 && o.gmres_tol < 1.0, BFM_EINVAL, "gmres_tol must be in (0, 1)");
     BFM_CHECK(o.gmres_restart >= 1 && o.gmres_restart <= 128, BFM_EINVAL,
               "gmres_restart must be in [1, 128]");
@@ -179,7 +183,11 @@ int bfm_create(const bfm_options *opt, bfm_ctx **out) {
         BFM_CHECK(opt->device >= 0 && opt->device < ndev, BFM_EINVAL, "device ordinal out of range");
         DeviceScope ds(opt->device);
         auto *c = new bfm_ctx();
-        c->fmm.prof = &c->prof;  // the diagonal pass is timed as a whole
+        c->fmm.prof = &c->prof;
+        c->fmm_diag.prof = &c->prof;  // the diagonal pass's kernels in their own classes
+        c->fmm_diag.prof_base = kDiagBase;
+        c->fmm_lo.prof = &c->prof;
+        c->fmm_lo.prof_base = kLoBase;
         c->opt = *opt;
         c->device = opt->device;
         if (opt->stream) {
@@ -198,6 +206,8 @@ int bfm_create(const bfm_options *opt, bfm_ctx **out) {
             if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm.ev_join, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm_diag.ev_fork, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm_diag.ev_join, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm_lo.ev_fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fmm_lo.ev_join, hipEventDisableTiming);
             if (e != hipSuccess) {
                 if (c->own_stream) (void)hipStreamDestroy(c->stream);
                 if (c->near) (void)hipStreamDestroy(c->near);
@@ -206,6 +216,7 @@ int bfm_create(const bfm_options *opt, bfm_ctx **out) {
             }
             c->fmm.near = c->near;
             c->fmm_diag.near = c->near;
+            c->fmm_lo.near = c->near;
         }
         *out = c;
     });
@@ -228,7 +239,7 @@ int bfm_destroy(bfm_ctx *c) {
             (void)hipStreamSynchronize(c->near);
             (void)hipStreamDestroy(c->near);
         }
-        for (bfm::FmmWork *w : {&c->fmm, &c->fmm_diag}) {
+        for (bfm::FmmWork *w : {&c->fmm, &c->fmm_diag, &c->fmm_lo}) {
             if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
             if (w->ev_join) (void)hipEventDestroy(w->ev_join);
         }
@@ -246,6 +257,7 @@ int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
         BFM_CHECK(opt->device == c->device, BFM_EINVAL, "cannot change the device of a handle");
         const bool tree_change = opt->lmax != c->opt.lmax || opt->leaf_target != c->opt.leaf_target;
         const bool p_change = opt->p != c->opt.p || opt->p_diag != c->opt.p_diag;
+        // (p_lo and precision take effect at the next low-precision product)
         void *keep_stream = c->opt.stream;
         c->opt = *opt;
         c->opt.stream = keep_stream;
@@ -481,23 +493,38 @@ int bfm_solve(bfm_ctx *c, const double *phi, double *q, int use_guess, bfm_solve
     return rc != BFM_OK ? rc : rc_solve;
 }
 
-int bfm_tree_stats(bfm_ctx *c, int64_t stats[8]) {
+int bfm_direct_dev(int64_t n, const double *xyz, const double *s, const double *nrm, double f, const double *x,
+                   double g, const double *y, int64_t nr, const int64_t *rows, double *out, void *stream) {
+    return guarded([&] {
+        DirectArgs a;
+        a.n = n;
+        a.xyz = xyz;
+        a.s = s;
+        a.nrm = nrm;
+        a.f = f;
+        a.x = x;
+        a.g = g;
+        a.y = y;
+        a.nr = nr;
+        a.rows = rows;
+        a.out = out;
+        direct_product(a, (hipStream_t)stream);
+    });
+}
+
+int bfm_tree_stats(bfm_ctx *c, int n, int64_t *stats) {
     return guarded([&] {
         BFM_CHECK(c && stats, BFM_EINVAL, "null argument");
+        BFM_CHECK(n >= 0, BFM_EINVAL, "negative count");
         DeviceScope ds(c->device);
         ensure_tree(c);
         const Tree &t = c->tree;
         int64_t tr = 0;
         for (size_t l = 0; l < t.m2m.size(); ++l)
             if (t.m2m[l]) tr += t.m2m[l]->ntasks;
-        stats[0] = t.lmax;
-        stats[1] = t.nleaf;
-        stats[2] = t.nbox;
-        stats[3] = t.npairs_near;
-        stats[4] = t.m2l.ntasks;
-        stats[5] = 2 * tr;
-        stats[6] = t.max_leaf;
-        stats[7] = c->fmm.m2l_shape_used;
+        const int64_t v[BFM_TREE_STATS] = {t.lmax, t.nleaf, t.nbox, t.npairs_near, t.m2l.ntasks, 2 * tr,
+                                           t.max_leaf, c->fmm.m2l_shape_used, c->fmm_diag.m2l_shape_used};
+        for (int k = 0; k < n; ++k) stats[k] = k < BFM_TREE_STATS ? v[k] : 0;
     });
 }
 
@@ -511,17 +538,19 @@ int bfm_profile(bfm_ctx *c, int enable) {
     });
 }
 
-int bfm_profile_read(bfm_ctx *c, double ms[8], int64_t launches[8], double flops[8]) {
+int bfm_profile_read(bfm_ctx *c, int nclass, double *ms, int64_t *launches, double *flops) {
     return guarded([&] {
         BFM_CHECK(c && ms && launches && flops, BFM_EINVAL, "null argument");
+        BFM_CHECK(nclass >= 0, BFM_EINVAL, "negative class count");
         DeviceScope ds(c->device);
         BFM_HIP(hipStreamSynchronize(c->stream));
-        for (int k = 0; k < KC_COUNT; ++k) {
+        for (int k = 0; k < nclass; ++k) {
             ms[k] = 0.0;
             launches[k] = 0;
             flops[k] = 0.0;
         }
         for (const auto &r : c->prof.recs) {
+            if (r.cls >= nclass) continue;
             float t = 0.f;
             BFM_HIP(hipEventElapsedTime(&t, r.a, r.b));
             ms[r.cls] += t;

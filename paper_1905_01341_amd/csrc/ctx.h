@@ -75,8 +75,9 @@ struct bfm_ctx {
     bool tree_valid = false;
 
     bfm::Prof prof;
-    bfm::FmmWork fmm;       // products inside GMRES (order p)
+    bfm::FmmWork fmm;       // FP64 products inside GMRES (order p)
     bfm::FmmWork fmm_diag;  // diagonal + right-hand-side pass (order p_diag)
+    bfm::FmmWork fmm_lo;    // low-precision products (order p_lo; iterative refinement)
 
     // sorted-order solve data
     bfm::DevBuf<double> src_q, src_w;  // channel monopole strengths, dipole weights
@@ -108,6 +109,8 @@ namespace bfm {
 void ensure_geometry(bfm_ctx *c);
 void ensure_tree(bfm_ctx *c);
 void ensure_ops(bfm_ctx *c);
+// operators of the low-precision product group for precision prec (FP32 or BF16X3)
+void ensure_ops_lo(bfm_ctx *c, int prec);
 int diag_order(const bfm_options &o);
 
 // Five-channel pass: M_ii, L_ii (sorted) and, if phi_dev != null, b (sorted).

@@ -27,11 +27,20 @@ struct Sources {
 
 struct FmmWork {
     int p = 0;
+    // arithmetic of this group's products: BFM_PREC_FP64 (the GMRES products
+    // and the diagonal pass), or BFM_PREC_FP32 / BFM_PREC_BF16X3 (the
+    // low-precision products of iterative refinement, one channel)
+    int prec = BFM_PREC_FP64;
     int nch_cap = 0;
     int64_t nbox_cap = 0;
     DevBuf<double> mexp, lexp;      // [nbox][nch][P]
     DevBuf<double> ops_m2m, ops_l2l, ops_m2l;  // operators, column-major per op: [op][k][row]
+    DevBuf<float> mexp32, lexp32;   // low-precision expansions [nbox][P]
+    DevBuf<float> opf_m2m, opf_l2l, opf_m2l;   // FP32 operators, same layout
+    // split-BF16 operators: [0] = hi, [1] = lo, [op][chunk][row][32] (K padded to 32)
+    DevBuf<uint16_t> opb_m2m[2], opb_l2l[2], opb_m2l[2];
     int ops_p = 0;
+    int ops_prec = -1;
     int m2l_shape = -1;    // M2L launch shape (-1: chosen by size)
     int m2l_shape_used = -1;  // shape of the last M2L launch (-1: none yet)
     // optional second stream for the near field (default priority): the
@@ -39,6 +48,7 @@ struct FmmWork {
     hipStream_t near = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Prof *prof = nullptr;  // optional kernel timing
+    int prof_base = 0;     // class of this product group's P2P (KC_P2P .. KC_L2P follow)
 };
 
 // Build translation operators for p (host build + upload); no-op if current.

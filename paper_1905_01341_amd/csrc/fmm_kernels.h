@@ -11,17 +11,24 @@ namespace bfm {
 // Harmonic recurrence tables (constant memory of the leaf kernels), once per device.
 void leaf_tables_upload(int device);
 
-// M[leaf box][c][p^2] = multipole expansion of every leaf (M must be zero).
-template <int P_, int NCH, bool MONO, bool DIP>
-void launch_p2m(const Tree &t, const Sources &src, double *M, hipStream_t st);
+// M[leaf box][c][p^2] = multipole expansion of every leaf (M must be zero),
+// computed and stored in R (double, or float for low-precision products).
+template <int P_, int NCH, bool MONO, bool DIP, class R = double>
+void launch_p2m(const Tree &t, const Sources &src, R *M, hipStream_t st);
 
-// y[c][i] += local expansion of point i's leaf evaluated at the point.
-template <int P_, int NCH>
-void launch_l2p(const Tree &t, const double *L, double *y, hipStream_t st);
+// y[c][i] += local expansion of point i's leaf evaluated at the point
+// (expansion and arithmetic in R; y stays FP64).
+template <int P_, int NCH, class R = double>
+void launch_l2p(const Tree &t, const R *L, double *y, hipStream_t st);
 
 // y[c][i] = near-field sum of receiver i (leaf and neighbour leaves).
 template <int NCH, bool MONO, bool DIP>
 void launch_p2p(const Tree &t, const Sources &src, double *y, hipStream_t st);
+
+// y[i] = near-field sum of one channel in FP32 arithmetic (coordinates
+// relative to the receiver's leaf centre), accumulated into FP64.
+template <bool MONO, bool DIP>
+void launch_p2p32(const Tree &t, const Sources &src, double *y, hipStream_t st);
 
 // y[c][i] = near-field sum of the five packed channels (Sources::packed).
 void launch_p2p_packed(const Tree &t, const double *packed, double *y, hipStream_t st);

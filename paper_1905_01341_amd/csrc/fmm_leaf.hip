@@ -46,12 +46,18 @@ void leaf_tables_upload(int device) {
     if (device < 32) done_mask |= 1 << device;
 }
 
-// Copy the recurrence tables for order P into LDS (block-wide).
-template <int P_>
-__device__ inline void stage_tables(double2 *rec, double *sect, int tid, int nthreads) {
+// Pair of recurrence constants in the arithmetic type R.
+template <class R>
+struct Pair2 {
+    R x, y;
+};
+
+// Copy the recurrence tables for order P into LDS (block-wide), rounded to R.
+template <int P_, class R>
+__device__ inline void stage_tables(Pair2<R> *rec, R *sect, int tid, int nthreads) {
     constexpr int NT = P_ * (P_ + 1) / 2;
-    for (int t = tid; t < NT; t += nthreads) rec[t] = c_rec[t];
-    for (int t = tid; t < P_; t += nthreads) sect[t] = c_sect[t];
+    for (int t = tid; t < NT; t += nthreads) rec[t] = Pair2<R>{(R)c_rec[t].x, (R)c_rec[t].y};
+    for (int t = tid; t < P_; t += nthreads) sect[t] = (R)c_sect[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -70,14 +76,14 @@ __device__ inline void stage_tables(double2 *rec, double *sect, int tid, int nth
 //   D Rt_n^m = ae (n_z Rt_{n-1} + z D Rt_{n-1}) - ab (2 v.n Rt_{n-2} + r^2 D Rt_{n-2})
 // Slots run over m, then degree k >= m, then (real, imaginary) for m > 0;
 // column = slot * NCH + channel.
-template <int P_, int NCH, bool MONO, bool DIP>
+template <int P_, int NCH, bool MONO, bool DIP, class R>
 __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int64_t leaf0,
                                             const int *__restrict__ leaf_pt, const double *__restrict__ centre,
                                             double h, const double *__restrict__ px, const double *__restrict__ py,
                                             const double *__restrict__ pz, const double *__restrict__ pnx,
                                             const double *__restrict__ pny, const double *__restrict__ pnz, int64_t n,
                                             const double *__restrict__ q, const double *__restrict__ w,
-                                            double *__restrict__ mexp) {
+                                            R *__restrict__ mexp) {
     constexpr int PP = P_ * P_;
     constexpr int NT = P_ * (P_ + 1) / 2;
     constexpr int NCOL = PP * NCH;
@@ -89,16 +95,16 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
     // a flush gives each buffered column G lanes, each summing every G-th of
     // its 64 values; rows of 64 + G doubles put those reads in distinct banks
     constexpr int G = 64 / CAP;
-    __shared__ double red[CAP][64 + G];
-    __shared__ double2 rec[NT];
-    __shared__ double sect[P_];
+    __shared__ R red[CAP][64 + G];
+    __shared__ Pair2<R> rec[NT];
+    __shared__ R sect[P_];
     __shared__ int outi[PP];
     const int lane = threadIdx.x;
     const int2 it = items[blockIdx.x];
     const int leaf = it.x, rb = it.y;
     const int re = min(rb + kLeafChunk, leaf_pt[leaf + 1]);
     const int64_t box = leaf0 + leaf;
-    stage_tables<P_>(rec, sect, lane, 64);
+    stage_tables<P_, R>(rec, sect, lane, 64);
     // slot -> coefficient index in the packed expansion (n^2 + 2m - 1 + imaginary)
     for (int s = lane; s < PP; s += 64) {
         int k = s, o = s * s;
@@ -115,35 +121,36 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
     }
     const double cx = centre[3 * box], cy = centre[3 * box + 1], cz = centre[3 * box + 2];
     const double ih = 1.0 / h;
-    double x[kPPL], y[kPPL], z[kPPL], r2[kPPL], sq[kPPL][NCH], sw[kPPL][NCH];
-    double ux[kPPL], uy[kPPL], uz[kPPL], vu2[kPPL];
+    R x[kPPL], y[kPPL], z[kPPL], r2[kPPL], sq[kPPL][NCH], sw[kPPL][NCH];
+    R ux[kPPL], uy[kPPL], uz[kPPL], vu2[kPPL];
 #pragma unroll
     for (int u = 0; u < kPPL; ++u) {
         const int j0 = rb + 64 * u + lane;
         const bool ok = j0 < re;
         const int j = ok ? j0 : rb;  // idle slots: the first point, zero strength
-        x[u] = (px[j] - cx) * ih;
-        y[u] = (py[j] - cy) * ih;
-        z[u] = (pz[j] - cz) * ih;
+        // leaf-relative, box-scaled coordinates formed in FP64, then rounded to R
+        x[u] = (R)((px[j] - cx) * ih);
+        y[u] = (R)((py[j] - cy) * ih);
+        z[u] = (R)((pz[j] - cz) * ih);
         r2[u] = x[u] * x[u] + y[u] * y[u] + z[u] * z[u];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            sq[u][c] = MONO ? (ok ? q[(int64_t)c * n + j] : 0.0) : 0.0;
-            sw[u][c] = DIP ? (ok ? w[(int64_t)c * n + j] * ih : 0.0) : 0.0;
+            sq[u][c] = MONO ? (R)(ok ? q[(int64_t)c * n + j] : 0.0) : R(0);
+            sw[u][c] = DIP ? (R)(ok ? w[(int64_t)c * n + j] * ih : 0.0) : R(0);
         }
-        ux[u] = DIP ? pnx[j] : 0.0;
-        uy[u] = DIP ? pny[j] : 0.0;
-        uz[u] = DIP ? pnz[j] : 0.0;
-        vu2[u] = 2.0 * (x[u] * ux[u] + y[u] * uy[u] + z[u] * uz[u]);
+        ux[u] = DIP ? (R)pnx[j] : R(0);
+        uy[u] = DIP ? (R)pny[j] : R(0);
+        uz[u] = DIP ? (R)pnz[j] : R(0);
+        vu2[u] = R(2) * (x[u] * ux[u] + y[u] * uy[u] + z[u] * uz[u]);
     }
     __syncthreads();
-    double *mbox = mexp + box * NCH * PP;
+    R *mbox = mexp + box * NCH * PP;
     int col = 0, fill = 0;  // next column, buffered columns (wave-uniform)
     // buffered column sums -> the leaf's expansion
     auto flush = [&]() {
         __syncthreads();
         const int cl = lane / G, part = lane % G;
-        double s0 = 0.0, s1 = 0.0;
+        R s0 = 0, s1 = 0;
         if (cl < fill) {
 #pragma unroll
             for (int l = 0; l < 64 / G; l += 2) {
@@ -151,7 +158,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
                 s1 += red[cl][(l + 1) * G + part];
             }
         }
-        double sum = s0 + s1;
+        R sum = s0 + s1;
 #pragma unroll
         for (int o = 1; o < G; o <<= 1) sum += __shfl_xor(sum, o);
         if (cl < fill && part == 0) {
@@ -162,27 +169,27 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
         __syncthreads();
         fill = 0;
     };
-    auto put = [&](double v) {
+    auto put = [&](R v) {
         red[fill][lane] = v;
         ++fill;
         ++col;
     };
-    double dr[kPPL], di[kPPL], Ddr[kPPL], Ddi[kPPL];  // Rt_m^m and its derivative
+    R dr[kPPL], di[kPPL], Ddr[kPPL], Ddi[kPPL];  // Rt_m^m and its derivative
 #pragma unroll
     for (int u = 0; u < kPPL; ++u) {
-        dr[u] = 1.0;
-        di[u] = Ddr[u] = Ddi[u] = 0.0;
+        dr[u] = 1;
+        di[u] = Ddr[u] = Ddi[u] = 0;
     }
 #pragma unroll 1
     for (int m = 0; m < P_; ++m) {
         if (m > 0) {
-            const double f = sect[m];
+            const R f = sect[m];
 #pragma unroll
             for (int u = 0; u < kPPL; ++u) {
-                const double nr = (dr[u] * x[u] - di[u] * y[u]) * f, ni = (dr[u] * y[u] + di[u] * x[u]) * f;
+                const R nr = (dr[u] * x[u] - di[u] * y[u]) * f, ni = (dr[u] * y[u] + di[u] * x[u]) * f;
                 if (DIP) {
-                    const double nDr = (Ddr[u] * x[u] - Ddi[u] * y[u] + dr[u] * ux[u] - di[u] * uy[u]) * f;
-                    const double nDi = (Ddr[u] * y[u] + Ddi[u] * x[u] + dr[u] * uy[u] + di[u] * ux[u]) * f;
+                    const R nDr = (Ddr[u] * x[u] - Ddi[u] * y[u] + dr[u] * ux[u] - di[u] * uy[u]) * f;
+                    const R nDi = (Ddr[u] * y[u] + Ddi[u] * x[u] + dr[u] * uy[u] + di[u] * ux[u]) * f;
                     Ddr[u] = nDr;
                     Ddi[u] = nDi;
                 }
@@ -193,27 +200,27 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
         // degrees k = m, m+1, ...: two register sets take turns holding the
         // current and the previous degree (the new degree overwrites the
         // previous one), two degrees per loop trip
-        double Ar[kPPL], Ai[kPPL], Br[kPPL], Bi[kPPL], DAr[kPPL], DAi[kPPL], DBr[kPPL], DBi[kPPL];
+        R Ar[kPPL], Ai[kPPL], Br[kPPL], Bi[kPPL], DAr[kPPL], DAi[kPPL], DBr[kPPL], DBi[kPPL];
 #pragma unroll
         for (int u = 0; u < kPPL; ++u) {
             Ar[u] = dr[u];
             Ai[u] = di[u];
             DAr[u] = Ddr[u];
             DAi[u] = Ddi[u];
-            Br[u] = Bi[u] = DBr[u] = DBi[u] = 0.0;
+            Br[u] = Bi[u] = DBr[u] = DBi[u] = 0;
         }
         // P <- degree k from C (degree k-1) and P (degree k-2)
-        auto advance = [&](int t, const double(&Cr)[kPPL], const double(&Ci)[kPPL], const double(&DCr)[kPPL],
-                           const double(&DCi)[kPPL], double(&Pr)[kPPL], double(&Pi)[kPPL], double(&DPr)[kPPL],
-                           double(&DPi)[kPPL]) {
-            const double2 ca = rec[t];
+        auto advance = [&](int t, const R(&Cr)[kPPL], const R(&Ci)[kPPL], const R(&DCr)[kPPL],
+                           const R(&DCi)[kPPL], R(&Pr)[kPPL], R(&Pi)[kPPL], R(&DPr)[kPPL],
+                           R(&DPi)[kPPL]) {
+            const Pair2<R> ca = rec[t];
 #pragma unroll
             for (int u = 0; u < kPPL; ++u) {
-                const double ez = ca.x * z[u], br = ca.y * r2[u];
+                const R ez = ca.x * z[u], br = ca.y * r2[u];
                 if (DIP) {
-                    const double eu = ca.x * uz[u], bv = ca.y * vu2[u];
-                    const double nDr = eu * Cr[u] + ez * DCr[u] - bv * Pr[u] - br * DPr[u];
-                    const double nDi = eu * Ci[u] + ez * DCi[u] - bv * Pi[u] - br * DPi[u];
+                    const R eu = ca.x * uz[u], bv = ca.y * vu2[u];
+                    const R nDr = eu * Cr[u] + ez * DCr[u] - bv * Pr[u] - br * DPr[u];
+                    const R nDi = eu * Ci[u] + ez * DCi[u] - bv * Pi[u] - br * DPi[u];
                     DPr[u] = nDr;
                     DPi[u] = nDi;
                 }
@@ -222,11 +229,11 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
             }
         };
         // the conjugated coefficient of degree k (held in C) for every channel
-        auto emit = [&](const double(&Cr)[kPPL], const double(&Ci)[kPPL], const double(&DCr)[kPPL],
-                        const double(&DCi)[kPPL]) {
+        auto emit = [&](const R(&Cr)[kPPL], const R(&Ci)[kPPL], const R(&DCr)[kPPL],
+                        const R(&DCi)[kPPL]) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                double v = sq[0][c] * Cr[0] + sw[0][c] * DCr[0];
+                R v = sq[0][c] * Cr[0] + sw[0][c] * DCr[0];
 #pragma unroll
                 for (int u = 1; u < kPPL; ++u) v += sq[u][c] * Cr[u] + sw[u][c] * DCr[u];
                 put(v);
@@ -234,7 +241,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
             if (m > 0) {
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    double v = sq[0][c] * Ci[0] + sw[0][c] * DCi[0];
+                    R v = sq[0][c] * Ci[0] + sw[0][c] * DCi[0];
 #pragma unroll
                     for (int u = 1; u < kPPL; ++u) v += sq[u][c] * Ci[u] + sw[u][c] * DCi[u];
                     put(-v);
@@ -267,79 +274,78 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
 // the harmonics built in registers order by order. The leaf's coefficients
 // and the recurrence constants are first copied to LDS with coalesced loads;
 // every step reads them at a wave-uniform LDS address.
-template <int P_, int NCH>
+template <int P_, int NCH, class R>
 __global__ void __launch_bounds__(64) k_l2p(const int2 *__restrict__ items, int64_t leaf0,
                                             const int *__restrict__ leaf_pt, const double *__restrict__ centre,
                                             double h, const double *__restrict__ px, const double *__restrict__ py,
                                             const double *__restrict__ pz, int64_t n,
-                                            const double *__restrict__ lexp, double *__restrict__ y) {
+                                            const R *__restrict__ lexp, double *__restrict__ y) {
     constexpr int PP = P_ * P_;
     constexpr int NT = P_ * (P_ + 1) / 2;
-    __shared__ double Ls[NCH * PP];
-    __shared__ double2 rec[NT];
-    __shared__ double sect[P_];
+    __shared__ R Ls[NCH * PP];
+    __shared__ Pair2<R> rec[NT];
+    __shared__ R sect[P_];
     const int lane = threadIdx.x;
     const int2 it = items[blockIdx.x];
     const int leaf = it.x, rb = it.y;
     const int re = min(rb + kLeafChunk, leaf_pt[leaf + 1]);
     const int64_t box = leaf0 + leaf;
-    const double *L = lexp + box * NCH * PP;
+    const R *L = lexp + box * NCH * PP;
     for (int t = lane; t < NCH * PP; t += 64) Ls[t] = L[t];
-    stage_tables<P_>(rec, sect, lane, 64);
+    stage_tables<P_, R>(rec, sect, lane, 64);
     const double ih = 1.0 / h;
     const double cx = centre[3 * box], cy = centre[3 * box + 1], cz = centre[3 * box + 2];
-    double x[kPPL], yy[kPPL], z[kPPL], r2[kPPL], acc[kPPL][NCH];
+    R x[kPPL], yy[kPPL], z[kPPL], r2[kPPL], acc[kPPL][NCH];
 #pragma unroll
     for (int u = 0; u < kPPL; ++u) {
         const int j0 = rb + 64 * u + lane;
         const int j = j0 < re ? j0 : rb;
-        x[u] = (px[j] - cx) * ih;
-        yy[u] = (py[j] - cy) * ih;
-        z[u] = (pz[j] - cz) * ih;
+        x[u] = (R)((px[j] - cx) * ih);
+        yy[u] = (R)((py[j] - cy) * ih);
+        z[u] = (R)((pz[j] - cz) * ih);
         r2[u] = x[u] * x[u] + yy[u] * yy[u] + z[u] * z[u];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) acc[u][c] = 0.0;
+        for (int c = 0; c < NCH; ++c) acc[u][c] = 0;
     }
     __syncthreads();
-    double dr[kPPL], di[kPPL];
+    R dr[kPPL], di[kPPL];
 #pragma unroll
     for (int u = 0; u < kPPL; ++u) {
-        dr[u] = 1.0;
-        di[u] = 0.0;
+        dr[u] = 1;
+        di[u] = 0;
     }
 #pragma unroll 1
     for (int m = 0; m < P_; ++m) {
         if (m > 0) {
-            const double f = sect[m];
+            const R f = sect[m];
 #pragma unroll
             for (int u = 0; u < kPPL; ++u) {
-                const double nr = (dr[u] * x[u] - di[u] * yy[u]) * f, ni = (dr[u] * yy[u] + di[u] * x[u]) * f;
+                const R nr = (dr[u] * x[u] - di[u] * yy[u]) * f, ni = (dr[u] * yy[u] + di[u] * x[u]) * f;
                 dr[u] = nr;
                 di[u] = ni;
             }
         }
-        double Ar[kPPL], Ai[kPPL], Br[kPPL], Bi[kPPL];  // current / previous degree, taking turns
+        R Ar[kPPL], Ai[kPPL], Br[kPPL], Bi[kPPL];  // current / previous degree, taking turns
 #pragma unroll
         for (int u = 0; u < kPPL; ++u) {
             Ar[u] = dr[u];
             Ai[u] = di[u];
-            Br[u] = Bi[u] = 0.0;
+            Br[u] = Bi[u] = 0;
         }
-        const double wgt = (m == 0) ? 1.0 : 2.0;
-        auto advance = [&](int t, const double(&Cr)[kPPL], const double(&Ci)[kPPL], double(&Pr)[kPPL],
-                           double(&Pi)[kPPL]) {
-            const double2 ca = rec[t];
+        const R wgt = (m == 0) ? R(1) : R(2);
+        auto advance = [&](int t, const R(&Cr)[kPPL], const R(&Ci)[kPPL], R(&Pr)[kPPL], R(&Pi)[kPPL]) {
+            const Pair2<R> ca = rec[t];
 #pragma unroll
             for (int u = 0; u < kPPL; ++u) {
-                const double ez = ca.x * z[u], br = ca.y * r2[u];
+                const R ez = ca.x * z[u], br = ca.y * r2[u];
                 Pr[u] = ez * Cr[u] - br * Pr[u];
                 Pi[u] = ez * Ci[u] - br * Pi[u];
             }
         };
-        auto gather = [&](int li, const double(&Cr)[kPPL], const double(&Ci)[kPPL]) {
+        auto gather = [&](int li, const R(&Cr)[kPPL], const R(&Ci)[kPPL]) {
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                const double lre = wgt * Ls[c * PP + li], lim = (m == 0) ? 0.0 : wgt * Ls[c * PP + li + 1];
+                const R lre = wgt * Ls[c * PP + li], lim = (m == 0) ? R(0) : wgt * Ls[c * PP + li + 1];
 #pragma unroll
                 for (int u = 0; u < kPPL; ++u) acc[u][c] += lre * Cr[u] - lim * Ci[u];
             }
@@ -369,28 +375,28 @@ __global__ void __launch_bounds__(64) k_l2p(const int2 *__restrict__ items, int6
         const int j = rb + 64 * u + lane;
         if (j < re) {
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + j] += acc[u][c] * ih;
+            for (int c = 0; c < NCH; ++c) y[(int64_t)c * n + j] += (double)acc[u][c] * ih;
         }
     }
 }
 
-template <int P_, int NCH, bool MONO, bool DIP>
-void launch_p2m(const Tree &t, const Sources &src, double *M, hipStream_t st) {
+template <int P_, int NCH, bool MONO, bool DIP, class R>
+void launch_p2m(const Tree &t, const Sources &src, R *M, hipStream_t st) {
     if (t.n_leaf_items <= 0) return;
     const int64_t leaf0 = t.lvl_off[t.lmax];
     const double hleaf = t.side / (double)(1 << t.lmax);
-    k_p2m<P_, NCH, MONO, DIP><<<(unsigned)t.n_leaf_items, 64, 0, st>>>(
+    k_p2m<P_, NCH, MONO, DIP, R><<<(unsigned)t.n_leaf_items, 64, 0, st>>>(
         t.leaf_items.get(), leaf0, t.leaf_pt.get(), t.box_centre.get(), hleaf, t.px.get(), t.py.get(), t.pz.get(),
         t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, M);
     BFM_LAUNCHED();
 }
 
-template <int P_, int NCH>
-void launch_l2p(const Tree &t, const double *L, double *y, hipStream_t st) {
+template <int P_, int NCH, class R>
+void launch_l2p(const Tree &t, const R *L, double *y, hipStream_t st) {
     if (t.n_leaf_items <= 0) return;
     const int64_t leaf0 = t.lvl_off[t.lmax];
     const double hleaf = t.side / (double)(1 << t.lmax);
-    k_l2p<P_, NCH><<<(unsigned)t.n_leaf_items, 64, 0, st>>>(t.leaf_items.get(), leaf0, t.leaf_pt.get(),
+    k_l2p<P_, NCH, R><<<(unsigned)t.n_leaf_items, 64, 0, st>>>(t.leaf_items.get(), leaf0, t.leaf_pt.get(),
                                                            t.box_centre.get(), hleaf, t.px.get(), t.py.get(),
                                                            t.pz.get(), t.n, L, y);
     BFM_LAUNCHED();
@@ -402,7 +408,11 @@ void launch_l2p(const Tree &t, const double *L, double *y, hipStream_t st) {
     template void launch_p2m<P, 1, true, true>(const Tree &, const Sources &, double *, hipStream_t);  \
     template void launch_p2m<P, 5, true, true>(const Tree &, const Sources &, double *, hipStream_t);  \
     template void launch_l2p<P, 1>(const Tree &, const double *, double *, hipStream_t);               \
-    template void launch_l2p<P, 5>(const Tree &, const double *, double *, hipStream_t);
+    template void launch_l2p<P, 5>(const Tree &, const double *, double *, hipStream_t);               \
+    template void launch_p2m<P, 1, true, false, float>(const Tree &, const Sources &, float *, hipStream_t); \
+    template void launch_p2m<P, 1, false, true, float>(const Tree &, const Sources &, float *, hipStream_t); \
+    template void launch_p2m<P, 1, true, true, float>(const Tree &, const Sources &, float *, hipStream_t);  \
+    template void launch_l2p<P, 1, float>(const Tree &, const float *, double *, hipStream_t);
 BFM_LEAF_INST(4)
 BFM_LEAF_INST(8)
 BFM_LEAF_INST(12)

@@ -467,6 +467,237 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_sym(const int4 *__restrict_
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// FP32 near field (low-precision products). Coordinates are taken relative to
+// the receiver leaf's centre in FP64 and rounded to FP32, so that the
+// rounding error of a coordinate is relative to the leaf size rather than to
+// the cube; 1/r is the hardware FP32 estimate (v_rsq_f32, about one ulp).
+// The sums over a block of 64 sources run in FP32 and are added into FP64
+// accumulators after each block.
+
+// Symmetric form of one channel of monopoles (k_p2p_sym's items and pair
+// order): each unordered pair once, its two terms added to both points.
+template <int R>
+__device__ inline void p2p_sym32_block(const float4 *src, float *sacc, const float *xi, const float *yi,
+                                       const float *zi, const float *qi, double *accd, int b, bool diag) {
+    const int lane = threadIdx.x;
+    float acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.f;
+#pragma unroll 2
+    for (int t = 0; t < kP2PThreads; ++t) {
+        const int s = (lane + t) & (kP2PThreads - 1);
+        const float4 a = src[s];
+        float c = 0.f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            // diagonal block: groups above b skipped, group b one-sided without
+            // the receiver itself (step 0), groups below both ways
+            if (diag && (k > b || (k == b && t == 0))) continue;  // wave-uniform
+            const float dx = xi[k] - a.x, dy = yi[k] - a.y, dz = zi[k] - a.z;
+            const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+            acc[k] = fmaf(a.w, inv, acc[k]);
+            if (!diag || k < b) c = fmaf(qi[k], inv, c);
+        }
+        if (!diag || b > 0) atomicAdd(sacc + s, c);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) accd[k] += (double)acc[k];
+}
+
+template <int R>
+__device__ inline void p2p_sym32_item(int leaf, int r0, int r1, int s0, int s1, const int2 *__restrict__ near_rng,
+                                      const int *__restrict__ near_cnt, double ox, double oy, double oz,
+                                      const double *__restrict__ px, const double *__restrict__ py,
+                                      const double *__restrict__ pz, const double *__restrict__ q,
+                                      double *__restrict__ y, float4 *src, float *sacc) {
+    const int lane = threadIdx.x;
+    float xi[R], yi[R], zi[R], qi[R];
+    double accd[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = r0 + lane + k * kP2PThreads;
+        const bool ok = i < r1;
+        // idle receivers sit far away with no weight; never stored
+        xi[k] = ok ? (float)(px[i] - ox) : 1e30f;
+        yi[k] = ok ? (float)(py[i] - oy) : 0.f;
+        zi[k] = ok ? (float)(pz[i] - oz) : 0.f;
+        qi[k] = ok ? (float)q[i] : 0.f;
+        accd[k] = 0.0;
+    }
+    if (s1 <= r1 - r0) {
+        // the chunk's own points, in blocks of 64 aligned with the receiver groups
+        for (int base = s0; base < s1; base += kP2PThreads) {
+            const int j = r0 + base + lane;
+            const bool ok = base + lane < s1;
+            src[lane] = ok ? make_float4((float)(px[j] - ox), (float)(py[j] - oy), (float)(pz[j] - oz), (float)q[j])
+                           : make_float4(-1e30f, 0.f, 0.f, 0.f);
+            sacc[lane] = 0.f;
+            __syncthreads();
+            const int b = base / kP2PThreads;
+            p2p_sym32_block<R>(src, sacc, xi, yi, zi, qi, accd, b, true);
+            __syncthreads();
+            if (ok && b > 0) unsafeAtomicAdd(y + j, (double)sacc[lane]);
+        }
+    } else {
+        const int2 *rng = near_rng + 27 * (int64_t)leaf;
+        const int nr = near_cnt[leaf];
+        for (int base = s0; base < s1; base += kP2PThreads) {
+            const int p = base + lane;
+            int j = -1, cum = 0;
+            for (int g = 0; g < nr; ++g) {
+                const int2 r = rng[g];
+                const int a = max(r.x, r0), len = max(0, r.y - a);
+                if (p >= cum && p < cum + len) j = a + (p - cum);
+                cum += len;
+            }
+            const bool ok = p < s1 && j >= 0;
+            src[lane] = ok ? make_float4((float)(px[j] - ox), (float)(py[j] - oy), (float)(pz[j] - oz), (float)q[j])
+                           : make_float4(-1e30f, 0.f, 0.f, 0.f);
+            sacc[lane] = 0.f;
+            __syncthreads();
+            p2p_sym32_block<R>(src, sacc, xi, yi, zi, qi, accd, 0, false);
+            __syncthreads();
+            if (ok) unsafeAtomicAdd(y + j, (double)sacc[lane]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = r0 + lane + k * kP2PThreads;
+        if (i < r1) unsafeAtomicAdd(y + i, accd[k]);
+    }
+}
+
+__global__ void __launch_bounds__(kP2PThreads) k_p2p_sym32(const int4 *__restrict__ items,
+                                                           const int *__restrict__ leaf_pt,
+                                                           const int2 *__restrict__ near_rng,
+                                                           const int *__restrict__ near_cnt,
+                                                           const double *__restrict__ centre, int64_t leaf0,
+                                                           const double *__restrict__ px,
+                                                           const double *__restrict__ py,
+                                                           const double *__restrict__ pz,
+                                                           const double *__restrict__ q, double *__restrict__ y) {
+    __shared__ float4 src[kP2PThreads];
+    __shared__ float sacc[kP2PThreads];
+    const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
+    const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
+    const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
+    const int leaf = it.x, r0 = it.y, s0 = it.z, s1 = it.w;
+    const int r1 = min(r0 + kSymChunk, leaf_pt[leaf + 1]);
+    const double *c = centre + 3 * (leaf0 + leaf);
+    const double ox = c[0], oy = c[1], oz = c[2];
+    switch ((r1 - r0 + kP2PThreads - 1) / kP2PThreads) {
+        case 1:
+            p2p_sym32_item<1>(leaf, r0, r1, s0, s1, near_rng, near_cnt, ox, oy, oz, px, py, pz, q, y, src, sacc);
+            break;
+        case 2:
+            p2p_sym32_item<2>(leaf, r0, r1, s0, s1, near_rng, near_cnt, ox, oy, oz, px, py, pz, q, y, src, sacc);
+            break;
+        case 3:
+            p2p_sym32_item<3>(leaf, r0, r1, s0, s1, near_rng, near_cnt, ox, oy, oz, px, py, pz, q, y, src, sacc);
+            break;
+        default:
+            p2p_sym32_item<4>(leaf, r0, r1, s0, s1, near_rng, near_cnt, ox, oy, oz, px, py, pz, q, y, src, sacc);
+            break;
+    }
+}
+
+// One-sided FP32 form (any channel content; k_p2p's items and pieces):
+// receivers rc + lane + 64 k of the leaf against sources s0..s1-1 of its list,
+// read at wave-uniform addresses and shifted to the leaf centre per lane.
+template <bool MONO, bool DIP, bool SELF>
+__device__ inline void p2p32_range(int j0, int j1, double ox, double oy, double oz, const double *__restrict__ px,
+                                   const double *__restrict__ py, const double *__restrict__ pz,
+                                   const double *__restrict__ pnx, const double *__restrict__ pny,
+                                   const double *__restrict__ pnz, const double *__restrict__ q,
+                                   const double *__restrict__ w, const float *xi, const float *yi, const float *zi,
+                                   double *accd) {
+    constexpr int R = kP2PChunk / kP2PThreads;
+    for (int b0 = j0; b0 < j1; b0 += kP2PThreads) {
+        const int b1 = min(j1, b0 + kP2PThreads);
+        float acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = 0.f;
+        for (int j = b0; j < b1; ++j) {
+            const float sx = (float)(px[j] - ox), sy = (float)(py[j] - oy), sz = (float)(pz[j] - oz);
+            const float sq = MONO ? (float)q[j] : 0.f, sw = DIP ? (float)w[j] : 0.f;
+            const float nx = DIP ? (float)pnx[j] : 0.f, ny = DIP ? (float)pny[j] : 0.f, nz = DIP ? (float)pnz[j] : 0.f;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const float dx = xi[k] - sx, dy = yi[k] - sy, dz = zi[k] - sz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float inv = (!SELF || r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;  // j == i excluded
+                if (MONO) acc[k] = fmaf(sq, inv, acc[k]);
+                if (DIP) acc[k] = fmaf(sw * (nx * dx + ny * dy + nz * dz), inv * inv * inv, acc[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) accd[k] += (double)acc[k];
+    }
+}
+
+template <bool MONO, bool DIP, bool ATOMIC>
+__global__ void __launch_bounds__(kP2PThreads) k_p2p32(const int4 *__restrict__ items,
+                                                       const int *__restrict__ leaf_pt,
+                                                       const int2 *__restrict__ near_rng,
+                                                       const int *__restrict__ near_cnt,
+                                                       const double *__restrict__ centre, int64_t leaf0,
+                                                       const double *__restrict__ px, const double *__restrict__ py,
+                                                       const double *__restrict__ pz, const double *__restrict__ pnx,
+                                                       const double *__restrict__ pny, const double *__restrict__ pnz,
+                                                       const double *__restrict__ q, const double *__restrict__ w,
+                                                       double *__restrict__ y) {
+    constexpr int R = kP2PChunk / kP2PThreads;
+    const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
+    const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
+    const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
+    const int leaf = it.x, rc = it.y, s0 = it.z, s1 = it.w;
+    const int l0 = leaf_pt[leaf], r1 = leaf_pt[leaf + 1];
+    const double *c = centre + 3 * (leaf0 + leaf);
+    const double ox = c[0], oy = c[1], oz = c[2];
+    const int lane = threadIdx.x;
+    float xi[R], yi[R], zi[R];
+    double accd[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        const bool ok = i < r1;
+        xi[k] = ok ? (float)(px[i] - ox) : 1e30f;  // idle lanes sit far away; never stored
+        yi[k] = ok ? (float)(py[i] - oy) : 0.f;
+        zi[k] = ok ? (float)(pz[i] - oz) : 0.f;
+        accd[k] = 0.0;
+    }
+    const int2 *rng = near_rng + 27 * (int64_t)leaf;
+    const int nr = near_cnt[leaf];
+    int cum = 0;
+    for (int g = 0; g < nr && cum < s1; ++g) {
+        const int2 r = rng[g];
+        const int len = r.y - r.x;
+        const int a = r.x + max(0, s0 - cum), b = r.x + min(len, s1 - cum);
+        cum += len;
+        if (a >= b) continue;
+        if (a < r1 && l0 < b) {
+            const int m0 = max(a, l0), m1 = min(b, r1);
+            p2p32_range<MONO, DIP, false>(a, m0, ox, oy, oz, px, py, pz, pnx, pny, pnz, q, w, xi, yi, zi, accd);
+            p2p32_range<MONO, DIP, true>(m0, m1, ox, oy, oz, px, py, pz, pnx, pny, pnz, q, w, xi, yi, zi, accd);
+            p2p32_range<MONO, DIP, false>(m1, b, ox, oy, oz, px, py, pz, pnx, pny, pnz, q, w, xi, yi, zi, accd);
+        } else {
+            p2p32_range<MONO, DIP, false>(a, b, ox, oy, oz, px, py, pz, pnx, pny, pnz, q, w, xi, yi, zi, accd);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int i = rc + lane + k * kP2PThreads;
+        if (i < r1) {
+            if (ATOMIC)
+                unsafeAtomicAdd(y + i, accd[k]);
+            else
+                y[i] = accd[k];
+        }
+    }
+}
+
 __global__ void k_clear(double *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -546,6 +777,37 @@ void launch_direct(const Tree &t, const Sources &src, double *y, hipStream_t st)
         t.px.get(), t.py.get(), t.pz.get(), t.pnx.get(), t.pny.get(), t.pnz.get(), t.n, src.q, src.w, y);
     BFM_LAUNCHED();
 }
+
+
+template <bool MONO, bool DIP>
+void launch_p2p32(const Tree &t, const Sources &src, double *y, hipStream_t st) {
+    if (t.n_near_items <= 0) return;
+    const int64_t leaf0 = t.lvl_off[t.lmax];
+    if constexpr (MONO && !DIP) {
+        BFM_CHECK(t.n_sym_items > 0, BFM_EINVAL, "symmetric near-field items missing");
+        k_clear<<<1024, 256, 0, st>>>(y, t.n);
+        BFM_LAUNCHED();
+        k_p2p_sym32<<<(unsigned)t.n_sym_items, kP2PThreads, 0, st>>>(
+            t.sym_items.get(), t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(), t.box_centre.get(), leaf0,
+            t.px.get(), t.py.get(), t.pz.get(), src.q, y);
+        BFM_LAUNCHED();
+        return;
+    }
+    if (t.near_split) {
+        k_clear<<<1024, 256, 0, st>>>(y, t.n);
+        BFM_LAUNCHED();
+    }
+    auto kern = t.near_split ? k_p2p32<MONO, DIP, true> : k_p2p32<MONO, DIP, false>;
+    kern<<<(unsigned)t.n_near_items, kP2PThreads, 0, st>>>(t.near_items.get(), t.leaf_pt.get(), t.near_rng.get(),
+                                                           t.near_cnt.get(), t.box_centre.get(), leaf0, t.px.get(),
+                                                           t.py.get(), t.pz.get(), t.pnx.get(), t.pny.get(),
+                                                           t.pnz.get(), src.q, src.w, y);
+    BFM_LAUNCHED();
+}
+
+template void launch_p2p32<true, false>(const Tree &, const Sources &, double *, hipStream_t);
+template void launch_p2p32<false, true>(const Tree &, const Sources &, double *, hipStream_t);
+template void launch_p2p32<true, true>(const Tree &, const Sources &, double *, hipStream_t);
 
 #define BFM_NEAR_INST(NCH, MONO, DIP)                                                                    \
     template void launch_p2p<NCH, MONO, DIP>(const Tree &, const Sources &, double *, hipStream_t); \

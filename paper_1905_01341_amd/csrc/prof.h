@@ -9,7 +9,14 @@
 
 namespace bfm {
 
-enum KernelClass { KC_P2P = 0, KC_M2L, KC_M2M_L2L, KC_P2M, KC_L2P, KC_GMRES, KC_TREE, KC_DIAG, KC_COUNT };
+// Kernel classes. The five kernels of a fast multipole product (P2P .. L2P)
+// are counted per product group: the FP64 products of GMRES at classes 0..4,
+// the diagonal/right-hand-side pass at kDiagBase + 0..4 and the
+// low-precision products of iterative refinement at kLoBase + 0..4.
+enum KernelClass { KC_P2P = 0, KC_M2L, KC_M2M_L2L, KC_P2M, KC_L2P, KC_GMRES, KC_TREE, KC_DIAG };
+constexpr int kDiagBase = 8;
+constexpr int kLoBase = 13;
+constexpr int kClassCount = 18;
 
 struct Prof {
     bool on = false;

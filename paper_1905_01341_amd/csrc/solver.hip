@@ -114,6 +114,16 @@ void ensure_ops(bfm_ctx *c) {
     fmm_prepare_ops(c->fmm_diag, c->fmm_diag.p, c->stream);
 }
 
+void ensure_ops_lo(bfm_ctx *c, int prec) {
+    BFM_CHECK(prec == BFM_PREC_FP32 || prec == BFM_PREC_BF16X3, BFM_EINVAL, "not a low precision");
+    const int p = c->opt.p_lo > 0 ? c->opt.p_lo : c->opt.p;
+    if (c->fmm_lo.prec != prec || c->fmm_lo.p != p) graph_invalidate(c);
+    c->fmm_lo.prec = prec;
+    c->fmm_lo.p = p;
+    c->fmm_lo.m2l_shape = c->opt.m2l_shape;
+    fmm_prepare_ops(c->fmm_lo, p, c->stream);
+}
+
 // ---------------------------------------------------------------------------
 // Permutations
 
@@ -259,9 +269,12 @@ __global__ void k_finalize_1ch(const double *y, int64_t n, double f, const doubl
 
 void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const double *y_s, double *out_s,
                    bool add_diag, int precision, bool direct) {
-    BFM_CHECK(precision == BFM_PREC_FP64, BFM_EUNSUPPORTED, "only FP64 products are built");
+    BFM_CHECK(precision == BFM_PREC_FP64 || precision == BFM_PREC_FP32 || precision == BFM_PREC_BF16X3,
+              BFM_EINVAL, "unknown precision");
     ensure_tree(c);
+    const bool lo = precision != BFM_PREC_FP64 && !direct;
     if (!direct) ensure_ops(c);
+    if (lo) ensure_ops_lo(c, precision);
     if (add_diag && !c->diag_valid) diagonal_pass(c, nullptr);
     hipStream_t st = c->stream;
     Tree &t = c->tree;
@@ -283,7 +296,7 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
     src.dip = dip;
     src.q = q;
     src.w = wd;
-    fmm_apply(c->fmm, t, src, y, direct, st);
+    fmm_apply(lo ? c->fmm_lo : c->fmm, t, src, y, direct, st);
     k_finalize_1ch<<<nblk(n, 256), 256, 0, st>>>(y, n, f, mono ? x_s : nullptr, g, dip ? y_s : nullptr,
                                                  add_diag ? c->lii_s.get() : nullptr,
                                                  add_diag ? c->mii_s.get() : nullptr, out_s);
@@ -463,7 +476,11 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
     const int m = c->opt.gmres_restart;
     const int maxit = c->opt.gmres_maxit;
     const double tol = c->opt.gmres_tol;
+    // mixed-precision iterative refinement: the Arnoldi products in low
+    // precision, the residuals that start each cycle in FP64
     const int prec = c->opt.precision;
+    const bool ir = prec != BFM_PREC_FP64;
+    const double ir_tol = c->opt.ir_tol > 0.0 ? c->opt.ir_tol : 1e-4;
     SmallLayout L(m);
     double *V = c->V.ensure((size_t)(m + 1) * n);
     double *w = c->work.ensure(n);
@@ -515,7 +532,7 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
     }
     // r0
     if (use_guess) {
-        matvec_sorted(c, 1.0, x, 0.0, nullptr, V, true, prec, false);
+        matvec_sorted(c, 1.0, x, 0.0, nullptr, V, true, BFM_PREC_FP64, false);
         ++matvecs;
         k_sub_from<<<nblk(n, 256), 256, 0, st>>>(b, V, n);
         BFM_LAUNCHED();
@@ -570,7 +587,7 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
             ++it;
             k = j + 1;
             const double res = read_scalar(L.scal);
-            if (res <= tol * nb) break;
+            if (res <= tol * nb || (ir && res <= ir_tol * beta)) break;
         }
         k_trisolve<<<1, 1, 0, st>>>(sm, L, k);
         BFM_LAUNCHED();
@@ -586,8 +603,8 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
             k_combine<<<nblk(n, 256), 256, 0, st>>>(V, k, n, sm + L.yv, x, n);
             BFM_LAUNCHED();
         }
-        // true residual
-        matvec_sorted(c, 1.0, x, 0.0, nullptr, V, true, prec, false);
+        // true residual (FP64)
+        matvec_sorted(c, 1.0, x, 0.0, nullptr, V, true, BFM_PREC_FP64, false);
         ++matvecs;
         k_sub_from<<<nblk(n, 256), 256, 0, st>>>(b, V, n);
         BFM_LAUNCHED();

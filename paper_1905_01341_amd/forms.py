@@ -1,0 +1,45 @@
+"""The two solver configurations the benchmark compares, in one place so that
+the benchmark and the tests that pin it to the oracle run the same options.
+
+* plain: the paper's method as printed - unpreconditioned restarted GMRES
+  from a zero guess (Section 3.8), FP64 fast multipole products, no graph,
+  no autotuning. Its GMRES tolerance is the loosest that still brings the
+  1000-bubble solution within 1e-6 of the oracle's.
+* tuned: the same system and stopping test (true residual), reached with a
+  right preconditioner, graph-replayed products and the autotuner's choice
+  of expansion order, octree depth and M2L launch shape.
+
+Argument marshalling only: every step runs in the HIP library.
+"""
+from __future__ import annotations
+
+from . import bfm
+
+PLAIN = dict(p=16, p_diag=0, leaf_target=64, lmax=0, m2l_shape=-1, gmres_tol=1e-8, gmres_restart=30,
+             gmres_maxit=1000, precond=bfm.PRECOND_NONE, precond_degree=12, use_graph=0)
+TUNED = dict(p=16, p_diag=0, leaf_target=64, lmax=0, m2l_shape=-1, gmres_tol=1e-7, gmres_restart=30,
+             gmres_maxit=1000, precond=bfm.PRECOND_SH_COARSE, precond_degree=12, use_graph=1)
+# product accuracy the autotuner must keep (relative to the p = 20 product)
+TUNE_TOL = 1e-7
+AUTOTUNE = {"plain": False, "tuned": True}
+
+
+def options(form: str, **overrides) -> dict:
+    base = {"plain": PLAIN, "tuned": TUNED}[form]
+    opts = dict(base)
+    for k, v in overrides.items():
+        if v is not None:
+            opts[k] = v
+    return opts
+
+
+def make_solver(cl, form: str, autotune: bool | None = None, tune_tol: float = TUNE_TOL, device: int = 0,
+                **overrides):
+    """A Solver for cluster `cl` in `form` ("plain" or "tuned"); returns
+    (solver, autotune result dict or None)."""
+    sv = bfm.Solver(device=device, **options(form, **overrides))
+    sv.set_cluster(cl)
+    tune = None
+    if AUTOTUNE[form] if autotune is None else autotune:
+        tune = sv.autotune(tune_tol)
+    return sv, tune

@@ -1,8 +1,17 @@
-"""The 1000-bubble cluster (642,000 nodes) at full size, in the bench's
-configurations, against the oracle's solution (tests/golden/c1000_q_oracle.npy:
-float32 copy of the FP64 direct-sum solve at relative residual 6.5e-12,
-written by tests/golden/make_c1000_oracle.py). The bound is the metric's,
-relative L2 error <= 1e-6, for the plain FP64 form and the tuned form."""
+"""The 1000-bubble cluster (642,000 nodes) at full size, in exactly the
+configurations the benchmark times (paper_1905_01341_amd/forms.py: the same
+options, autotuning, graph replay and device-resident steps), against the
+oracle's solution (tests/golden/c1000_q_oracle.npy: float32 copy of the FP64
+direct-sum solve at relative residual 6.5e-12, written by
+tests/golden/make_c1000_oracle.py). The bound is the metric's: relative L2
+error <= 1e-6 (Section 3.11 measures the method against direct summation),
+plus an entry-wise bound (largest error against the largest entry). The
+entry-wise error of both forms is the same, 1.03e-5 (2.97e-7 and 4.33e-7 in
+the 2-norm), so it comes from the parts they share (expansion truncation of
+the products at p = 16 and of the diagonal/right-hand-side pass at
+p_diag = 20), not from the solver; the entry-wise bound is 3e-5. A lost
+near-field piece or a wrong diagonal entry shows as an error of order one
+at its receivers."""
 import json
 import os
 
@@ -10,6 +19,7 @@ import numpy as np
 import pytest
 
 from paper_1905_01341_amd import bfm
+from paper_1905_01341_amd import forms
 from paper_1905_01341_amd import workload as wl
 
 pytestmark = pytest.mark.gpu
@@ -25,17 +35,45 @@ def golden():
     return cl, phi, q
 
 
+def bench_steps(sv, cl, phi, steps=2):
+    """The benchmark's step: positions copied on the device (geometry and
+    octree rebuilt), then the device solve; returns the last q and info."""
+    import torch
+    dev = torch.device("cuda:0")
+    xyz_t = torch.tensor(cl.xyz, dtype=torch.float64, device=dev).contiguous()
+    phi_t = torch.tensor(phi, dtype=torch.float64, device=dev).contiguous()
+    q_t = torch.zeros_like(phi_t)
+    info = None
+    for _ in range(steps):
+        bfm._check(sv.lib.bfm_set_positions_dev(sv.h, bfm.ctypes.c_void_p(xyz_t.data_ptr())))
+        info = sv.solve_dev(phi_t, q_t)
+    torch.cuda.synchronize()
+    return q_t.cpu().numpy(), info
+
+
 @pytest.mark.parametrize("form", ["plain", "tuned"])
-def test_c1000_solution_within_1e6_of_oracle(golden, form):
+def test_c1000_bench_configuration_within_1e6_of_oracle(golden, form):
     cl, phi, q_ref = golden
-    kw = dict(p=16, gmres_tol=1e-8, gmres_maxit=1000)
+    sv, tune = forms.make_solver(cl, form)
+    q, info = bench_steps(sv, cl, phi)
+    err = float(np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref))
+    emax = float(np.max(np.abs(q - q_ref)) / np.max(np.abs(q_ref)))
+    worst = np.argsort(-np.abs(q - q_ref))[:5]
+    print(f"{form}: {info['iterations']} iterations, {info['matvecs']} products, autotune {tune}, "
+          f"error vs oracle {err:.3e} (max {emax:.3e}); largest errors at nodes {worst.tolist()} "
+          f"(|dq| {np.abs(q - q_ref)[worst].tolist()}, |q| {np.abs(q_ref)[worst].tolist()})")
+    assert info["converged"] and err <= 1e-6 and emax <= 3e-5, (err, emax, info)
     if form == "tuned":
-        kw.update(precond=bfm.PRECOND_SH_COARSE, precond_degree=12)
-    sv = bfm.Solver(**kw)
-    sv.set_cluster(cl)
-    if form == "tuned":
-        sv.autotune(1e-7)
+        assert sv.opt.use_graph == 1 and tune is not None
+
+
+def test_c1000_eager_tuned_matches_graph_tuned(golden):
+    """Graph replay changes nothing but launch overhead: the eager solve with
+    the autotuner's choice meets the same bound."""
+    cl, phi, q_ref = golden
+    sv, tune = forms.make_solver(cl, "tuned", use_graph=0)
     q, info = sv.solve(phi)
     err = float(np.linalg.norm(q - q_ref) / np.linalg.norm(q_ref))
-    print(f"{form}: {info['iterations']} iterations, error vs oracle {err:.3e}")
-    assert info["converged"] and err <= 1e-6
+    emax = float(np.max(np.abs(q - q_ref)) / np.max(np.abs(q_ref)))
+    print(f"eager tuned: {info['iterations']} iterations, error vs oracle {err:.3e} (max {emax:.3e})")
+    assert info["converged"] and err <= 1e-6 and emax <= 3e-5

@@ -1,7 +1,12 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle.
 
 Tolerances. The all-pairs GPU product and the geometry agree with the
-oracle to round-off. Fast multipole products carry the truncation error of
+oracle to round-off. Every comparison is made twice: as a relative 2-norm
+over the compared entries (rel) and entry by entry, as the largest error
+against the largest reference entry (maxrel), so that a few bad receivers
+(one lost or doubled near-field piece) cannot hide in a norm. The
+100-bubble products are checked on a fixed seeded subset of 10,000
+receivers against the oracle's exact sums over all 256,200 sources. Fast multipole products carry the truncation error of
 expansions of degree < p with one-box separation (geometric in p, cf. the
 paper's Table 1): single layer (L) within 1e-6 from p = 16, double layer
 (M, dipoles, one order slower) within 1e-6 from p = 20, which is why the
@@ -21,6 +26,12 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def maxrel(a, b):
+    """Largest entry-wise error against the largest reference entry."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 @pytest.fixture(scope="module")
 def single():
     cl, phi = wl.make("single")
@@ -32,8 +43,19 @@ def single():
 def c100():
     cl, phi = wl.make("c100")
     s, n, _ = oracle.geometry(cl.xyz, cl.tri)
-    rows = wl.subset_rows(cl.nv, 1500, 77)
+    rows = wl.subset_rows(cl.nv, 10000, 77)
     return cl, phi, s, n, rows
+
+
+@pytest.fixture(scope="module")
+def c100_ref(c100):
+    """The oracle's single- and double-layer products with phi and its
+    diagonal/right-hand-side sums at the 10,000 sampled receivers."""
+    cl, phi, s, n, rows = c100
+    ref_l = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, phi, rows=rows)
+    ref_m = oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi, rows=rows)
+    d = oracle.sums(cl.xyz, s, n, phi, rows=rows)
+    return ref_l, ref_m, d
 
 
 def _solver(cl, **kw):
@@ -70,46 +92,50 @@ def test_fmm_product_single_bubble(single, p):
     x = np.cos(np.arange(cl.nv) * 0.37)
     ref_l = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, x)
     ref_m = oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi)
-    e_l = rel(sv.matvec(1.0, x), ref_l)
-    e_m = rel(sv.matvec(0.0, None, 1.0, phi), ref_m)
-    print(f"p={p} L={e_l:.3e} M={e_m:.3e}")
+    yl, ym = sv.matvec(1.0, x), sv.matvec(0.0, None, 1.0, phi)
+    e_l, e_m = rel(yl, ref_l), rel(ym, ref_m)
+    x_l, x_m = maxrel(yl, ref_l), maxrel(ym, ref_m)
+    print(f"p={p} L={e_l:.3e} M={e_m:.3e} max L={x_l:.3e} M={x_m:.3e}")
     tol = {8: 2e-4, 12: 1e-5, 16: 1e-6, 20: 2e-7}[p]
     assert e_l < tol and e_m < 2 * tol, (p, e_l, e_m)
+    assert x_l < 5 * tol and x_m < 10 * tol, (p, x_l, x_m)
 
 
-@pytest.mark.parametrize("p", [12, 16, 20])
-def test_fmm_product_cluster_sampled(c100, p):
-    """256,200 sources; the oracle sums 1,500 sampled receivers exactly."""
+@pytest.mark.parametrize("p", [8, 12, 16, 20])
+def test_fmm_product_cluster_sampled(c100, c100_ref, p):
+    """256,200 sources; the oracle sums 10,000 sampled receivers exactly."""
     cl, phi, s, n, rows = c100
+    ref_l, ref_m, _ = c100_ref
     sv = _solver(cl, p=p)
     yl = sv.matvec(1.0, phi)
     ym = sv.matvec(0.0, None, 1.0, phi)
-    ref_l = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, phi, rows=rows)
-    ref_m = oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi, rows=rows)
     e_l, e_m = rel(yl[rows], ref_l), rel(ym[rows], ref_m)
-    print(f"p={p} L={e_l:.3e} M={e_m:.3e}")
-    tol_l = {12: 2e-6, 16: 2e-7, 20: 1e-7}[p]
-    tol_m = {12: 5e-5, 16: 3e-6, 20: 1e-6}[p]
+    x_l, x_m = maxrel(yl[rows], ref_l), maxrel(ym[rows], ref_m)
+    print(f"p={p} L={e_l:.3e} M={e_m:.3e} max L={x_l:.3e} M={x_m:.3e}")
+    tol_l = {8: 5e-5, 12: 2e-6, 16: 2e-7, 20: 1e-7}[p]
+    tol_m = {8: 1e-3, 12: 5e-5, 16: 3e-6, 20: 1e-6}[p]
     assert e_l < tol_l and e_m < tol_m, (p, e_l, e_m)
+    assert x_l < 5 * tol_l and x_m < 5 * tol_m, (p, x_l, x_m)
 
 
 @pytest.mark.parametrize("lmax", [3, 4])
-def test_fmm_product_coarse_and_fine_leaves(c100, lmax):
+def test_fmm_product_coarse_and_fine_leaves(c100, c100_ref, lmax):
     """Fixed octree depths on the 100-bubble cluster: at lmax = 3 every
     leaf's near-field source list runs to thousands of points and is split
     into pieces whose sums are added atomically; at lmax = 4 the lists are
     shorter. Both must give the same product to the expansion accuracy."""
     cl, phi, s, n, rows = c100
+    ref_l, ref_m, _ = c100_ref
     sv = _solver(cl, p=16, lmax=lmax)
     st = sv.tree_stats()
     assert st["lmax"] == lmax
     yl = sv.matvec(1.0, phi)
     ym = sv.matvec(0.0, None, 1.0, phi)
-    ref_l = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, phi, rows=rows)
-    ref_m = oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi, rows=rows)
     e_l, e_m = rel(yl[rows], ref_l), rel(ym[rows], ref_m)
-    print(f"lmax={lmax} near pairs={st['near_pairs']} L={e_l:.3e} M={e_m:.3e}")
+    x_l, x_m = maxrel(yl[rows], ref_l), maxrel(ym[rows], ref_m)
+    print(f"lmax={lmax} near pairs={st['near_pairs']} L={e_l:.3e} M={e_m:.3e} max L={x_l:.3e} M={x_m:.3e}")
     assert e_l < 2e-7 and e_m < 3e-6, (lmax, e_l, e_m)
+    assert x_l < 1e-6 and x_m < 1.5e-5, (lmax, x_l, x_m)
 
 
 def test_fmm_product_tiny_leaves(single):
@@ -122,10 +148,12 @@ def test_fmm_product_tiny_leaves(single):
     cl, phi, s, n = single
     sv = _solver(cl, p=16, lmax=5)
     x = np.cos(np.arange(cl.nv) * 0.37)
-    e_l = rel(sv.matvec(1.0, x), oracle.offdiag_mvp(cl.xyz, s, n, 1.0, x))
-    e_m = rel(sv.matvec(0.0, None, 1.0, phi), oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi))
-    print(f"L={e_l:.3e} M={e_m:.3e}")
+    ref_l, ref_m = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, x), oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi)
+    yl, ym = sv.matvec(1.0, x), sv.matvec(0.0, None, 1.0, phi)
+    e_l, e_m, x_l, x_m = rel(yl, ref_l), rel(ym, ref_m), maxrel(yl, ref_l), maxrel(ym, ref_m)
+    print(f"L={e_l:.3e} M={e_m:.3e} max L={x_l:.3e} M={x_m:.3e}")
     assert e_l < 3e-6 and e_m < 2e-5, (e_l, e_m)
+    assert x_l < 1.5e-5 and x_m < 1e-4, (x_l, x_m)
 
 
 def test_fmm_product_deep_octree(single):
@@ -137,13 +165,15 @@ def test_fmm_product_deep_octree(single):
     sv = _solver(cl, p=16, lmax=11)
     assert sv.tree_stats()["lmax"] == 11
     x = np.cos(np.arange(cl.nv) * 0.37)
-    e_l = rel(sv.matvec(1.0, x), oracle.offdiag_mvp(cl.xyz, s, n, 1.0, x))
-    e_m = rel(sv.matvec(0.0, None, 1.0, phi), oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi))
-    print(f"L={e_l:.3e} M={e_m:.3e}")
+    ref_l, ref_m = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, x), oracle.offdiag_mvp(cl.xyz, s, n, 0.0, None, 1.0, phi)
+    yl, ym = sv.matvec(1.0, x), sv.matvec(0.0, None, 1.0, phi)
+    e_l, e_m, x_l, x_m = rel(yl, ref_l), rel(ym, ref_m), maxrel(yl, ref_l), maxrel(ym, ref_m)
+    print(f"L={e_l:.3e} M={e_m:.3e} max L={x_l:.3e} M={x_m:.3e}")
     assert e_l < 3e-6 and e_m < 2e-5, (e_l, e_m)
+    assert x_l < 1.5e-5 and x_m < 1e-4, (x_l, x_m)
 
 
-def test_diagonals_and_rhs(single, c100):
+def test_diagonals_and_rhs(single, c100, c100_ref):
     """M_ii = -1/2 - sum M_ij is a small difference of O(1/2) terms, so its
     error is judged against 1/2 (the size of the sum it comes from)."""
     cl, phi, s, n = single
@@ -153,17 +183,21 @@ def test_diagonals_and_rhs(single, c100):
     M_ref, L_ref, _ = oracle.diagonals(cl.xyz, s, n, sm=d)
     b_ref = oracle.rhs(phi, d["B"])
     em, el, eb = np.abs(Mii - M_ref).max() / 0.5, rel(Lii, L_ref), rel(b, b_ref)
-    print(f"single: M={em:.3e} L={el:.3e} b={eb:.3e}")
+    xl, xb = maxrel(Lii, L_ref), maxrel(b, b_ref)
+    print(f"single: M={em:.3e} L={el:.3e} b={eb:.3e} max L={xl:.3e} b={xb:.3e}")
     assert em < 1e-6 and el < 1e-6 and eb < 1e-6, (em, el, eb)
+    assert xl < 5e-6 and xb < 5e-6, (xl, xb)
     cl, phi, s, n, rows = c100
+    d = c100_ref[2]
     sv = _solver(cl, p=16)
     Mii, Lii, b = sv.diagonals(phi)
-    d = oracle.sums(cl.xyz, s, n, phi, rows=rows)
     M_ref, L_ref, _ = oracle.diagonals(cl.xyz, s, n, rows=rows, sm=d)
     b_ref = oracle.rhs(phi, d["B"], rows=rows)
     em, el, eb = np.abs(Mii[rows] - M_ref).max() / 0.5, rel(Lii[rows], L_ref), rel(b[rows], b_ref)
-    print(f"c100: M={em:.3e} L={el:.3e} b={eb:.3e}")
+    xl, xb = maxrel(Lii[rows], L_ref), maxrel(b[rows], b_ref)
+    print(f"c100: M={em:.3e} L={el:.3e} b={eb:.3e} max L={xl:.3e} b={xb:.3e}")
     assert em < 1e-6 and el < 1e-6 and eb < 1e-6, (em, el, eb)
+    assert xl < 5e-6 and xb < 5e-6, (xl, xb)
 
 
 def test_solve_single_bubble_matches_oracle(single):
@@ -173,20 +207,22 @@ def test_solve_single_bubble_matches_oracle(single):
     q, info = sv.solve(phi)
     assert info["converged"]
     assert rel(q, q_ref) < 1e-6, (rel(q, q_ref), info)
+    assert maxrel(q, q_ref) < 5e-6, maxrel(q, q_ref)
 
 
-def test_solve_cluster_residual_against_oracle_rows(c100):
+def test_solve_cluster_residual_against_oracle_rows(c100, c100_ref):
     """The GPU solution satisfies the oracle's system at sampled rows."""
     cl, phi, s, n, rows = c100
     sv = _solver(cl, p=16, gmres_tol=1e-10)
     q, info = sv.solve(phi)
     assert info["converged"], info
-    d = oracle.sums(cl.xyz, s, n, phi, rows=rows)
+    d = c100_ref[2]
     _, Lii, _ = oracle.diagonals(cl.xyz, s, n, rows=rows, sm=d)
     b = oracle.rhs(phi, d["B"], rows=rows)
     Lq = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, q, rows=rows) + Lii * q[rows]
-    print(f"residual of the GPU solution in the oracle system: {rel(Lq, b):.3e} ({info})")
-    assert rel(Lq, b) < 1e-6, rel(Lq, b)
+    print(f"residual of the GPU solution in the oracle system: {rel(Lq, b):.3e} "
+          f"max {maxrel(Lq, b):.3e} ({info})")
+    assert rel(Lq, b) < 1e-6 and maxrel(Lq, b) < 5e-6, (rel(Lq, b), maxrel(Lq, b))
 
 
 def test_warm_start_and_tetrahedron_edge_cases():
@@ -201,7 +237,7 @@ def test_warm_start_and_tetrahedron_edge_cases():
     sv = _solver(wl.Cluster(v, f, np.array([0, 4]), np.array([0, 4]), np.zeros((1, 3)), np.ones(1), dirs),
                  p=16, gmres_tol=1e-13)
     q, info = sv.solve(phi)
-    assert rel(q, q_ref) < 1e-6, rel(q, q_ref)
+    assert rel(q, q_ref) < 1e-6 and maxrel(q, q_ref) < 5e-6, (rel(q, q_ref), maxrel(q, q_ref))
     # warm start from the answer converges immediately
     q2, info2 = sv.solve(phi, q0=q)
     assert info2["iterations"] <= 1 and rel(q2, q) < 1e-12
@@ -229,23 +265,25 @@ def test_sh_preconditioned_solve_single_bubble(single):
     q1, i1 = pre.solve(phi)
     print(f"plain {i0['iterations']} it, preconditioned {i1['iterations']} it")
     assert i1["converged"] and rel(q1, q_ref) < 1e-6, (rel(q1, q_ref), i1)
+    assert maxrel(q1, q_ref) < 5e-6, maxrel(q1, q_ref)
     assert i1["iterations"] < i0["iterations"] / 2
 
 
-def test_sh_preconditioned_solve_cluster(c100):
+def test_sh_preconditioned_solve_cluster(c100, c100_ref):
     cl, phi, s, n, rows = c100
     sv = _solver(cl, p=16, gmres_tol=1e-10, precond=bfm.PRECOND_SH, precond_degree=12)
     q, info = sv.solve(phi)
     assert info["converged"], info
-    d = oracle.sums(cl.xyz, s, n, phi, rows=rows)
+    d = c100_ref[2]
     _, Lii, _ = oracle.diagonals(cl.xyz, s, n, rows=rows, sm=d)
     b = oracle.rhs(phi, d["B"], rows=rows)
     Lq = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, q, rows=rows) + Lii * q[rows]
-    print(f"preconditioned: {info['iterations']} it, oracle-system residual {rel(Lq, b):.3e}")
-    assert rel(Lq, b) < 1e-6 and info["iterations"] < 60
+    print(f"preconditioned: {info['iterations']} it, oracle-system residual {rel(Lq, b):.3e} "
+          f"max {maxrel(Lq, b):.3e}")
+    assert rel(Lq, b) < 1e-6 and maxrel(Lq, b) < 5e-6 and info["iterations"] < 60
 
 
-def test_two_level_preconditioned_solve_cluster(c100):
+def test_two_level_preconditioned_solve_cluster(c100, c100_ref):
     """The coarse correction (one unknown per bubble) leaves the solution
     unchanged and needs fewer iterations than the block step alone."""
     cl, phi, s, n, rows = c100
@@ -254,13 +292,13 @@ def test_two_level_preconditioned_solve_cluster(c100):
     two = _solver(cl, p=16, gmres_tol=1e-10, precond=bfm.PRECOND_SH_COARSE, precond_degree=12)
     q2, i2 = two.solve(phi)
     assert i2["converged"], i2
-    d = oracle.sums(cl.xyz, s, n, phi, rows=rows)
+    d = c100_ref[2]
     _, Lii, _ = oracle.diagonals(cl.xyz, s, n, rows=rows, sm=d)
     b = oracle.rhs(phi, d["B"], rows=rows)
     Lq = oracle.offdiag_mvp(cl.xyz, s, n, 1.0, q2, rows=rows) + Lii * q2[rows]
     print(f"block {i1['iterations']} it, two-level {i2['iterations']} it, "
-          f"oracle-system residual {rel(Lq, b):.3e}")
-    assert rel(Lq, b) < 1e-6
+          f"oracle-system residual {rel(Lq, b):.3e} max {maxrel(Lq, b):.3e}")
+    assert rel(Lq, b) < 1e-6 and maxrel(Lq, b) < 5e-6
     assert rel(q2, q1) < 1e-8
     assert i2["iterations"] < i1["iterations"]
     # the second solve on the same mesh reuses nothing stale: positions moved
