@@ -246,6 +246,24 @@ int bfm_solve_dev(bfm_ctx *ctx, const double *phi_dev, double *q_dev, int use_gu
 int bfm_direct_dev(int64_t n, const double *xyz, const double *s, const double *nrm, double f, const double *x,
                    double g, const double *y, int64_t nr, const int64_t *rows, double *out, void *stream);
 
+/*
+ * bfm_direct_dev without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, kernels and result
+ * as bfm_direct_dev, with the partial sums in a fixed device array of the
+ * library (4,194,304 doubles = 32 MiB per device, held until the process
+ * ends). It calls no hipMalloc, hipFree or allocating library routine.
+ * Limit: (source splits x nr) <= 4,194,304, which holds for every nr up to
+ * 4,063,232 receivers; a larger nr returns BFM_EINVAL before any launch.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (other streams or threads) race and must be ordered by the
+ * caller. Nothing in the array needs clearing (each call writes every
+ * partial it reads). Errors as bfm_direct_dev.
+ */
+int bfm_direct_dev_noalloc(int64_t n, const double *xyz, const double *s, const double *nrm, double f,
+                           const double *x, double g, const double *y, int64_t nr, const int64_t *rows, double *out,
+                           void *stream);
+
 /* Autotuning of the fast multipole product for the current mesh (not in the
  * paper, which tunes the octree depth by hand, Section 4): p = the smallest
  * of 8, 12, 16, 20 whose product with a fixed pseudo-random vector is within

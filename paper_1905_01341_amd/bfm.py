@@ -169,6 +169,7 @@ def load(path: str = LIB_PATH):
         "bfm_profile_read": ([P, I, P, P, P], I),
         "bfm_autotune": ([P, D, ctypes.POINTER(TuneResult)], I),
         "bfm_direct_dev": ([I64, P, P, P, D, P, D, P, I64, P, P, P], I),
+        "bfm_direct_dev_noalloc": ([I64, P, P, P, D, P, D, P, I64, P, P, P], I),
         "bfm_default_physics": ([ctypes.POINTER(Physics)], I),
         "bfm_set_physics": ([P, ctypes.POINTER(Physics)], I),
         "bfm_state_set": ([P, P, P, D], I),
@@ -252,10 +253,12 @@ def _dptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def direct_dev(xyz_t, s_t, nrm_t, f=1.0, x_t=None, g=0.0, y_t=None, rows_t=None, out_t=None, nr=None):
+def direct_dev(xyz_t, s_t, nrm_t, f=1.0, x_t=None, g=0.0, y_t=None, rows_t=None, out_t=None, nr=None,
+               noalloc=False):
     """All-pairs off-diagonal product on torch device tensors (FP64, caller
     order; rows_t int64 or None); returns out_t. Runs on torch's current
-    stream."""
+    stream. noalloc: the allocation-free entry point (out_t must be given
+    for a call that allocates nothing on the Python side either)."""
     import torch
     n = xyz_t.shape[0]
     if nr is None:
@@ -263,8 +266,9 @@ def direct_dev(xyz_t, s_t, nrm_t, f=1.0, x_t=None, g=0.0, y_t=None, rows_t=None,
     if out_t is None:
         out_t = torch.empty(nr, dtype=torch.float64, device=xyz_t.device)
     st = torch.cuda.current_stream(xyz_t.device).cuda_stream
-    _check(load().bfm_direct_dev(n, _dptr(xyz_t), _dptr(s_t), _dptr(nrm_t), float(f), _dptr(x_t), float(g),
-                                 _dptr(y_t), nr, _dptr(rows_t), _dptr(out_t), ctypes.c_void_p(st)))
+    fn = load().bfm_direct_dev_noalloc if noalloc else load().bfm_direct_dev
+    _check(fn(n, _dptr(xyz_t), _dptr(s_t), _dptr(nrm_t), float(f), _dptr(x_t), float(g), _dptr(y_t), nr,
+              _dptr(rows_t), _dptr(out_t), ctypes.c_void_p(st)))
     return out_t
 
 

@@ -512,6 +512,26 @@ int bfm_direct_dev(int64_t n, const double *xyz, const double *s, const double *
     });
 }
 
+int bfm_direct_dev_noalloc(int64_t n, const double *xyz, const double *s, const double *nrm, double f,
+                           const double *x, double g, const double *y, int64_t nr, const int64_t *rows, double *out,
+                           void *stream) {
+    return guarded([&] {
+        DirectArgs a;
+        a.n = n;
+        a.xyz = xyz;
+        a.s = s;
+        a.nrm = nrm;
+        a.f = f;
+        a.x = x;
+        a.g = g;
+        a.y = y;
+        a.nr = nr;
+        a.rows = rows;
+        a.out = out;
+        direct_product_noalloc(a, (hipStream_t)stream);
+    });
+}
+
 int bfm_tree_stats(bfm_ctx *c, int n, int64_t *stats) {
     return guarded([&] {
         BFM_CHECK(c && stats, BFM_EINVAL, "null argument");

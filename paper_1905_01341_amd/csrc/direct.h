@@ -21,4 +21,10 @@ struct DirectArgs {
 // Allocates its partial-sum buffer on the stream (stream-ordered).
 void direct_product(const DirectArgs &a, hipStream_t st);
 
+// Doubles in the allocation-free entry point's device scratch array.
+constexpr int64_t kDirectScratch = (int64_t)1 << 22;
+
+// The same product with the partial sums in that array: no allocation.
+void direct_product_noalloc(const DirectArgs &a, hipStream_t st);
+
 }  // namespace bfm

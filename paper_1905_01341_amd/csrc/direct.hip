@@ -7,10 +7,12 @@
 // The sources are split into nsplit ranges so that a small receiver set
 // still fills the device: one wave per (64 receivers, source range) writes a
 // partial sum per receiver, and a second kernel adds each receiver's partials
-// in a fixed order (bitwise reproducible). bfm_direct_dev allocates the
-// partial sums per call, stream-ordered.
+// in a fixed order (bitwise reproducible). The partial sums are the scratch
+// buffer: bfm_direct_dev allocates it per call, stream-ordered;
+// bfm_direct_dev_noalloc uses the file-scope device array `scratch` below.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "direct.h"
 
@@ -18,6 +20,11 @@ namespace bfm {
 
 constexpr int kDirThreads = 64;
 constexpr double kInv4PiD = 0.079577471545947667884441881686257;
+
+// Scratch of the allocation-free entry point (kDirectScratch doubles,
+// 32 MiB): every device the library runs on holds its own copy until the
+// process ends, and every call on that device shares it.
+__device__ __align__(256) double scratch[kDirectScratch];
 
 __device__ inline double rsqrt_nr(double x) {
     const double y = __builtin_amdgcn_rsq(x);
@@ -116,6 +123,37 @@ void direct_product(const DirectArgs &a, hipStream_t st) {
         throw;
     }
     BFM_HIP(hipFreeAsync(part, st));
+}
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current (in host code the array's name is a
+// host-side stand-in, not a device address).
+static double *scratch_ptr() {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptrs[kMaxDevices] = {nullptr};
+    int dev = 0;
+    BFM_HIP(hipGetDevice(&dev));
+    BFM_CHECK(dev >= 0 && dev < kMaxDevices, BFM_EINVAL, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void *p = nullptr;
+        BFM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        BFM_CHECK(p != nullptr, BFM_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        ptrs[dev] = static_cast<double *>(p);
+    }
+    return ptrs[dev];
+}
+
+void direct_product_noalloc(const DirectArgs &a, hipStream_t st) {
+    direct_check(a);
+    double *part = scratch_ptr();
+    if (a.nr == 0) return;
+    const int nsplit = direct_splits(a.n, a.nr);
+    BFM_CHECK((int64_t)nsplit * a.nr <= kDirectScratch, BFM_EINVAL,
+              "nr = " + std::to_string(a.nr) + " needs " + std::to_string((int64_t)nsplit * a.nr) +
+                  " scratch doubles; the allocation-free entry point holds " + std::to_string(kDirectScratch));
+    direct_launch(a, part, nsplit, st);
 }
 
 }  // namespace bfm
