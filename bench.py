@@ -188,6 +188,19 @@ def learned_study(a):
     print(json.dumps(out), flush=True)
 
 
+def form_text(opt):
+    """One line describing the tuned form's arithmetic and solver."""
+    if opt.precision == 0:
+        arith = "FP64 FMM products"
+    else:
+        kind = {1: "FP32", 2: "split-BF16 (hi + lo, three products, FP32 accumulation)"}[opt.precision]
+        arith = (f"mixed-precision iterative refinement: GMRES Arnoldi products with {kind} "
+                 f"translations and an FP32 near field at order {opt.p_lo}, FP64 residuals at order {opt.p}, "
+                 f"cycles ending at a {opt.ir_tol:g} residual reduction")
+    return (f"tuned: {arith}; GMRES right-preconditioned by a two-level method (per-bubble spherical "
+            f"harmonics to degree {opt.precond_degree}, then a coarse correction with one unknown per bubble)")
+
+
 def cpu_model():
     """CPU model name of the host (from /proc/cpuinfo), or None."""
     try:
@@ -200,48 +213,62 @@ def cpu_model():
     return None
 
 
-# Kernel classes whose launches are one kernel (so a roofline line can name
-# it): class -> (kernel-name function, bound, traffic-table class).
-def p2p_kernel_name(p, shape, group):
-    return {"": "bfm::k_p2p_sym", "diag_": "bfm::k_p2p_diag<true>"}.get(group)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (packed; plain FP32 issues at half of it)
 
 
-def roofline_entry(cls, prof, prof_steps, stats, opt_p, p_diag, nv, workload):
+def p2p_kernel_name(group):
+    return {"": "bfm::k_p2p_sym", "diag_": "bfm::k_p2p_diag<true>", "lo_": "bfm::k_p2p_sym32"}.get(group)
+
+
+def roofline_entry(cls, prof, prof_steps, stats, opt, p_diag, nv, workload):
     """Roofline line of one kernel class: algorithmic flops of its launches
-    over their summed event time against the FP64 peak (the FP64 MFMA peak for
-    M2L, the FP64 vector peak for the near field, which is bound by plain ALU
-    work), with the HBM traffic measured for that kernel where the traffic
-    table holds a line for it on the current sources."""
+    over their summed event time against the peak of the arithmetic the
+    kernel runs on (FP64 MFMA for the FP64 M2L, BF16 MFMA / 3 for the
+    split-BF16 M2L, which issues three BF16 products per FP32-equivalent
+    product; FP64 or FP32 vector peak for the near field, which is bound by
+    plain ALU work), with the HBM traffic measured for that kernel where the
+    traffic table holds a line for it on the current sources."""
     d = prof[cls]
     if d["launches"] == 0 or d["ms"] <= 0:
         return None
-    group = "diag_" if cls.startswith("diag_") else ""
+    group = next((g for g in ("diag_", "lo_") if cls.startswith(g)), "")
     kind = cls[len(group):]
-    p = p_diag if group else opt_p
+    p = {"": opt.p, "diag_": p_diag, "lo_": opt.p_lo or opt.p}[group]
+    lo_prec = opt.precision if group == "lo_" else 0
     if kind == "m2l":
-        shape = stats["diag_m2l_shape" if group else "m2l_shape"]
-        kname = m2l_kernel_name(p, shape) if shape >= 0 else None
-        bound, tcls = "mfma", "m2l"
         pp = p * p
-        nch = 5 if group else 1
+        if lo_prec == 2:
+            rows = pp if pp <= 144 else (128 if pp == 256 else 80)
+            kname = f"bfm::k_translate_bf3<{pp}, {rows}, 0, true> + bfm::k_m2l_reduce<{pp}>"
+            peak, unit_bytes = PEAK_BF16_TFLOPS / 3.0, 4.0
+        elif lo_prec == 1:
+            kname, peak, unit_bytes = None, PEAK_FP32_TFLOPS, 4.0
+        else:
+            shape = stats["diag_m2l_shape" if group else "m2l_shape"]
+            kname = m2l_kernel_name(p, shape) if shape >= 0 else None
+            peak, unit_bytes = PEAK_FP64_TFLOPS, 8.0
+        bound, tcls = "mfma", "m2l"
+        nch = 5 if group == "diag_" else 1
         # every operator read once, every box's multipole read and local
         # expansion written once
-        alg_bytes = 8.0 * (316 * pp * pp + 2 * stats["boxes"] * pp * nch)
+        alg_bytes = unit_bytes * (316 * pp * pp + 2 * stats["boxes"] * pp * nch)
     elif kind == "p2p":
-        kname = p2p_kernel_name(p, None, group)
+        kname = p2p_kernel_name(group)
         bound, tcls = "alu", "p2p"
+        peak = PEAK_FP32_TFLOPS if group == "lo_" else PEAK_FP64_TFLOPS
         # positions (24 B) and strengths of every point read once, its sums
         # written once (one channel: 8 + 8 B; five packed channels: a 128-byte
         # record read, five sums written)
-        alg_bytes = (40.0 if not group else 168.0) * nv
+        alg_bytes = (168.0 if group == "diag_" else 40.0) * nv
     else:
         return None
     avg_ms = d["ms"] / d["launches"]
     ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
     tr = measured_traffic(tcls, kname, workload, stats["lmax"], p) if kname else None
     return {"kernel": kname or cls, "class": cls, "bound": bound,
-            "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+            "achieved": round(ach, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4),
             "traffic": None if tr is None else round(tr[0]),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
             "traffic_GBps": None if tr is None else round(tr[0] / (avg_ms * 1e-3) / 1e9, 1),
@@ -340,8 +367,8 @@ def main():
 
     roof, roof_p2p = None, None
     if prof:
-        named = [c for c in ("m2l", "p2p", "diag_m2l", "diag_p2p") if prof[c]["launches"] > 0]
-        entries = {c: roofline_entry(c, prof, prof_steps, stats, sv.opt.p, p_diag, cl.nv, a.workload)
+        named = [c for c in ("m2l", "p2p", "diag_m2l", "diag_p2p", "lo_m2l", "lo_p2p") if prof[c]["launches"] > 0]
+        entries = {c: roofline_entry(c, prof, prof_steps, stats, sv.opt, p_diag, cl.nv, a.workload)
                    for c in named}
         entries = {c: e for c, e in entries.items() if e is not None}
         if entries:
@@ -349,18 +376,19 @@ def main():
             # group (GMRES products and the diagonal/right-hand-side pass)
             dom = max(entries, key=lambda c: prof[c]["ms"])
             roof = entries[dom]
-            roof_p2p = entries.get("p2p")
+            # the near field of the GMRES products (the low-precision one when
+            # the solve refines)
+            roof_p2p = entries.get("lo_p2p") or entries.get("p2p")
     out = {
         "metric": METRIC, "value": round(ms / 1e3, 6), "unit": "s/step", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": {0: "f64", 1: "f64+f32", 2: "f64+bf16x3"}[sv.opt.precision] if tuned else "f64",
         "data": "synthetic",
         "config": {
             "workload": (f"{a.workload}: {cl.nb} icosphere bubbles, {cl.nv} nodes, {cl.nt} triangles"),
-            "form": ("tuned: FP64 FMM products, GMRES right-preconditioned by a two-level method "
-                     f"(per-bubble spherical harmonics to degree {sv.opt.precond_degree}, then a coarse "
-                     "correction with one unknown per bubble)") if tuned else "plain FP64",
-            "p": sv.opt.p, "p_diag": p_diag,
+            "form": form_text(sv.opt) if tuned else "plain FP64",
+            "p": sv.opt.p, "p_lo": sv.opt.p_lo if sv.opt.precision else None, "p_diag": p_diag,
             "graph": graph_on, "autotune": tune,
             "lmax": stats["lmax"], "leaves": stats["leaves"], "near_pairs": stats["near_pairs"],
             "m2l_pairs": stats["m2l_pairs"], "gmres_tol": sv.opt.gmres_tol, "gmres_restart": sv.opt.gmres_restart,

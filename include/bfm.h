@@ -267,17 +267,22 @@ int bfm_direct_dev_noalloc(int64_t n, const double *xyz, const double *s, const 
 /* Autotuning of the fast multipole product for the current mesh (not in the
  * paper, which tunes the octree depth by hand, Section 4): p = the smallest
  * of 8, 12, 16, 20 whose product with a fixed pseudo-random vector is within
- * mvp_tol (relative 2-norm) of the p = 20 product (p = 20 if none); then
- * the octree depth (the depth chosen from leaf_target and one level either
- * side) that minimises one diagonal/right-hand-side pass plus ten products,
- * and the M2L launch shape with the fastest product at that depth, timed
- * with HIP events after a warm-up. The choice is stored in the handle's
- * options (p, lmax, m2l_shape; p_diag is left as set). out may be NULL. */
+ * mvp_tol (relative 2-norm) of the p = 20 product (p = 20 if none); with
+ * iterative refinement (precision FP32 or BF16X3) also p_lo = the smallest
+ * of 8, 12, 16 whose low-precision product is within ir_tol of that
+ * reference; then the octree depth (the depth chosen from leaf_target and
+ * one level either side) that minimises one diagonal/right-hand-side pass
+ * plus the products of a typical solve (ten FP64 products, or two FP64 and
+ * eight low-precision ones), and the M2L launch shape with the fastest
+ * product at that depth, timed with HIP events after a warm-up. The choice
+ * is stored in the handle's options (p, p_lo, lmax, m2l_shape; p_diag is
+ * left as set). out may be NULL. */
 typedef struct bfm_tune_result {
     int p, lmax, m2l_shape; /* chosen */
     int candidates;         /* configurations timed */
-    double mvp_ms;          /* time of one product with the chosen configuration */
+    double mvp_ms;          /* time of one FP64 product with the chosen configuration */
     double p_err;           /* relative difference of the chosen p's product from p = 20 */
+    int p_lo;               /* chosen order of the low-precision products (0 without refinement) */
 } bfm_tune_result;
 int bfm_autotune(bfm_ctx *ctx, double mvp_tol, bfm_tune_result *out);
 

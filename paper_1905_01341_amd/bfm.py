@@ -63,6 +63,7 @@ class TuneResult(ctypes.Structure):
         ("candidates", ctypes.c_int),
         ("mvp_ms", ctypes.c_double),
         ("p_err", ctypes.c_double),
+        ("p_lo", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -395,6 +396,8 @@ class Solver:
         r = TuneResult()
         _check(self.lib.bfm_autotune(self.h, float(mvp_tol), ctypes.byref(r)))
         self.opt.p, self.opt.lmax, self.opt.m2l_shape = r.p, r.lmax, r.m2l_shape
+        if r.p_lo:
+            self.opt.p_lo = r.p_lo
         return r.as_dict()
 
     def tree_stats(self):

@@ -36,6 +36,7 @@ struct FmmWork {
     DevBuf<double> mexp, lexp;      // [nbox][nch][P]
     DevBuf<double> ops_m2m, ops_l2l, ops_m2l;  // operators, column-major per op: [op][k][row]
     DevBuf<float> mexp32, lexp32;   // low-precision expansions [nbox][P]
+    DevBuf<float> part32;           // low-precision M2L results per task [ntasks][P]
     DevBuf<float> opf_m2m, opf_l2l, opf_m2l;   // FP32 operators, same layout
     // split-BF16 operators: [0] = hi, [1] = lo, [op][chunk][row][32] (K padded to 32)
     DevBuf<uint16_t> opb_m2m[2], opb_l2l[2], opb_m2l[2];

@@ -217,7 +217,9 @@ __device__ inline void split8(const float *v, bool ok, bf16x8 &hi, bf16x8 &lo) {
     }
 }
 
-template <int PP, int ROWS, int KIND>
+// STORE: the result of every task is stored (out = [task][PP]) for a
+// reduction per target box instead of added atomically into the target.
+template <int PP, int ROWS, int KIND, bool STORE>
 __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const int *tile_off, int ntiles,
                                                                  const int *op_off, const int *tsrc,
                                                                  const int *tdst, int nch, int swap,
@@ -350,11 +352,41 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const
             const int col = colbase + cb * 16 + 4 * kq + r;
             if (col >= ncols) continue;
             const int task = t0 + col / nch, ch = col % nch;
-            const int db = swap ? tsrc[task] : tdst[task];
-            float *dcol = out + ((int64_t)db * nch + ch) * PP + slab * ROWS + rl;
+            if (STORE) {
+                float *dcol = out + ((int64_t)(t0 * nch + col)) * PP + slab * ROWS + rl;
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) unsafeAtomicAdd(dcol + rb * 16, acc[cb][rb][r]);
+                for (int rb = 0; rb < RB; ++rb) dcol[rb * 16] = acc[cb][rb][r];
+            } else {
+                const int db = swap ? tsrc[task] : tdst[task];
+                float *dcol = out + ((int64_t)db * nch + ch) * PP + slab * ROWS + rl;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) unsafeAtomicAdd(dcol + rb * 16, acc[cb][rb][r]);
+            }
         }
+}
+
+// L[b] = sum of the stored M2L results of target box b's tasks, in the order
+// the tasks were generated (fixed, so the sum is reproducible). One wave per
+// target box, four coefficients per lane per pass.
+template <int PP>
+__global__ void __launch_bounds__(64) k_m2l_reduce(const int *dst_off, const int *pos_of, int64_t box0,
+                                                   const float *part, float *L) {
+    static_assert(PP % 4 == 0, "whole float4 groups");
+    const int64_t k = blockIdx.x;
+    const int a = dst_off[k], e = dst_off[k + 1];
+    if (a == e) return;  // no far-field sources at this box's level (L stays zero)
+    float *lb = L + (box0 + k) * PP;
+    for (int c = threadIdx.x * 4; c < PP; c += 256) {
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = a; i < e; ++i) {
+            const float4 v = *reinterpret_cast<const float4 *>(part + (int64_t)pos_of[i] * PP + c);
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+        *reinterpret_cast<float4 *>(lb + c) = s;
+    }
 }
 
 template <class R>
@@ -542,23 +574,41 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
     prof_end(w, pi, st, 2.0 * (double)PP * PP * (double)tl.ntasks * nch);
 }
 
+// Row slab of the split-BF16 translation: every row up to p = 12 (the input
+// columns are then loaded and split once per tile), 128 rows at p = 16, 80
+// at p = 20 (accumulator registers and LDS bound the slab).
+constexpr int bf_rows(int PP) { return PP <= 144 ? PP : (PP == 256 ? 128 : 80); }
+
 // Split-BF16 translation of FP32 expansions (one launch shape: 128-column
-// tiles, row slabs of mid_rows).
+// tiles, row slabs of bf_rows).
 template <int P_>
 static void translate_bf3(FmmWork &w, int cls, TaskList &tl, bool swap, const uint16_t *Thi, const uint16_t *Tlo,
                           const float *in, float *out, hipStream_t st) {
     constexpr int PP = P_ * P_;
-    constexpr int RM = mid_rows(PP);
+    constexpr int RM = bf_rows(PP);
     prepare_tiles(tl, 1, kBfTile, st);
     const int nt = tl.ntiles_for(1, kBfTile);
     if (cls == KC_M2L) w.m2l_shape_used = 1;
     if (nt <= 0) return;
     const int pi = prof_begin(w, cls, st);
-    auto kern = (cls == KC_M2L) ? k_translate_bf3<PP, RM, 0> : k_translate_bf3<PP, RM, 1>;
-    kern<<<(unsigned)(nt * (PP / RM)), 64 * kBfWaves, 0, st>>>(
-        tl.nops, tl.tile_for(1, kBfTile), nt, tl.op_off.get(), tl.src.get(), tl.dst.get(), 1, swap ? 1 : 0,
-        reinterpret_cast<const uint4 *>(Thi), reinterpret_cast<const uint4 *>(Tlo), in, out);
-    BFM_LAUNCHED();
+    if (cls == KC_M2L) {
+        // the tasks' results are stored, then summed per target box (no atomics)
+        float *part = w.part32.ensure((size_t)tl.ntasks * PP);
+        k_translate_bf3<PP, RM, 0, true><<<(unsigned)(nt * (PP / RM)), 64 * kBfWaves, 0, st>>>(
+            tl.nops, tl.tile_for(1, kBfTile), nt, tl.op_off.get(), tl.src.get(), tl.dst.get(), 1, swap ? 1 : 0,
+            reinterpret_cast<const uint4 *>(Thi), reinterpret_cast<const uint4 *>(Tlo), in, part);
+        BFM_LAUNCHED();
+        if (tl.dst_nbox > 0) {
+            k_m2l_reduce<PP><<<(unsigned)tl.dst_nbox, 64, 0, st>>>(tl.dst_off.get(), tl.pos_of.get(), tl.dst_box0,
+                                                                  part, out);
+            BFM_LAUNCHED();
+        }
+    } else {
+        k_translate_bf3<PP, RM, 1, false><<<(unsigned)(nt * (PP / RM)), 64 * kBfWaves, 0, st>>>(
+            tl.nops, tl.tile_for(1, kBfTile), nt, tl.op_off.get(), tl.src.get(), tl.dst.get(), 1, swap ? 1 : 0,
+            reinterpret_cast<const uint4 *>(Thi), reinterpret_cast<const uint4 *>(Tlo), in, out);
+        BFM_LAUNCHED();
+    }
     prof_end(w, pi, st, 2.0 * (double)PP * PP * (double)tl.ntasks);
 }
 

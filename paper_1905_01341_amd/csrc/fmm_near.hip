@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_sym(const int4 *__restrict_
 // Symmetric form of one channel of monopoles (k_p2p_sym's items and pair
 // order): each unordered pair once, its two terms added to both points.
 template <int R>
-__device__ inline void p2p_sym32_block(const float4 *src, float *sacc, const float *xi, const float *yi,
+__device__ inline void p2p_sym32_block(const float4 *src, double *sacc, const float *xi, const float *yi,
                                        const float *zi, const float *qi, double *accd, int b, bool diag) {
     const int lane = threadIdx.x;
     float acc[R];
@@ -500,7 +500,9 @@ __device__ inline void p2p_sym32_block(const float4 *src, float *sacc, const flo
             acc[k] = fmaf(a.w, inv, acc[k]);
             if (!diag || k < b) c = fmaf(qi[k], inv, c);
         }
-        if (!diag || b > 0) atomicAdd(sacc + s, c);
+        // source-side sums in FP64 slots (ds_add_f64; the FP32 LDS add
+        // stalled this loop on LDS waits)
+        if (!diag || b > 0) atomicAdd(sacc + s, (double)c);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) accd[k] += (double)acc[k];
@@ -511,7 +513,7 @@ __device__ inline void p2p_sym32_item(int leaf, int r0, int r1, int s0, int s1, 
                                       const int *__restrict__ near_cnt, double ox, double oy, double oz,
                                       const double *__restrict__ px, const double *__restrict__ py,
                                       const double *__restrict__ pz, const double *__restrict__ q,
-                                      double *__restrict__ y, float4 *src, float *sacc) {
+                                      double *__restrict__ y, float4 *src, double *sacc) {
     const int lane = threadIdx.x;
     float xi[R], yi[R], zi[R], qi[R];
     double accd[R];
@@ -533,12 +535,12 @@ __device__ inline void p2p_sym32_item(int leaf, int r0, int r1, int s0, int s1, 
             const bool ok = base + lane < s1;
             src[lane] = ok ? make_float4((float)(px[j] - ox), (float)(py[j] - oy), (float)(pz[j] - oz), (float)q[j])
                            : make_float4(-1e30f, 0.f, 0.f, 0.f);
-            sacc[lane] = 0.f;
+            sacc[lane] = 0.0;
             __syncthreads();
             const int b = base / kP2PThreads;
             p2p_sym32_block<R>(src, sacc, xi, yi, zi, qi, accd, b, true);
             __syncthreads();
-            if (ok && b > 0) unsafeAtomicAdd(y + j, (double)sacc[lane]);
+            if (ok && b > 0) unsafeAtomicAdd(y + j, sacc[lane]);
         }
     } else {
         const int2 *rng = near_rng + 27 * (int64_t)leaf;
@@ -555,11 +557,11 @@ __device__ inline void p2p_sym32_item(int leaf, int r0, int r1, int s0, int s1, 
             const bool ok = p < s1 && j >= 0;
             src[lane] = ok ? make_float4((float)(px[j] - ox), (float)(py[j] - oy), (float)(pz[j] - oz), (float)q[j])
                            : make_float4(-1e30f, 0.f, 0.f, 0.f);
-            sacc[lane] = 0.f;
+            sacc[lane] = 0.0;
             __syncthreads();
             p2p_sym32_block<R>(src, sacc, xi, yi, zi, qi, accd, 0, false);
             __syncthreads();
-            if (ok) unsafeAtomicAdd(y + j, (double)sacc[lane]);
+            if (ok) unsafeAtomicAdd(y + j, sacc[lane]);
         }
     }
 #pragma unroll
@@ -579,7 +581,7 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_sym32(const int4 *__restric
                                                            const double *__restrict__ pz,
                                                            const double *__restrict__ q, double *__restrict__ y) {
     __shared__ float4 src[kP2PThreads];
-    __shared__ float sacc[kP2PThreads];
+    __shared__ double sacc[kP2PThreads];
     const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
     const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
     const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];

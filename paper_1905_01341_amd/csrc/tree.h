@@ -37,6 +37,13 @@ struct TaskList {
     DevBuf<int> tile_off[16];
     int ntiles[16] = {0};
     bool tiles_ready[16] = {false};
+    // M2L lists only: the tasks of each target box, for a reduction of
+    // per-task results: target box dst_box0 + k owns the tasks at grouped
+    // positions pos_of[dst_off[k]] .. pos_of[dst_off[k + 1] - 1] (in the
+    // order they were generated)
+    DevBuf<int> pos_of;   // [ntasks] generation index -> grouped position
+    DevBuf<int> dst_off;  // [dst_nbox + 1]
+    int64_t dst_box0 = 0, dst_nbox = 0;
     static int slot(int nch, int width) { return nch * 2 + (width == 128 ? 1 : 0); }
     int ntiles_for(int nch, int width) const { return ntiles[slot(nch, width)]; }
     const int *tile_for(int nch, int width) const { return tile_off[slot(nch, width)].get(); }

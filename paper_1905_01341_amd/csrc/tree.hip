@@ -661,6 +661,19 @@ __global__ void k_op_keys(const int *top, int64_t n, uint64_t *key, int *idx) {
     idx[i] = (int)i;
 }
 
+__global__ void k_invert(const int *order, int64_t n, int *pos) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r < n) pos[order[r]] = (int)r;
+}
+
+// dst_off[k] = first generated M2L task of target box b0 + k (the tasks come
+// out ordered by box, then by parent-neighbour slot: 27 slots per box)
+__global__ void k_dst_off(const int *offs, int64_t nb, int64_t total, int *dst_off) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < nb) dst_off[k] = offs[27 * k];
+    if (k == nb) dst_off[k] = (int)total;
+}
+
 __global__ void k_op_gather(const int *order, const int *src, const int *dst, int64_t n, int *osrc, int *odst) {
     int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -673,7 +686,7 @@ __global__ void k_op_gather(const int *order, const int *src, const int *dst, in
 // per-operator scan for a few operators, a stable radix sort on the operator
 // index for many.
 static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst, const int *top,
-                        int64_t n, Tree::Scratch &scr, hipStream_t st) {
+                        int64_t n, Tree::Scratch &scr, hipStream_t st, bool keep_positions = false) {
     tl.nops = nops;
     tl.ntasks = n;
     tl.op_off_h.assign(nops + 1, 0);
@@ -713,7 +726,13 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
         radix_sort(k0, i0, k1, i1, n, bits, scr, st);
         k_op_gather<<<nblk(n, 256), 256, 0, st>>>(i0, tsrc, tdst, n, tl.src.get(), tl.dst.get());
         BFM_LAUNCHED();
+        if (keep_positions) {
+            tl.pos_of.ensure(n);
+            k_invert<<<nblk(n, 256), 256, 0, st>>>(i0, n, tl.pos_of.get());
+            BFM_LAUNCHED();
+        }
     }
+    BFM_CHECK(!keep_positions || n == 0 || nops > 16, BFM_EINVAL, "task positions kept only for the sorted grouping");
 }
 
 // Workgroup-tile prefix of one (channel count, tile width) shape:
@@ -1013,7 +1032,12 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                        t.box_parent.get(), t.nbr.get(), count.get(),
                                                        offs.get(), ts.get(), td.get(), to.get());
         BFM_LAUNCHED();
-        group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, scr, st);
+        group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, scr, st, true);
+        t.m2l.dst_box0 = b0;
+        t.m2l.dst_nbox = nb;
+        t.m2l.dst_off.ensure(nb + 1);
+        k_dst_off<<<nblk(nb + 1, 256), 256, 0, st>>>(offs.get(), nb, total, t.m2l.dst_off.get());
+        BFM_LAUNCHED();
     }
     // M2M / L2L lists: child levels 3..lmax (index l)
     // task lists are reused between builds (their buffers only grow)

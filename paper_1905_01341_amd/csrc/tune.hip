@@ -102,14 +102,14 @@ static double diff_host(const double *a, const double *b, int64_t n, hipStream_t
     return std::sqrt(s);
 }
 
-static double time_mvp(bfm_ctx *c, const double *x, double *y, int reps) {
+static double time_mvp(bfm_ctx *c, const double *x, double *y, int reps, int prec = BFM_PREC_FP64) {
     hipStream_t st = c->stream;
-    matvec_sorted(c, 1.0, x, 0.0, nullptr, y, false, BFM_PREC_FP64, false);  // warm-up
+    matvec_sorted(c, 1.0, x, 0.0, nullptr, y, false, prec, false);  // warm-up
     hipEvent_t a, b;
     BFM_HIP(hipEventCreate(&a));
     BFM_HIP(hipEventCreate(&b));
     BFM_HIP(hipEventRecord(a, st));
-    for (int r = 0; r < reps; ++r) matvec_sorted(c, 1.0, x, 0.0, nullptr, y, false, BFM_PREC_FP64, false);
+    for (int r = 0; r < reps; ++r) matvec_sorted(c, 1.0, x, 0.0, nullptr, y, false, prec, false);
     BFM_HIP(hipEventRecord(b, st));
     BFM_HIP(hipEventSynchronize(b));
     float ms = 0.f;
@@ -158,9 +158,29 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
         }
         c->opt.p = best_p;
         ensure_ops(c);
+        // 1b. iterative refinement (low-precision inner products): p_lo = the
+        // smallest of 8, 12, 16 whose low-precision product is within the
+        // refinement step's tolerance ir_tol of the p = 20 FP64 product
+        const bool ir = saved.precision != BFM_PREC_FP64;
+        const double ir_tol = saved.ir_tol > 0.0 ? saved.ir_tol : 1e-4;
+        int best_plo = 0;
+        if (ir) {
+            best_plo = 16;
+            for (int plo : {8, 12, 16}) {
+                c->opt.p_lo = plo;
+                matvec_sorted(c, 1.0, x.get(), 0.0, nullptr, y.get(), false, saved.precision, false);
+                const double err = diff_host(y.get(), yref.get(), n, st) / nref;
+                if (err <= ir_tol) {
+                    best_plo = plo;
+                    break;
+                }
+            }
+            c->opt.p_lo = best_plo;
+        }
         // 2. octree depth and M2L launch shape: the depth minimises one
-        // diagonal/right-hand-side pass plus ten products (a typical solve);
-        // the shape, the product at that depth
+        // diagonal/right-hand-side pass plus the products of a typical solve
+        // (ten FP64 products; with refinement two FP64 and eight
+        // low-precision ones); the shape, the FP64 product at that depth
         DevBuf<double> xo;
         xo.ensure(n);
         BFM_HIP(hipMemcpyAsync(xo.get(), xh.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
@@ -200,7 +220,9 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
                     lvl_s = shape;
                 }
             }
-            const double cost = dms + 10.0 * lvl_ms;
+            c->opt.m2l_shape = lvl_s;
+            const double lo_ms = ir ? time_mvp(c, x.get(), y.get(), 5, saved.precision) : 0.0;
+            const double cost = ir ? dms + 2.0 * lvl_ms + 8.0 * lo_ms : dms + 10.0 * lvl_ms;
             if (cost < best_cost) {
                 best_cost = cost;
                 best_ms = lvl_ms;
@@ -212,11 +234,13 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
         c->opt.p = best_p;
         c->opt.lmax = best_l;
         c->opt.m2l_shape = best_s;
+        if (ir) c->opt.p_lo = best_plo;
         c->tree_valid = false;
         c->diag_valid = false;
         graph_invalidate(c);
         if (out) {
             out->p = best_p;
+            out->p_lo = ir ? best_plo : 0;
             out->lmax = best_l;
             out->m2l_shape = best_s;
             out->candidates = cand;
