@@ -118,6 +118,13 @@ typedef struct bfm_options {
                           product) from one captured HIP graph per octree */
     int m2l_shape;     /* M2L launch shape: -1 = by size, 0 = wide tiles, 1 = row slabs,
                           2 = narrow slabs (set by bfm_autotune) */
+    int m2l_orders;    /* 0: every M2L translation at the product's order p (Section 3.9);
+                          1: offsets d = (c_target - c_source)/h (box sides) translated at
+                          orders falling with |d|: p for |d|^2 <= 5, 4 ceil(p/5) for 6..10,
+                          4 ceil(3p/20) from 11 on (20/16/12 at p = 20, 16/16/12 at
+                          p = 16) - the truncation error of a translation falls
+                          geometrically with |d|, so distant offsets reach the nearest
+                          ones' accuracy at lower order. Applies to every product */
 } bfm_options;
 
 typedef struct bfm_solve_info {
@@ -137,7 +144,7 @@ typedef struct bfm_ctx bfm_ctx;
 /* Fill *opt with defaults: p = 16, p_diag = 0, lmax = 0, leaf_target = 64,
  * FP64 (p_lo = 0, ir_tol = 0), tol 1e-10, restart 30, maxit 300, device 0,
  * stream NULL, no preconditioner (precond_degree 12), no graph, M2L shape
- * by size. */
+ * by size, every M2L at order p (m2l_orders = 0). */
 int bfm_default_options(bfm_options *opt);
 
 /* Create a handle on opt->device. The handle owns every device buffer

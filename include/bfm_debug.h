@@ -19,8 +19,9 @@ extern "C" {
  * kind 1: local-to-local, parent -> child octant `index` (0..7)
  * kind 2: multipole-to-local, offset operator `index` (0..315)
  * Octant o: child box integer coordinates have low bits (o>>2 & 1, o>>1 & 1,
- * o & 1). Offset operator k: the k-th (dx, dy, dz) in lexicographic order of
- * [-3,3]^3 excluding [-1,1]^3, meaning c_target - c_source = d * h.
+ * o & 1). Offset operator k: the k-th (dx, dy, dz) of [-3,3]^3 excluding
+ * [-1,1]^3, ordered by dx^2 + dy^2 + dz^2 and then lexicographically,
+ * meaning c_target - c_source = d * h.
  * out: host, p^2 * p^2 doubles, row-major (out[row * p^2 + col]).
  * d_out (may be NULL): for kind 2 receives the offset (dx, dy, dz).
  * Returns 0, or -1 (BFM_EINVAL) on a bad p, kind or index.

@@ -102,6 +102,7 @@ class Options(ctypes.Structure):
         ("precond_degree", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("m2l_shape", ctypes.c_int),
+        ("m2l_orders", ctypes.c_int),
     ]
 
 

@@ -59,6 +59,7 @@ static void check_options(const bfm_options &o) {
               BFM_EINVAL, "unknown precond");
     BFM_CHECK(o.precond_degree >= 1 && o.precond_degree <= 40, BFM_EINVAL, "precond_degree must be in [1, 40]");
     BFM_CHECK(o.m2l_shape >= -1 && o.m2l_shape <= 2, BFM_EINVAL, "m2l_shape must be -1, 0, 1 or 2");
+    BFM_CHECK(o.m2l_orders == 0 || o.m2l_orders == 1, BFM_EINVAL, "m2l_orders must be 0 or 1");
 }
 
 struct DeviceScope {
@@ -256,7 +257,8 @@ int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
         check_options(*opt);
         BFM_CHECK(opt->device == c->device, BFM_EINVAL, "cannot change the device of a handle");
         const bool tree_change = opt->lmax != c->opt.lmax || opt->leaf_target != c->opt.leaf_target;
-        const bool p_change = opt->p != c->opt.p || opt->p_diag != c->opt.p_diag;
+        const bool p_change =
+            opt->p != c->opt.p || opt->p_diag != c->opt.p_diag || opt->m2l_orders != c->opt.m2l_orders;
         // (p_lo and precision take effect at the next low-precision product)
         void *keep_stream = c->opt.stream;
         c->opt = *opt;

@@ -43,6 +43,7 @@ struct FmmWork {
     int ops_p = 0;
     int ops_prec = -1;
     int m2l_shape = -1;    // M2L launch shape (-1: chosen by size)
+    int m2l_orders = 0;    // 1: distant offset classes translated at reduced orders (ops.h)
     int m2l_shape_used = -1;  // shape of the last M2L launch (-1: none yet)
     // optional second stream for the near field (default priority): the
     // P2P runs there beside the far-field chain and the L2P waits for it

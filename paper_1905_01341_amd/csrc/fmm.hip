@@ -70,12 +70,17 @@ struct Mma<float> {
 constexpr int kTKC = 16;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
-template <int PP, int ROWS, int WAVES, int KIND, class R = double>
-__global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *tile_off, int ntiles,
-                                                          const int *op_off, const int *tsrc,
+// LD: stored order (expansions and operators hold LD = p^2 coefficients);
+// PP <= LD: the order applied (the leading PP x PP block of each operator,
+// degrees below sqrt(PP)) - smaller for distant offsets when the product
+// reduces their order. The launch covers operators op0 .. op0 + nops - 1,
+// whose tiles are g0 .. g0 + ntiles - 1 of the prefix tile_off.
+template <int PP, int ROWS, int WAVES, int KIND, class R = double, int LD = PP>
+__global__ void __launch_bounds__(64 * WAVES) k_translate(int op0, int nops, const int *tile_off, int g0,
+                                                          int ntiles, const int *op_off, const int *tsrc,
                                                           const int *tdst, int nch, int swap,
                                                           const R *T, const R *in, R *out) {
-    static_assert(PP % ROWS == 0 && ROWS % 16 == 0, "row slab");
+    static_assert(PP % ROWS == 0 && ROWS % 16 == 0 && PP <= LD, "row slab");
     constexpr int NSLAB = PP / ROWS;
     __shared__ R As[2][kTKC * ROWS];         // two buffers of [k][row within slab]
     __shared__ R Bs[2][WAVES][kTKC / 4][64];  // two buffers of each wave's input chunk
@@ -85,10 +90,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     const int nblock = gridDim.x, per = nblock / kXcds, rem = nblock % kXcds;
     const int xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
     const int logical = xcd * per + (xcd < rem ? xcd : rem) + idx;
-    const int g = logical / NSLAB, slab = logical % NSLAB;
-    if (g >= ntiles) return;
+    if (logical / NSLAB >= ntiles) return;
+    const int g = g0 + logical / NSLAB, slab = logical % NSLAB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    int lo = 0, hi = nops;
+    int lo = op0, hi = op0 + nops;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (tile_off[mid] <= g)
@@ -106,8 +111,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
     const int bch = bok ? bcolid % nch : 0;
     const int sb = bok ? (swap ? tdst[btask] : tsrc[btask]) : 0;
     // idle columns read box 0's expansion (valid memory) and are never stored
-    const R *bcol = in + ((int64_t)sb * nch + bch) * PP;
-    const R *Top = T + (int64_t)op * PP * PP + slab * ROWS;
+    const R *bcol = in + ((int64_t)sb * nch + bch) * LD;
+    const R *Top = T + (int64_t)op * LD * LD + slab * ROWS;
     const int kq = lane >> 4, rl = lane & 15;
     typename Mma<R>::acc_t acc[ROWS / 16];
 #pragma unroll
@@ -128,7 +133,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = tid + u * NT;
-            if (EXACT || e < kTKC * ROWS) pre[u] = Top[(int64_t)(k0 + e / ROWS) * PP + e % ROWS];
+            if (EXACT || e < kTKC * ROWS) pre[u] = Top[(int64_t)(k0 + e / ROWS) * LD + e % ROWS];
         }
 #pragma unroll
         for (int kk = 0; kk < kTKC / 4; ++kk) bv[kk] = bcol[k0 + 4 * kk + kq];
@@ -186,7 +191,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_translate(int nops, const int *t
         if (col >= ncols) continue;
         const int task = t0 + col / nch, ch = col % nch;
         const int db = swap ? tsrc[task] : tdst[task];
-        R *dcol = out + ((int64_t)db * nch + ch) * PP + slab * ROWS + rl;
+        R *dcol = out + ((int64_t)db * nch + ch) * LD + slab * ROWS + rl;
 #pragma unroll
         for (int rb = 0; rb < ROWS / 16; ++rb) unsafeAtomicAdd(dcol + rb * 16, acc[rb][r]);
     }
@@ -217,16 +222,20 @@ __device__ inline void split8(const float *v, bool ok, bf16x8 &hi, bf16x8 &lo) {
     }
 }
 
-// STORE: the result of every task is stored (out = [task][PP]) for a
+// STORE: the result of every task is stored (out = [task][LD]) for a
 // reduction per target box instead of added atomically into the target.
-template <int PP, int ROWS, int KIND, bool STORE>
-__global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const int *tile_off, int ntiles,
+// LD, PP, op0, g0 as for k_translate (the operators hold LD rows and
+// round-up(LD, 32) / 32 chunks; K beyond PP is masked through the input).
+template <int PP, int ROWS, int KIND, bool STORE, int LD = PP>
+__global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int op0, int nops, const int *tile_off, int g0,
+                                                                 int ntiles,
                                                                  const int *op_off, const int *tsrc,
                                                                  const int *tdst, int nch, int swap,
                                                                  const uint4 *Thi, const uint4 *Tlo,
                                                                  const float *in, float *out) {
-    static_assert(PP % ROWS == 0 && ROWS % 16 == 0, "row slab");
+    static_assert(PP % ROWS == 0 && ROWS % 16 == 0 && PP <= LD, "row slab");
     constexpr int KP = (PP + 31) / 32 * 32, NC = KP / 32, NSLAB = PP / ROWS, RB = ROWS / 16;
+    constexpr int NCF = (LD + 31) / 32;  // chunks of the stored operators
     constexpr int NST = ROWS * 4;  // 16-byte units of one part (hi or lo) of a chunk's slab
     constexpr int NT = 64 * kBfWaves;
     constexpr int PER = (2 * NST + NT - 1) / NT;
@@ -234,10 +243,10 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const
     const int nblock = gridDim.x, per = nblock / kXcds, rem = nblock % kXcds;
     const int xcd = blockIdx.x % kXcds, idx = blockIdx.x / kXcds;
     const int logical = xcd * per + (xcd < rem ? xcd : rem) + idx;
-    const int g = logical / NSLAB, slab = logical % NSLAB;
-    if (g >= ntiles) return;
+    if (logical / NSLAB >= ntiles) return;
+    const int g = g0 + logical / NSLAB, slab = logical % NSLAB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    int lo = 0, hi = nops;
+    int lo = op0, hi = op0 + nops;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (tile_off[mid] <= g)
@@ -259,11 +268,11 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const
         const int task = t0 + (aok[cb] ? col / nch : 0);
         const int ch = aok[cb] ? col % nch : 0;
         const int sb = aok[cb] ? (swap ? tdst[task] : tsrc[task]) : 0;
-        acol[cb] = in + ((int64_t)sb * nch + ch) * PP;
+        acol[cb] = in + ((int64_t)sb * nch + ch) * LD;
     }
     // chunk c of this slab: 16-byte unit u (row u / 4, k group u % 4)
-    const uint4 *sh = Thi + ((int64_t)op * NC * PP + slab * ROWS) * 4;
-    const uint4 *sl = Tlo + ((int64_t)op * NC * PP + slab * ROWS) * 4;
+    const uint4 *sh = Thi + ((int64_t)op * NCF * LD + slab * ROWS) * 4;
+    const uint4 *sl = Tlo + ((int64_t)op * NCF * LD + slab * ROWS) * 4;
     uint4 pre[PER];
     auto fetch_op = [&](int c) {
 #pragma unroll
@@ -271,7 +280,7 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const
             const int e = tid + u * NT;
             if (e < 2 * NST) {
                 const int part = e / NST, v = e - part * NST;
-                pre[u] = (part ? sl : sh)[(int64_t)c * PP * 4 + v];
+                pre[u] = (part ? sl : sh)[(int64_t)c * LD * 4 + v];
             }
         }
     };
@@ -353,12 +362,12 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const
             if (col >= ncols) continue;
             const int task = t0 + col / nch, ch = col % nch;
             if (STORE) {
-                float *dcol = out + ((int64_t)(t0 * nch + col)) * PP + slab * ROWS + rl;
+                float *dcol = out + ((int64_t)(t0 * nch + col)) * LD + slab * ROWS + rl;
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) dcol[rb * 16] = acc[cb][rb][r];
             } else {
                 const int db = swap ? tsrc[task] : tdst[task];
-                float *dcol = out + ((int64_t)db * nch + ch) * PP + slab * ROWS + rl;
+                float *dcol = out + ((int64_t)db * nch + ch) * LD + slab * ROWS + rl;
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) unsafeAtomicAdd(dcol + rb * 16, acc[cb][rb][r]);
             }
@@ -367,19 +376,24 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int nops, const
 
 // L[b] = sum of the stored M2L results of target box b's tasks, in the order
 // the tasks were generated (fixed, so the sum is reproducible). One wave per
-// target box, four coefficients per lane per pass.
-template <int PP>
-__global__ void __launch_bounds__(64) k_m2l_reduce(const int *dst_off, const int *pos_of, int64_t box0,
-                                                   const float *part, float *L) {
-    static_assert(PP % 4 == 0, "whole float4 groups");
+// target box, four coefficients per lane per pass. Tasks at grouped
+// positions >= cut[0] (>= cut[1]) belong to the second (third) distance
+// class and carry only their first pp[1] (pp[2]) coefficients.
+template <int LD>
+__global__ void __launch_bounds__(64) k_m2l_reduce(const int *dst_off, const int *pos_of, int64_t box0, int cut1,
+                                                   int cut2, int pp1, int pp2, const float *part, float *L) {
+    static_assert(LD % 4 == 0, "whole float4 groups");
     const int64_t k = blockIdx.x;
     const int a = dst_off[k], e = dst_off[k + 1];
     if (a == e) return;  // no far-field sources at this box's level (L stays zero)
-    float *lb = L + (box0 + k) * PP;
-    for (int c = threadIdx.x * 4; c < PP; c += 256) {
+    float *lb = L + (box0 + k) * LD;
+    for (int c = threadIdx.x * 4; c < LD; c += 256) {
         float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
         for (int i = a; i < e; ++i) {
-            const float4 v = *reinterpret_cast<const float4 *>(part + (int64_t)pos_of[i] * PP + c);
+            const int pos = pos_of[i];
+            const int pp = pos >= cut2 ? pp2 : (pos >= cut1 ? pp1 : LD);
+            if (c >= pp) continue;
+            const float4 v = *reinterpret_cast<const float4 *>(part + (int64_t)pos * LD + c);
             s.x += v.x;
             s.y += v.y;
             s.z += v.z;
@@ -535,6 +549,38 @@ constexpr int mid_rows(int PP) { return PP == 144 ? 48 : (PP == 400 ? 80 : (PP >
 // (p <= 12), half the rows at p = 16.
 constexpr int wide_rows(int PP) { return PP <= 144 ? PP : (PP == 256 ? 128 : mid_rows(PP)); }
 
+// Tiles of `width` columns (nch per task) before operator o of a task list.
+static int tiles_before(const TaskList &tl, int nch, int width, int o) {
+    int run = 0;
+    for (int q = 0; q < o; ++q) run += ((tl.op_off_h[q + 1] - tl.op_off_h[q]) * nch + width - 1) / width;
+    return run;
+}
+
+// One launch of k_translate over operators op0 .. op0 + nops - 1 (tiles g0 ..
+// g0 + ntiles - 1) at applied order PPo, stored order LD, launch shape
+// `shape` (0: 8 waves, all rows up to p = 12; 1: row slabs; 2: 16-row slabs).
+template <int PPo, int LD, class R>
+static void launch_translate(int shape, bool m2l, int op0, int nops, int g0, int ntiles, const int *to,
+                             const TaskList &tl, int nch, int sw, const R *T, const R *in, R *out, hipStream_t st) {
+    if (ntiles <= 0) return;
+    if (shape == 0) {
+        constexpr int RW = wide_rows(PPo);
+        auto kern = m2l ? k_translate<PPo, RW, 8, 0, R, LD> : k_translate<PPo, RW, 8, 1, R, LD>;
+        kern<<<(unsigned)(ntiles * (PPo / RW)), 512, 0, st>>>(op0, nops, to, g0, ntiles, tl.op_off.get(),
+                                                               tl.src.get(), tl.dst.get(), nch, sw, T, in, out);
+    } else if (shape == 1) {
+        constexpr int RM = mid_rows(PPo);
+        auto kern = m2l ? k_translate<PPo, RM, 4, 0, R, LD> : k_translate<PPo, RM, 4, 1, R, LD>;
+        kern<<<(unsigned)(ntiles * (PPo / RM)), 256, 0, st>>>(op0, nops, to, g0, ntiles, tl.op_off.get(),
+                                                               tl.src.get(), tl.dst.get(), nch, sw, T, in, out);
+    } else {
+        auto kern = m2l ? k_translate<PPo, 16, 4, 0, R, LD> : k_translate<PPo, 16, 4, 1, R, LD>;
+        kern<<<(unsigned)(ntiles * (PPo / 16)), 256, 0, st>>>(op0, nops, to, g0, ntiles, tl.op_off.get(),
+                                                               tl.src.get(), tl.dst.get(), nch, sw, T, in, out);
+    }
+    BFM_LAUNCHED();
+}
+
 template <int P_, class R = double>
 static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, const R *T, const R *in, R *out,
                       hipStream_t st) {
@@ -555,23 +601,35 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
     const int pi = prof_begin(w, cls, st);
     const int *to = tl.tile_for(nch, width);
     const int sw = swap ? 1 : 0;
-    if (shape == 0) {
-        constexpr int RW = wide_rows(PP);
-        auto kern = (cls == KC_M2L) ? k_translate<PP, RW, 8, 0, R> : k_translate<PP, RW, 8, 1, R>;
-        kern<<<(unsigned)(nt * (PP / RW)), 512, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(),
-                                                          tl.dst.get(), nch, sw, T, in, out);
-    } else if (shape == 1) {
-        constexpr int RM = mid_rows(PP);
-        auto kern = (cls == KC_M2L) ? k_translate<PP, RM, 4, 0, R> : k_translate<PP, RM, 4, 1, R>;
-        kern<<<(unsigned)(nt * (PP / RM)), 256, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(),
-                                                          tl.dst.get(), nch, sw, T, in, out);
+    const bool m2l = cls == KC_M2L;
+    double flops = 2.0 * (double)PP * PP * (double)tl.ntasks * nch;
+    if (m2l && w.m2l_orders) {
+        // distance classes of offsets, each at its own order (contiguous
+        // operator ranges)
+        constexpr int P1 = m2l_class_order(P_, 1), P2 = m2l_class_order(P_, 2);
+        int first[kM2LClasses + 1];
+        for (int c = 0; c <= kM2LClasses; ++c) first[c] = m2l_class_first_op(c);
+        flops = 0.0;
+        for (int c = 0; c < kM2LClasses; ++c) {
+            const int g0 = tiles_before(tl, nch, width, first[c]);
+            const int g1 = tiles_before(tl, nch, width, first[c + 1]);
+            const int64_t nk = tl.op_off_h[first[c + 1]] - tl.op_off_h[first[c]];
+            const int po = m2l_class_order(P_, c);
+            flops += 2.0 * (double)po * po * po * po * (double)nk * nch;
+            const int nops = first[c + 1] - first[c];
+            if (c == 0)
+                launch_translate<PP, PP, R>(shape, true, first[c], nops, g0, g1 - g0, to, tl, nch, sw, T, in, out, st);
+            else if (c == 1)
+                launch_translate<P1 * P1, PP, R>(shape, true, first[c], nops, g0, g1 - g0, to, tl, nch, sw, T, in, out,
+                                                 st);
+            else
+                launch_translate<P2 * P2, PP, R>(shape, true, first[c], nops, g0, g1 - g0, to, tl, nch, sw, T, in, out,
+                                                 st);
+        }
     } else {
-        auto kern = (cls == KC_M2L) ? k_translate<PP, 16, 4, 0, R> : k_translate<PP, 16, 4, 1, R>;
-        kern<<<(unsigned)(nt * (PP / 16)), 256, 0, st>>>(tl.nops, to, nt, tl.op_off.get(), tl.src.get(),
-                                                          tl.dst.get(), nch, sw, T, in, out);
+        launch_translate<PP, PP, R>(shape, m2l, 0, tl.nops, 0, nt, to, tl, nch, sw, T, in, out, st);
     }
-    BFM_LAUNCHED();
-    prof_end(w, pi, st, 2.0 * (double)PP * PP * (double)tl.ntasks * nch);
+    prof_end(w, pi, st, flops);
 }
 
 // Row slab of the split-BF16 translation: every row up to p = 12 (the input
@@ -579,37 +637,67 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
 // at p = 20 (accumulator registers and LDS bound the slab).
 constexpr int bf_rows(int PP) { return PP <= 144 ? PP : (PP == 256 ? 128 : 80); }
 
+template <int PPo, int LD, bool STORE>
+static void launch_bf3(int op0, int nops, int g0, int ntiles, const int *to, const TaskList &tl, bool swap,
+                       const uint16_t *Thi, const uint16_t *Tlo, const float *in, float *out, hipStream_t st) {
+    if (ntiles <= 0) return;
+    constexpr int RM = bf_rows(PPo);
+    k_translate_bf3<PPo, RM, STORE ? 0 : 1, STORE, LD><<<(unsigned)(ntiles * (PPo / RM)), 64 * kBfWaves, 0, st>>>(
+        op0, nops, to, g0, ntiles, tl.op_off.get(), tl.src.get(), tl.dst.get(), 1, swap ? 1 : 0,
+        reinterpret_cast<const uint4 *>(Thi), reinterpret_cast<const uint4 *>(Tlo), in, out);
+    BFM_LAUNCHED();
+}
+
 // Split-BF16 translation of FP32 expansions (one launch shape: 128-column
-// tiles, row slabs of bf_rows).
+// tiles, row slabs of bf_rows). M2L results are stored per task, then summed
+// per target box (no atomics).
 template <int P_>
 static void translate_bf3(FmmWork &w, int cls, TaskList &tl, bool swap, const uint16_t *Thi, const uint16_t *Tlo,
                           const float *in, float *out, hipStream_t st) {
     constexpr int PP = P_ * P_;
-    constexpr int RM = bf_rows(PP);
     prepare_tiles(tl, 1, kBfTile, st);
     const int nt = tl.ntiles_for(1, kBfTile);
     if (cls == KC_M2L) w.m2l_shape_used = 1;
     if (nt <= 0) return;
     const int pi = prof_begin(w, cls, st);
+    const int *to = tl.tile_for(1, kBfTile);
+    double flops = 2.0 * (double)PP * PP * (double)tl.ntasks;
     if (cls == KC_M2L) {
-        // the tasks' results are stored, then summed per target box (no atomics)
         float *part = w.part32.ensure((size_t)tl.ntasks * PP);
-        k_translate_bf3<PP, RM, 0, true><<<(unsigned)(nt * (PP / RM)), 64 * kBfWaves, 0, st>>>(
-            tl.nops, tl.tile_for(1, kBfTile), nt, tl.op_off.get(), tl.src.get(), tl.dst.get(), 1, swap ? 1 : 0,
-            reinterpret_cast<const uint4 *>(Thi), reinterpret_cast<const uint4 *>(Tlo), in, part);
-        BFM_LAUNCHED();
+        constexpr int P1 = m2l_class_order(P_, 1), P2 = m2l_class_order(P_, 2);
+        int cut1 = (int)tl.ntasks, cut2 = (int)tl.ntasks;
+        if (w.m2l_orders) {
+            int first[kM2LClasses + 1];
+            for (int c = 0; c <= kM2LClasses; ++c) first[c] = m2l_class_first_op(c);
+            flops = 0.0;
+            for (int c = 0; c < kM2LClasses; ++c) {
+                const int g0 = tiles_before(tl, 1, kBfTile, first[c]);
+                const int g1 = tiles_before(tl, 1, kBfTile, first[c + 1]);
+                const int64_t nk = tl.op_off_h[first[c + 1]] - tl.op_off_h[first[c]];
+                const int po = m2l_class_order(P_, c);
+                flops += 2.0 * (double)po * po * po * po * (double)nk;
+                const int nops = first[c + 1] - first[c];
+                if (c == 0)
+                    launch_bf3<PP, PP, true>(first[c], nops, g0, g1 - g0, to, tl, swap, Thi, Tlo, in, part, st);
+                else if (c == 1)
+                    launch_bf3<P1 * P1, PP, true>(first[c], nops, g0, g1 - g0, to, tl, swap, Thi, Tlo, in, part, st);
+                else
+                    launch_bf3<P2 * P2, PP, true>(first[c], nops, g0, g1 - g0, to, tl, swap, Thi, Tlo, in, part, st);
+            }
+            cut1 = tl.op_off_h[first[1]];
+            cut2 = tl.op_off_h[first[2]];
+        } else {
+            launch_bf3<PP, PP, true>(0, tl.nops, 0, nt, to, tl, swap, Thi, Tlo, in, part, st);
+        }
         if (tl.dst_nbox > 0) {
             k_m2l_reduce<PP><<<(unsigned)tl.dst_nbox, 64, 0, st>>>(tl.dst_off.get(), tl.pos_of.get(), tl.dst_box0,
-                                                                  part, out);
+                                                                  cut1, cut2, P1 * P1, P2 * P2, part, out);
             BFM_LAUNCHED();
         }
     } else {
-        k_translate_bf3<PP, RM, 1, false><<<(unsigned)(nt * (PP / RM)), 64 * kBfWaves, 0, st>>>(
-            tl.nops, tl.tile_for(1, kBfTile), nt, tl.op_off.get(), tl.src.get(), tl.dst.get(), 1, swap ? 1 : 0,
-            reinterpret_cast<const uint4 *>(Thi), reinterpret_cast<const uint4 *>(Tlo), in, out);
-        BFM_LAUNCHED();
+        launch_bf3<PP, PP, false>(0, tl.nops, 0, nt, to, tl, swap, Thi, Tlo, in, out, st);
     }
-    prof_end(w, pi, st, 2.0 * (double)PP * PP * (double)tl.ntasks);
+    prof_end(w, pi, st, flops);
 }
 
 template <int P_, int NCH, bool MONO, bool DIP>

@@ -18,6 +18,8 @@
 // conj(R_j^k(rho)) I_{n+j}^{m+k}(D) (standard solid-harmonic translation
 // theorems for the Laplace kernel; the paper uses such expansions truncated
 // to degrees 0..p_fmm-1, Section 3.9).
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -154,36 +156,64 @@ void build_l2l(int p, int octant, double *T) {
     fill_real(p, G, T);
 }
 
+// Operator order: by squared offset length d^2 (nearest first), then
+// lexicographic in (dx, dy, dz), so that the offsets of one distance class
+// (m2l_class) are one contiguous range of operator indices.
+static const std::vector<std::array<int, 3>> &m2l_offsets() {
+    static const std::vector<std::array<int, 3>> list = [] {
+        std::vector<std::array<int, 3>> v;
+        for (int a = -3; a <= 3; ++a)
+            for (int b = -3; b <= 3; ++b)
+                for (int c = -3; c <= 3; ++c) {
+                    if (a >= -1 && a <= 1 && b >= -1 && b <= 1 && c >= -1 && c <= 1) continue;
+                    v.push_back({a, b, c});
+                }
+        std::stable_sort(v.begin(), v.end(), [](const std::array<int, 3> &x, const std::array<int, 3> &y) {
+            return x[0] * x[0] + x[1] * x[1] + x[2] * x[2] < y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+        });
+        return v;
+    }();
+    return list;
+}
+
 int m2l_op_index(int dx, int dy, int dz) {
     if (dx < -3 || dx > 3 || dy < -3 || dy > 3 || dz < -3 || dz > 3) return -1;
     if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) return -1;
-    int idx = 0;
-    for (int a = -3; a <= 3; ++a)
-        for (int b = -3; b <= 3; ++b)
-            for (int c = -3; c <= 3; ++c) {
-                if (a >= -1 && a <= 1 && b >= -1 && b <= 1 && c >= -1 && c <= 1) continue;
-                if (a == dx && b == dy && c == dz) return idx;
-                ++idx;
-            }
+    const auto &v = m2l_offsets();
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i][0] == dx && v[i][1] == dy && v[i][2] == dz) return (int)i;
     return -1;
 }
 
 void m2l_op_offset(int op, int d[3]) {
-    int idx = 0;
-    for (int a = -3; a <= 3; ++a)
-        for (int b = -3; b <= 3; ++b)
-            for (int c = -3; c <= 3; ++c) {
-                if (a >= -1 && a <= 1 && b >= -1 && b <= 1 && c >= -1 && c <= 1) continue;
-                if (idx == op) {
-                    d[0] = a;
-                    d[1] = b;
-                    d[2] = c;
-                    return;
-                }
-                ++idx;
-            }
-    d[0] = d[1] = d[2] = 0;
+    const auto &v = m2l_offsets();
+    if (op < 0 || op >= (int)v.size()) {
+        d[0] = d[1] = d[2] = 0;
+        return;
+    }
+    d[0] = v[op][0];
+    d[1] = v[op][1];
+    d[2] = v[op][2];
 }
+
+int m2l_class_first_op(int cls) {
+    // classes: d^2 <= 5, 6 <= d^2 <= 10, d^2 >= 11
+    const auto &v = m2l_offsets();
+    const int lim[3] = {0, 6, 11};
+    if (cls >= 3) return (int)v.size();
+    for (size_t i = 0; i < v.size(); ++i) {
+        const int d2 = v[i][0] * v[i][0] + v[i][1] * v[i][1] + v[i][2] * v[i][2];
+        if (d2 >= lim[cls]) return (int)i;
+    }
+    return (int)v.size();
+}
+
+static_assert(m2l_class_order(20, 0) == 20 && m2l_class_order(20, 1) == 16 && m2l_class_order(20, 2) == 12,
+              "class orders at p = 20");
+static_assert(m2l_class_order(16, 1) == 16 && m2l_class_order(16, 2) == 12 && m2l_class_order(12, 1) == 12 &&
+                  m2l_class_order(12, 2) == 8 && m2l_class_order(8, 1) == 8 && m2l_class_order(8, 2) == 8 &&
+                  m2l_class_order(4, 1) == 4 && m2l_class_order(4, 2) == 4,
+              "class orders");
 
 void build_m2l(int p, int op, double *T) {
     int d[3];

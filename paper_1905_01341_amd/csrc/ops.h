@@ -10,9 +10,25 @@ void build_m2m(int p, int octant, double *T);
 void build_l2l(int p, int octant, double *T);
 
 // Multipole-to-local operators: 316 offsets d = (c_target - c_source)/h with
-// components in [-3, 3] and not all in [-1, 1].
+// components in [-3, 3] and not all in [-1, 1], numbered by |d|^2 (nearest
+// first), then lexicographically.
 int m2l_op_index(int dx, int dy, int dz);  // -1 when d is not a far offset
 void m2l_op_offset(int op, int d[3]);
+// Distance classes of the offsets (|d|^2 <= 5, 6..10, >= 11; contiguous
+// operator ranges): first operator of class cls (cls = 3: 316), and the
+// expansion order used for that class when a product of order p reduces the
+// order of distant translations: p, then 4 ceil(p/5) and 4 ceil(3p/20)
+// (about 0.8 p and 0.6 p rounded up to multiples of 4: at p = 20 the orders
+// 20, 16, 12; at p = 16: 16, 16, 12; at p = 12: 12, 12, 8). A translation's
+// truncation error falls like (c/|d|)^p, and the effective ratio measured
+// on the nearest offsets (about 0.47 per degree at |d| = 2) puts the orders
+// that match the nearest class's error at about 0.8 p for |d|^2 = 6 and
+// 0.6 p for |d|^2 = 11.
+int m2l_class_first_op(int cls);
+constexpr int m2l_class_order(int p, int cls) {
+    return cls <= 0 ? p : (cls == 1 ? 4 * ((p + 4) / 5) : 4 * ((3 * p + 19) / 20));
+}
+constexpr int kM2LClasses = 3;
 void build_m2l(int p, int op, double *T);
 
 }  // namespace bfm

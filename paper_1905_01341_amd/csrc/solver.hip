@@ -109,8 +109,10 @@ int diag_order(const bfm_options &o) {
 void ensure_ops(bfm_ctx *c) {
     c->fmm.p = c->opt.p;
     c->fmm.m2l_shape = c->opt.m2l_shape;
+    c->fmm.m2l_orders = c->opt.m2l_orders;
     fmm_prepare_ops(c->fmm, c->opt.p, c->stream);
     c->fmm_diag.p = diag_order(c->opt);
+    c->fmm_diag.m2l_orders = c->opt.m2l_orders;
     fmm_prepare_ops(c->fmm_diag, c->fmm_diag.p, c->stream);
 }
 
@@ -121,6 +123,7 @@ void ensure_ops_lo(bfm_ctx *c, int prec) {
     c->fmm_lo.prec = prec;
     c->fmm_lo.p = p;
     c->fmm_lo.m2l_shape = c->opt.m2l_shape;
+    c->fmm_lo.m2l_orders = c->opt.m2l_orders;
     fmm_prepare_ops(c->fmm_lo, p, c->stream);
 }
 

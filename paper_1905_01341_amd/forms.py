@@ -8,9 +8,10 @@ the benchmark and the tests that pin it to the oracle run the same options.
 * tuned: the same system and stopping test (true FP64 residual), reached by
   mixed-precision iterative refinement (Arnoldi products in split-BF16
   arithmetic at a lower order p_lo, FP64 residuals at p; Section 3.11 weighs
-  single against double precision), a right preconditioner, graph-replayed
-  products and the autotuner's choice of p, p_lo, octree depth and M2L
-  launch shape.
+  single against double precision), M2L translations of distant offsets at
+  reduced orders (the same accuracy as the nearest offsets at order p), a
+  right preconditioner, graph-replayed products and the autotuner's choice of
+  p, p_lo, octree depth and M2L launch shape.
 
 Argument marshalling only: every step runs in the HIP library.
 """
@@ -22,7 +23,7 @@ PLAIN = dict(p=16, p_diag=0, leaf_target=64, lmax=0, m2l_shape=-1, gmres_tol=1e-
              gmres_maxit=1000, precond=bfm.PRECOND_NONE, precond_degree=12, use_graph=0)
 TUNED = dict(p=16, p_diag=0, leaf_target=64, lmax=0, m2l_shape=-1, gmres_tol=1e-7, gmres_restart=30,
              gmres_maxit=1000, precond=bfm.PRECOND_SH_COARSE, precond_degree=12, use_graph=1,
-             precision=bfm.PREC_BF16X3, p_lo=0, ir_tol=1e-4)
+             precision=bfm.PREC_BF16X3, p_lo=0, ir_tol=1e-4, m2l_orders=1)
 # product accuracy the autotuner must keep (relative to the p = 20 product)
 TUNE_TOL = 1e-7
 AUTOTUNE = {"plain": False, "tuned": True}

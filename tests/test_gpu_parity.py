@@ -118,6 +118,49 @@ def test_fmm_product_cluster_sampled(c100, c100_ref, p):
     assert x_l < 5 * tol_l and x_m < 5 * tol_m, (p, x_l, x_m)
 
 
+@pytest.mark.parametrize("p", [12, 16, 20])
+def test_reduced_order_m2l_matches_full_order_bounds(c100, c100_ref, p):
+    """M2L of distant offsets at reduced orders (m2l_orders = 1: |d|^2 <= 5 at
+    p, 6..10 at 4 ceil(p/5), >= 11 at 4 ceil(3p/20)) keeps the full-order
+    product's accuracy: the same 2-norm and entry-wise bounds as
+    test_fmm_product_cluster_sampled."""
+    cl, phi, s, n, rows = c100
+    ref_l, ref_m, _ = c100_ref
+    sv = _solver(cl, p=p, m2l_orders=1)
+    yl = sv.matvec(1.0, phi)
+    ym = sv.matvec(0.0, None, 1.0, phi)
+    e_l, e_m = rel(yl[rows], ref_l), rel(ym[rows], ref_m)
+    x_l, x_m = maxrel(yl[rows], ref_l), maxrel(ym[rows], ref_m)
+    print(f"p={p} reduced orders: L={e_l:.3e} M={e_m:.3e} max L={x_l:.3e} M={x_m:.3e}")
+    tol_l = {12: 2e-6, 16: 2e-7, 20: 1e-7}[p]
+    tol_m = {12: 5e-5, 16: 3e-6, 20: 1e-6}[p]
+    assert e_l < tol_l and e_m < tol_m, (p, e_l, e_m)
+    assert x_l < 5 * tol_l and x_m < 5 * tol_m, (p, x_l, x_m)
+
+
+def test_reduced_order_diagonals_and_rhs(c100, c100_ref):
+    """The five-channel pass (p_diag = 20) with reduced-order distant
+    translations against the full-order pass, both against the oracle:
+    M_ii, L_ii and b within the same 2-norm bounds, and entry-wise within
+    twice the full-order pass's error (L_ii, a small difference of sums of
+    coordinates relative to the cube centre, is the channel most sensitive
+    to the expansion order)."""
+    cl, phi, s, n, rows = c100
+    d = c100_ref[2]
+    M_ref, L_ref, _ = oracle.diagonals(cl.xyz, s, n, rows=rows, sm=d)
+    b_ref = oracle.rhs(phi, d["B"], rows=rows)
+    errs = {}
+    for orders in (0, 1):
+        sv = _solver(cl, p=16, m2l_orders=orders)
+        Mii, Lii, b = sv.diagonals(phi)
+        errs[orders] = (np.abs(Mii[rows] - M_ref).max() / 0.5, rel(Lii[rows], L_ref), rel(b[rows], b_ref),
+                        maxrel(Lii[rows], L_ref), maxrel(b[rows], b_ref))
+        print("orders=%d: M=%.3e L=%.3e b=%.3e max L=%.3e b=%.3e" % ((orders,) + errs[orders]))
+    em, el, eb, xl, xb = errs[1]
+    assert em < 1e-6 and el < 1e-6 and eb < 1e-6, errs[1]
+    assert em <= 2 * errs[0][0] + 1e-12 and xl <= 2 * errs[0][3] and xb <= 2 * errs[0][4] + 1e-12, errs
+
+
 @pytest.mark.parametrize("lmax", [3, 4])
 def test_fmm_product_coarse_and_fine_leaves(c100, c100_ref, lmax):
     """Fixed octree depths on the 100-bubble cluster: at lmax = 3 every

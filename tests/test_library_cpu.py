@@ -183,8 +183,9 @@ def test_m2l_converges_geometrically():
     rng = np.random.default_rng(4)
     h = 1.0
     errs = []
+    far = next(k for k in range(316) if tuple(bfm.debug_operator(4, 2, k)[1]) == (-3, -3, -3))
     for p in (4, 8, 12):
-        for op in (0, 100, 315):
+        for op in (far, 100, 0):
             T, d = bfm.debug_operator(p, 2, op)
             cs = np.zeros(3)
             ct = cs + d * h
@@ -194,18 +195,25 @@ def test_m2l_converges_geometrically():
             e = 0.0
             for r in ct + rng.uniform(-0.5, 0.5, (4, 3)) * h:
                 e = max(e, abs(_l2p(p, Lt, ct, h, r) / _direct(pts, q, r) - 1))
-            if op == 0:
+            if op == far:
                 errs.append(e)
     assert errs[1] < errs[0] / 20 and errs[2] < errs[1] / 20, errs
     assert errs[2] < 1e-6
 
 
 def test_m2l_offset_enumeration():
+    """316 distinct far offsets, numbered nearest first (by |d|^2), so that
+    each distance class of the reduced-order M2L is a contiguous range."""
     seen = set()
+    d2 = []
     for op in range(316):
         _, d = bfm.debug_operator(4, 2, op)
         assert np.abs(d).max() >= 2 and np.abs(d).max() <= 3
         seen.add(tuple(d))
+        d2.append(int(d @ d))
     assert len(seen) == 316
+    assert d2 == sorted(d2) and d2[0] == 4 and d2[-1] == 27
+    # class boundaries: |d|^2 <= 5 (30 offsets), 6..10 (90), >= 11 (196)
+    assert sum(v <= 5 for v in d2) == 30 and sum(6 <= v <= 10 for v in d2) == 90
     with pytest.raises(bfm.BfmError):
         bfm.debug_operator(4, 2, 316)
