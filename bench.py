@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--workload", default="c1000")
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--p-diag", type=int, default=None)
+    ap.add_argument("--p-lo", type=int, default=None, help="order of the low-precision products (autotuned if unset)")
     ap.add_argument("--leaf", type=int, default=None)
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--m2l-shape", type=int, default=None, help="M2L launch shape 0..2 (-1: by size)")
@@ -108,14 +109,23 @@ def measured_traffic(cls, kernel, workload, lmax, p):
     return None
 
 
-def m2l_kernel_name(p, shape):
-    """Instantiation of the M2L translation kernel for order p and launch
-    shape (template arguments: p^2, rows per block, waves, class)."""
-    pp = p * p
-    mid = 48 if pp == 144 else (80 if pp == 400 else (64 if pp >= 64 else pp))
-    wide = pp if pp <= 144 else (128 if pp == 256 else mid)
-    rows, waves = {0: (wide, 8), 1: (mid, 4), 2: (16, 4)}[shape]
-    return f"bfm::k_translate<{pp}, {rows}, {waves}, 0>"
+def m2l_kernel_name(p, shape, orders=0):
+    """Instantiation(s) of the FP64 M2L translation kernel for order p and
+    launch shape (template arguments: applied p^2, rows per block, waves,
+    class, element type, stored p^2); with reduced orders for distant
+    offsets, the three distance classes' launches joined by ' + '."""
+    def rows_of(pp):
+        mid = 48 if pp == 144 else (80 if pp == 400 else (64 if pp >= 64 else pp))
+        wide = pp if pp <= 144 else (128 if pp == 256 else mid)
+        return {0: (wide, 8), 1: (mid, 4), 2: (16, 4)}[shape]
+    ld = p * p
+    orders_p = [p] if not orders else [p, 4 * ((p + 4) // 5), 4 * ((3 * p + 19) // 20)]
+    names = []
+    for po in orders_p:
+        pp = po * po
+        rows, waves = rows_of(pp)
+        names.append(f"bfm::k_translate<{pp}, {rows}, {waves}, 0, double, {ld}>")
+    return " + ".join(names)
 
 
 def cpu_baseline(cl, phi, matvecs, rows_n):
@@ -243,14 +253,15 @@ def roofline_entry(cls, prof, prof_steps, stats, opt, p_diag, nv, workload):
     if kind == "m2l":
         pp = p * p
         if lo_prec == 2:
-            rows = pp if pp <= 144 else (128 if pp == 256 else 80)
-            kname = f"bfm::k_translate_bf3<{pp}, {rows}, 0, true> + bfm::k_m2l_reduce<{pp}>"
+            orders_p = [p] if not opt.m2l_orders else [p, 4 * ((p + 4) // 5), 4 * ((3 * p + 19) // 20)]
+            kname = " + ".join(f"bfm::k_translate_bf3<{q * q}, {q * q if q * q <= 144 else (128 if q * q == 256 else 80)}, "
+                               f"0, true, {pp}>" for q in dict.fromkeys(orders_p)) + f" + bfm::k_m2l_reduce<{pp}>"
             peak, unit_bytes = PEAK_BF16_TFLOPS / 3.0, 4.0
         elif lo_prec == 1:
             kname, peak, unit_bytes = None, PEAK_FP32_TFLOPS, 4.0
         else:
             shape = stats["diag_m2l_shape" if group else "m2l_shape"]
-            kname = m2l_kernel_name(p, shape) if shape >= 0 else None
+            kname = m2l_kernel_name(p, shape, opt.m2l_orders) if shape >= 0 else None
             peak, unit_bytes = PEAK_FP64_TFLOPS, 8.0
         bound, tcls = "mfma", "m2l"
         nch = 5 if group == "diag_" else 1
@@ -308,6 +319,7 @@ def main():
     q_t = torch.zeros_like(phi_t)
     overrides = dict(p=a.p, p_diag=a.p_diag, leaf_target=a.leaf, lmax=a.lmax, m2l_shape=a.m2l_shape,
                      gmres_restart=a.restart, precond_degree=a.precond_degree)
+    tuned_only = dict(p_lo=a.p_lo)
 
     def run(sv, steps, warmup, profile):
         def step():
@@ -350,7 +362,7 @@ def main():
     if tuned:
         sv, tune = forms.make_solver(cl, "tuned", autotune=bool(a.autotune),
                                      tune_tol=forms.TUNE_TOL if a.tune_tol is None else a.tune_tol,
-                                     gmres_tol=a.tol, use_graph=a.graph, **overrides)
+                                     gmres_tol=a.tol, use_graph=a.graph, **overrides, **tuned_only)
     else:
         sv, tune = forms.make_solver(cl, "plain", gmres_tol=a.plain_tol, **overrides)
     if tune is not None:

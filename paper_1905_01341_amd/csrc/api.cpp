@@ -107,14 +107,15 @@ struct Timer {
     }
 };
 
+static void solve_rest(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, Timer &t_tree,
+                       bfm_solve_info *info);
+
 void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm_solve_info *info) {
     BFM_CHECK(guess == BFM_GUESS_ZERO || guess == BFM_GUESS_GIVEN || guess == BFM_GUESS_LEARNED, BFM_EINVAL,
               "use_guess must be BFM_GUESS_ZERO, BFM_GUESS_GIVEN or BFM_GUESS_LEARNED");
-    bfm_solve_info loc{};
-    const int64_t n = c->nv;
     // phase timers only record events; their times are read once at the end
     Timer t_tree(c->stream);
-    ensure_geometry(c);
+    ensure_geometry(c, false);  // checked by the octree build's first wait
     // the coarse space needs only the geometry: it is built on a second stream
     // beside the octree build, whose short kernels and host round trips leave
     // most of the device free (beside the diagonal pass its serial chain of
@@ -123,6 +124,23 @@ void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm
         coarse_mark(c);
         coarse_launch(c);
     }
+    try {
+        solve_rest(c, phi_dev, q_dev, guess, t_tree, info);
+    } catch (...) {
+        // the worker has queued the build before the call returns (no thread
+        // of the handle is left running between calls)
+        try {
+            coarse_join(c);
+        } catch (...) {
+        }
+        throw;
+    }
+}
+
+static void solve_rest(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, Timer &t_tree,
+                       bfm_solve_info *info) {
+    bfm_solve_info loc{};
+    const int64_t n = c->nv;
     ensure_tree(c);
     t_tree.stop();
     Timer t_guess(c->stream);
@@ -231,7 +249,13 @@ int bfm_destroy(bfm_ctx *c) {
         mlp_free(c);
         step_free(c);
         graph_invalidate(c);
+        try {
+            coarse_join(c);  // (an error of the build is of no interest here)
+        } catch (...) {
+        }
+        coarse_worker_free(c);
         if (c->host_small) (void)hipHostFree(c->host_small);
+        if (c->host_flag) (void)hipHostFree(c->host_flag);
         if (c->side) {
             (void)hipStreamSynchronize(c->side);
             (void)hipStreamDestroy(c->side);
@@ -282,8 +306,8 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
         BFM_CHECK(nb >= 0, BFM_EINVAL, "negative bubble count");
         if (c->side) {  // a coarse build in flight reads the buffers replaced below
             DeviceScope ds(c->device);
+            coarse_join(c);  // the worker has queued the build
             BFM_HIP(hipStreamSynchronize(c->side));
-            c->coarse_pending = false;
         }
         if (nb > 1) BFM_CHECK(vtx_off && tri_off, BFM_EINVAL, "bubble ranges required when nb > 1");
         DeviceScope ds(c->device);

@@ -31,10 +31,12 @@ struct Precond {
     // coarse space of per-bubble constants (two-level form)
     DevBuf<double> U;                  // own-bubble column sums of s^T L, caller order [nv]
     DevBuf<double> ccen, carea;        // area-weighted centroids [nb][3], areas [nb]
+    DevBuf<double> cusum;              // bubble sums of U [nb] (the coarse matrix's diagonal)
     DevBuf<double> Ainv, gj_row, gj_col, gj_piv;  // inverse coarse matrix [nb x nb] and Gauss-Jordan work
     DevBuf<double> csum, cy;           // per-bubble sums [3][nb], coarse correction [nb]
 };
 struct Mlp;      // learned initial guess (learn.hip)
+struct CoarseWorker;  // host thread queueing the coarse build (precond.hip)
 struct Stepper;  // captured product (tune.hip)
 void graph_invalidate(bfm_ctx *c);
 // out_s = A P^{-1} in_s (pc) or A in_s through the captured graph; captures on first use
@@ -54,6 +56,7 @@ struct bfm_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_geom = nullptr, ev_coarse = nullptr;
     bool coarse_pending = false;  // a coarse build for the current geometry is in flight on `side`
+    bfm::CoarseWorker *coarse_worker = nullptr;  // host thread that queues the coarse build
     bool coarse_marked = false;   // ev_geom marks the geometry a coarse build will read
     hipStream_t near = nullptr;   // near-field stream of both fast multipole products (default priority)
     bool own_stream = false;
@@ -69,7 +72,9 @@ struct bfm_ctx {
     // geometry (original order): s [nv], normals SoA [3][nv]
     bfm::DevBuf<double> s, nrm, tri_hc, tri_area;
     bfm::DevBuf<int> flag;
+    int *host_flag = nullptr;     // pinned copy of the geometry checks
     bool geom_valid = false;
+    bool geom_unchecked = false;  // geometry rebuilt, its checks not yet read
 
     bfm::Tree tree;
     bool tree_valid = false;
@@ -106,7 +111,10 @@ struct bfm_ctx {
 
 namespace bfm {
 
-void ensure_geometry(bfm_ctx *c);
+void ensure_geometry(bfm_ctx *c, bool check_now = true);
+// read the checks of the last geometry build; synced: the stream has been
+// waited for since the build (else this waits)
+void geometry_check(bfm_ctx *c, bool synced = false);
 void ensure_tree(bfm_ctx *c);
 void ensure_ops(bfm_ctx *c);
 // operators of the low-precision product group for precision prec (FP32 or BF16X3)
@@ -140,6 +148,8 @@ void coarse_mark(bfm_ctx *c);
 void coarse_launch(bfm_ctx *c);
 // order the main stream after a coarse build in flight (no-op if none)
 void coarse_join(bfm_ctx *c);
+// stop the handle's coarse-build thread (after the build it queued)
+void coarse_worker_free(bfm_ctx *c);
 // in-place inverse of an SPD n x n column-major device matrix (blocked Gauss-Jordan)
 void spd_inverse(double *A, int n, DevBuf<double> &piv, DevBuf<double> &row, DevBuf<double> &col,
                  hipStream_t st);

@@ -376,30 +376,63 @@ __global__ void __launch_bounds__(64 * kBfWaves) k_translate_bf3(int op0, int no
 
 // L[b] = sum of the stored M2L results of target box b's tasks, in the order
 // the tasks were generated (fixed, so the sum is reproducible). One wave per
-// target box, four coefficients per lane per pass. Tasks at grouped
-// positions >= cut[0] (>= cut[1]) belong to the second (third) distance
-// class and carry only their first pp[1] (pp[2]) coefficients.
+// target box: a row of LD coefficients is LD / 4 float4 groups; when that is
+// under 64, the wave's lanes form G = 64 / (LD / 4) groups that take every
+// G-th task (two tasks' loads in flight per lane), and the groups' sums are
+// added by lane shuffles in a fixed order. Tasks at grouped positions >=
+// cut1 (>= cut2) belong to the second (third) distance class and carry only
+// their first pp1 (pp2) coefficients.
 template <int LD>
 __global__ void __launch_bounds__(64) k_m2l_reduce(const int *dst_off, const int *pos_of, int64_t box0, int cut1,
                                                    int cut2, int pp1, int pp2, const float *part, float *L) {
     static_assert(LD % 4 == 0, "whole float4 groups");
+    constexpr int NV = LD / 4;
+    constexpr int G = NV >= 64 ? 1 : 64 / NV;
+    static_assert(G == 1 || G * NV == 64, "groups tile the wave");
     const int64_t k = blockIdx.x;
     const int a = dst_off[k], e = dst_off[k + 1];
     if (a == e) return;  // no far-field sources at this box's level (L stays zero)
     float *lb = L + (box0 + k) * LD;
-    for (int c = threadIdx.x * 4; c < LD; c += 256) {
+    const int lane = threadIdx.x, grp = lane / (G > 1 ? NV : 64);
+    auto add = [](float4 &s, const float4 v) {
+        s.x += v.x;
+        s.y += v.y;
+        s.z += v.z;
+        s.w += v.w;
+    };
+    for (int c0 = 0; c0 < NV; c0 += (G > 1 ? NV : 64)) {
+        const int cv = c0 + (G > 1 ? lane % NV : lane);  // this lane's float4 group
+        const int c = 4 * cv;
         float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int i = a; i < e; ++i) {
-            const int pos = pos_of[i];
-            const int pp = pos >= cut2 ? pp2 : (pos >= cut1 ? pp1 : LD);
-            if (c >= pp) continue;
-            const float4 v = *reinterpret_cast<const float4 *>(part + (int64_t)pos * LD + c);
-            s.x += v.x;
-            s.y += v.y;
-            s.z += v.z;
-            s.w += v.w;
+        if (cv < NV) {
+            int i = a + grp;
+            for (; i + G < e; i += 2 * G) {
+                const int p0 = pos_of[i], p1 = pos_of[i + G];
+                const int q0 = p0 >= cut2 ? pp2 : (p0 >= cut1 ? pp1 : LD);
+                const int q1 = p1 >= cut2 ? pp2 : (p1 >= cut1 ? pp1 : LD);
+                const float4 v0 = c < q0 ? *reinterpret_cast<const float4 *>(part + (int64_t)p0 * LD + c)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 v1 = c < q1 ? *reinterpret_cast<const float4 *>(part + (int64_t)p1 * LD + c)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                add(s, v0);
+                add(s, v1);
+            }
+            if (i < e) {
+                const int p0 = pos_of[i];
+                const int q0 = p0 >= cut2 ? pp2 : (p0 >= cut1 ? pp1 : LD);
+                if (c < q0) add(s, *reinterpret_cast<const float4 *>(part + (int64_t)p0 * LD + c));
+            }
         }
-        *reinterpret_cast<float4 *>(lb + c) = s;
+        if (G > 1) {
+#pragma unroll
+            for (int off = 32; off >= NV; off >>= 1) {
+                s.x += __shfl_down(s.x, off);
+                s.y += __shfl_down(s.y, off);
+                s.z += __shfl_down(s.z, off);
+                s.w += __shfl_down(s.w, off);
+            }
+        }
+        if (cv < NV && grp == 0) *reinterpret_cast<float4 *>(lb + c) = s;
     }
 }
 

@@ -18,6 +18,11 @@
 #include <complex>
 #include <vector>
 
+#include <condition_variable>
+#include <exception>
+#include <mutex>
+#include <thread>
+
 #include "ctx.h"
 
 namespace bfm {
@@ -325,7 +330,7 @@ __global__ void k_precond_out(const double *Y, const int *perm, int64_t n, int n
 //   U_a = s_a^T L_aa (per vertex), m_b = sum_{j in b} s_j x_j.
 
 // area and area-weighted centroid of every bubble
-__global__ void k_coarse_geom(const double *xyz, const double *s, int nd, double *cen, double *area) {
+__global__ void k_coarse_geom(const double *xyz, const double *s, int nd, double *cen, double *area, double *usum) {
     __shared__ double red[4][256];
     const int b = blockIdx.x;
     double a[4] = {0, 0, 0, 0};
@@ -347,6 +352,7 @@ __global__ void k_coarse_geom(const double *xyz, const double *s, int nd, double
     if (threadIdx.x == 0) {
         for (int k = 0; k < 3; ++k) cen[3 * b + k] = red[k][0] / red[3][0];
         area[b] = red[3][0];
+        usum[b] = 0.0;  // summed by k_coarse_u
     }
 }
 
@@ -358,72 +364,84 @@ __global__ void k_coarse_geom(const double *xyz, const double *s, int nd, double
 // (The other bubbles' closed surfaces contribute only their discretisation
 // error to these sums; the coarse space is a preconditioner, so the own
 // bubble suffices and the build does not wait for the diagonal pass.)
-// Grid (vertex blocks, bubbles); the bubble's points pass through LDS in
-// chunks. 1/r: the hardware estimate refined by one Newton step (relative
-// error ~1e-15); the pair i = j (r = 0) is masked.
+// One workgroup per tile (vertex block of 256, bubble; a grid-stride loop
+// over tiles: a capped grid that left wave slots free for the octree build
+// beside it measured slower, its kernels started later); the bubble's points
+// pass through LDS in chunks. The sums run in FP32 on coordinates relative to the
+// bubble's centroid (formed in FP64): the coarse space only preconditions,
+// and at a mesh spacing of a tenth of the radius the relative error of r_ij
+// is about 1e-6. The pair i = j (r = 0) is masked. usum[b] += the tile's
+// sum of U (the coarse matrix's diagonal).
 __global__ void __launch_bounds__(256) k_coarse_u(const double *xyz, const double *s, const double *nrm, int64_t nv,
-                                                  int nd, double *U) {
+                                                  int nd, int nb, const double *cen, double *U, double *usum) {
     constexpr int CH = 256;
-    __shared__ double sx[CH], sy[CH], sz[CH], ss[CH], snx[CH], sny[CH], snz[CH];
-    const int b = blockIdx.y;
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    const int64_t base = (int64_t)b * nd;
-    const bool ok = j < nd;
-    const int64_t oj = base + (ok ? j : 0);
-    const double xj = xyz[3 * oj], yj = xyz[3 * oj + 1], zj = xyz[3 * oj + 2];
-    double acc = 0.0, ax = 0.0, ay = 0.0, az = 0.0;  // sum s_i / r; sum M-type vector - L-type vector
-    for (int c0 = 0; c0 < nd; c0 += CH) {
-        const int cn = min(CH, nd - c0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < cn; t += 256) {
-            const int64_t o = base + c0 + t;
-            sx[t] = xyz[3 * o];
-            sy[t] = xyz[3 * o + 1];
-            sz[t] = xyz[3 * o + 2];
-            ss[t] = s[o];
-            snx[t] = nrm[o];
-            sny[t] = nrm[nv + o];
-            snz[t] = nrm[2 * nv + o];
+    __shared__ float4 sp[CH];  // x, y, z, s
+    __shared__ float4 sn[CH];  // n_x, n_y, n_z
+    __shared__ double red[4];
+    const int nvb = (nd + 255) / 256;
+    for (int64_t tile = blockIdx.x; tile < (int64_t)nvb * nb; tile += gridDim.x) {
+        const int b = (int)(tile / nvb);
+        const int j = (int)(tile - (int64_t)b * nvb) * 256 + threadIdx.x;
+        const int64_t base = (int64_t)b * nd;
+        const bool ok = j < nd;
+        const int64_t oj = base + (ok ? j : 0);
+        const double c0x = cen[3 * b], c0y = cen[3 * b + 1], c0z = cen[3 * b + 2];
+        const float xj = (float)(xyz[3 * oj] - c0x), yj = (float)(xyz[3 * oj + 1] - c0y),
+                    zj = (float)(xyz[3 * oj + 2] - c0z);
+        float acc = 0.f, ax = 0.f, ay = 0.f, az = 0.f;  // sum s_i / r; sum M-type vector - L-type vector
+        for (int c0 = 0; c0 < nd; c0 += CH) {
+            const int cn = min(CH, nd - c0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < cn; t += 256) {
+                const int64_t o = base + c0 + t;
+                sp[t] = make_float4((float)(xyz[3 * o] - c0x), (float)(xyz[3 * o + 1] - c0y),
+                                    (float)(xyz[3 * o + 2] - c0z), (float)s[o]);
+                sn[t] = make_float4((float)nrm[o], (float)nrm[nv + o], (float)nrm[2 * nv + o], 0.f);
+            }
+            __syncthreads();
+            const int self = j - c0;  // position of the receiver in this chunk (masked)
+            for (int t = 0; t < cn; ++t) {
+                const float4 q = sp[t], m = sn[t];
+                const float dx = xj - q.x, dy = yj - q.y, dz = zj - q.z;  // r_j - r_i
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float inv = (t == self) ? 0.f : __builtin_amdgcn_rsqf(r2);
+                const float si = q.w * inv;  // s_i / r
+                acc += si;
+                // s_i n_i.(r_j - r_i) / r^3 (r_i - r_j) - s_i / r n_i
+                const float g = (m.x * dx + m.y * dy + m.z * dz) * si * inv * inv;
+                ax -= g * dx + si * m.x;
+                ay -= g * dy + si * m.y;
+                az -= g * dz + si * m.z;
+            }
         }
-        __syncthreads();
-        for (int t = 0; t < cn; ++t) {
-            const double dx = xj - sx[t], dy = yj - sy[t], dz = zj - sz[t];  // r_j - r_i
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double y = __builtin_amdgcn_rsq(r2);
-            double inv = fma(0.5 * y, fma(-r2 * y, y, 1.0), y);
-            inv = (c0 + t == j) ? 0.0 : inv;
-            const double si = ss[t] * inv;  // s_i / r
-            acc += si;
-            // s_i n_i.(r_j - r_i) / r^3 (r_i - r_j) - s_i / r n_i
-            const double g = (snx[t] * dx + sny[t] * dy + snz[t] * dz) * si * inv * inv;
-            ax -= g * dx + si * snx[t];
-            ay -= g * dy + si * sny[t];
-            az -= g * dz + si * snz[t];
+        double u = 0.0;
+        if (ok) {
+            const double k4 = 1.0 / (4.0 * 3.14159265358979323846);
+            const double ljj =
+                (nrm[oj] * (double)ax + nrm[nv + oj] * (double)ay + nrm[2 * nv + oj] * (double)az) * k4;
+            u = s[oj] * ((double)acc * k4 + ljj);
+            U[oj] = u;
         }
-    }
-    if (ok) {
-        const double k4 = 1.0 / (4.0 * 3.14159265358979323846);
-        const double ljj = (nrm[oj] * ax + nrm[nv + oj] * ay + nrm[2 * nv + oj] * az) * k4;
-        U[oj] = s[oj] * (acc * k4 + ljj);
+        // the tile's sum of U: wave sums, then one atomic
+        for (int o = 32; o > 0; o >>= 1) u += __shfl_down(u, o);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = u;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(usum + b, red[0] + red[1] + red[2] + red[3]);
     }
 }
 
 // A (column-major nb x nb): off-diagonal point-monopole couplings; the
 // diagonal from the bubble sums of U.
-__global__ void k_coarse_matrix(const double *cen, const double *area, const double *U, int nd, int nb,
-                                double *A) {
+__global__ void k_coarse_matrix(const double *cen, const double *area, const double *usum, int nb, double *A) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= (int64_t)nb * nb) return;
     const int a = (int)(e % nb), b = (int)(e / nb);
-    if (a != b) {
-        const double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1],
-                     dz = cen[3 * a + 2] - cen[3 * b + 2];
-        A[e] = area[a] * area[b] / (4.0 * 3.14159265358979323846 * sqrt(dx * dx + dy * dy + dz * dz));
+    if (a == b) {
+        A[e] = usum[a];
         return;
     }
-    double t = 0.0;
-    for (int v = 0; v < nd; ++v) t += U[(int64_t)a * nd + v];
-    A[e] = t;
+    const double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1], dz = cen[3 * a + 2] - cen[3 * b + 2];
+    A[e] = area[a] * area[b] / (4.0 * 3.14159265358979323846 * sqrt(dx * dx + dy * dy + dz * dz));
 }
 
 // Gauss-Jordan inverse (no pivoting: the coarse matrix is symmetric positive
@@ -629,22 +647,26 @@ void coarse_build(bfm_ctx *c, hipStream_t st) {
     const int nd = P.nd, nb = c->nb;
     P.csum.ensure(3 * (size_t)nb);  // used by precond_apply
     P.cy.ensure(nb);
-    double *cen = P.ccen.ensure(3 * (size_t)nb), *area = P.carea.ensure(nb);
-    k_coarse_geom<<<nb, 256, 0, st>>>(c->xyz.get(), c->s.get(), nd, cen, area);
+    double *cen = P.ccen.ensure(3 * (size_t)nb), *area = P.carea.ensure(nb), *usum = P.cusum.ensure(nb);
+    k_coarse_geom<<<nb, 256, 0, st>>>(c->xyz.get(), c->s.get(), nd, cen, area, usum);
     BFM_LAUNCHED();
     double *U = P.U.ensure((size_t)nd * nb);
-    k_coarse_u<<<dim3(nblk(nd, 256), nb), 256, 0, st>>>(c->xyz.get(), c->s.get(), c->nrm.get(), c->nv, nd, U);
+    const int64_t tiles = (int64_t)nblk(nd, 256) * nb;
+    k_coarse_u<<<(unsigned)tiles, 256, 0, st>>>(c->xyz.get(), c->s.get(), c->nrm.get(), c->nv, nd, nb, cen, U, usum);
     BFM_LAUNCHED();
     double *A = P.Ainv.ensure((size_t)nb * nb);
-    k_coarse_matrix<<<nblk((int64_t)nb * nb, 256), 256, 0, st>>>(cen, area, U, nd, nb, A);
+    k_coarse_matrix<<<nblk((int64_t)nb * nb, 256), 256, 0, st>>>(cen, area, usum, nb, A);
     BFM_LAUNCHED();
     spd_inverse(A, nb, P.gj_piv, P.gj_row, P.gj_col, st);
 }
 
+static void coarse_worker_wait(CoarseWorker *w);
+
 void coarse_join(bfm_ctx *c) {
     if (!c->coarse_pending) return;
-    BFM_HIP(hipStreamWaitEvent(c->stream, c->ev_coarse, 0));
     c->coarse_pending = false;
+    if (c->coarse_worker) coarse_worker_wait(c->coarse_worker);  // the build and its event are queued
+    BFM_HIP(hipStreamWaitEvent(c->stream, c->ev_coarse, 0));
 }
 
 void coarse_mark(bfm_ctx *c) {
@@ -658,12 +680,90 @@ void coarse_mark(bfm_ctx *c) {
     c->coarse_marked = true;
 }
 
+// The coarse build is about a hundred small launches. Queued by the solving
+// thread they would hold it, and so the octree build that runs beside them on
+// the main stream, for a millisecond or more; a worker thread of the handle
+// queues them instead. coarse_launch hands the build over and returns;
+// coarse_join waits until the worker has queued the build and its completion
+// event (not for the device), then orders the main stream after that event.
+struct CoarseWorker {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bfm_ctx *job = nullptr;  // pending build (taken by the worker)
+    bool busy = false, stop = false;
+    std::exception_ptr err;
+};
+
+static void coarse_worker_main(CoarseWorker *w, int device) {
+    bool dev_set = false;
+    for (;;) {
+        bfm_ctx *c = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(w->mu);
+            w->cv.wait(lk, [&] { return w->job != nullptr || w->stop; });
+            if (!w->job) return;  // stop, nothing pending
+            c = w->job;
+            w->job = nullptr;
+        }
+        try {
+            if (!dev_set) {
+                BFM_HIP(hipSetDevice(device));
+                dev_set = true;
+            }
+            BFM_HIP(hipStreamWaitEvent(c->side, c->ev_geom, 0));
+            coarse_build(c, c->side);
+            BFM_HIP(hipEventRecord(c->ev_coarse, c->side));
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(w->mu);
+            w->err = std::current_exception();
+        }
+        {
+            std::lock_guard<std::mutex> lk(w->mu);
+            w->busy = false;
+        }
+        w->cv.notify_all();
+    }
+}
+
+static void coarse_worker_wait(CoarseWorker *w) {
+    std::unique_lock<std::mutex> lk(w->mu);
+    w->cv.wait(lk, [&] { return !w->busy; });
+    if (w->err) {
+        std::exception_ptr e = w->err;
+        w->err = nullptr;
+        std::rethrow_exception(e);
+    }
+}
+
+void coarse_worker_free(bfm_ctx *c) {
+    CoarseWorker *w = c->coarse_worker;
+    if (!w) return;
+    {
+        std::lock_guard<std::mutex> lk(w->mu);
+        w->stop = true;
+    }
+    w->cv.notify_all();
+    if (w->th.joinable()) w->th.join();
+    delete w;
+    c->coarse_worker = nullptr;
+}
+
 void coarse_launch(bfm_ctx *c) {
     if (!c->coarse_marked) coarse_mark(c);
     c->coarse_marked = false;
-    BFM_HIP(hipStreamWaitEvent(c->side, c->ev_geom, 0));
-    coarse_build(c, c->side);
-    BFM_HIP(hipEventRecord(c->ev_coarse, c->side));
+    if (!c->coarse_worker) {
+        auto *w = new CoarseWorker();
+        w->th = std::thread(coarse_worker_main, w, c->device);
+        c->coarse_worker = w;
+    }
+    CoarseWorker *w = c->coarse_worker;
+    {
+        std::lock_guard<std::mutex> lk(w->mu);
+        w->job = c;
+        w->busy = true;
+    }
+    w->cv.notify_all();
     c->coarse_pending = true;
 }
 

@@ -42,6 +42,8 @@ __global__ void k_tri_geom(const double *xyz, const int *tri, int64_t nt, int64_
     area[k] = 0.5 * len;
 }
 
+__global__ void k_fill_flag(int *flag) { *flag = 0; }
+
 __global__ void k_vertex_geom(const int *v2t_off, const int *v2t, const double *hc, const double *area,
                               int64_t nv, double *s, double *nrm, int *flag) {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -63,7 +65,10 @@ __global__ void k_vertex_geom(const int *v2t_off, const int *v2t, const double *
     nrm[2 * nv + j] = mz * il;
 }
 
-void ensure_geometry(bfm_ctx *c) {
+// The mesh checks of the geometry kernels land in a pinned flag; check_now
+// waits for it, otherwise the first wait of the octree build that follows
+// (geometry_check) brings it in with no extra round trip.
+void ensure_geometry(bfm_ctx *c, bool check_now) {
     if (c->geom_valid) return;
     BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
     hipStream_t st = c->stream;
@@ -72,7 +77,9 @@ void ensure_geometry(bfm_ctx *c) {
     c->tri_hc.ensure(3 * c->nt);
     c->tri_area.ensure(c->nt);
     int *flag = c->flag.ensure(1);
-    BFM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    if (!c->host_flag) BFM_HIP(hipHostMalloc((void **)&c->host_flag, sizeof(int), 0));
+    k_fill_flag<<<1, 1, 0, st>>>(flag);
+    BFM_LAUNCHED();
     k_tri_geom<<<nblk(c->nt, 256), 256, 0, st>>>(c->xyz.get(), c->tri.get(), c->nt, c->nv,
                                                  c->tri_hc.get(), c->tri_area.get(), flag);
     BFM_LAUNCHED();
@@ -80,20 +87,34 @@ void ensure_geometry(bfm_ctx *c) {
                                                     c->tri_area.get(), c->nv, c->s.get(), c->nrm.get(),
                                                     flag);
     BFM_LAUNCHED();
-    int hf = 0;
-    BFM_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipStreamSynchronize(st));
+    BFM_HIP(hipMemcpyAsync(c->host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    c->geom_valid = true;
+    c->geom_unchecked = true;
+    if (check_now) geometry_check(c);
+}
+
+void geometry_check(bfm_ctx *c, bool synced) {
+    if (!c->geom_unchecked) return;
+    if (!synced) BFM_HIP(hipStreamSynchronize(c->stream));
+    c->geom_unchecked = false;
+    const int hf = *c->host_flag;
+    if (hf) c->geom_valid = false;  // a later call rebuilds and fails the same way
     BFM_CHECK(!(hf & 2), BFM_EMESH, "triangle vertex index out of range");
     BFM_CHECK(!(hf & 1), BFM_EMESH, "degenerate (zero-area) triangle");
     BFM_CHECK(!(hf & 4), BFM_EMESH, "vertex with vanishing area-weighted normal");
-    c->geom_valid = true;
 }
 
 void ensure_tree(bfm_ctx *c) {
-    ensure_geometry(c);
-    if (c->tree_valid) return;
+    ensure_geometry(c, false);
+    if (c->tree_valid) {
+        geometry_check(c);
+        return;
+    }
     const int pi = c->prof.begin(KC_TREE, c->stream);
     build_tree(c->tree, c->xyz.get(), c->nv, c->opt.lmax, c->opt.leaf_target, c->stream);
+    // the build has waited for the stream after the flag's copy (its bounding
+    // box is read back first): no extra round trip
+    geometry_check(c, true);
     sort_geometry(c->tree, c->s.get(), c->nrm.get(), c->stream);
     c->prof.end(pi, c->stream, 0.0, 0.0);
     c->tree_valid = true;

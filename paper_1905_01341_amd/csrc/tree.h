@@ -106,14 +106,16 @@ struct Tree {
     // once the sizes have been seen
     struct Scratch {
         DevBuf<unsigned long long> cnt, np;
-        DevBuf<int> mo, flag, pos, tmp, icnt, ioff, iidx, iidx2, count, offs, ts, td, to, hist;
+        DevBuf<int> mo, flag, pos, tmp, icnt, ioff, lcnt, loff, iidx, iidx2, count, offs, ts, td, to, cs, cd, co, hist;
         DevBuf<int> rs_hist, rs_scanned, rs_tmp;
         DevBuf<uint64_t> ikey, ikey2;
         DevBuf<double> bbox;
+        void *host = nullptr;  // pinned block the build's waits read sizes into
     } scratch;
 
     ~Tree() {
         for (auto *t : m2m) delete t;
+        if (scratch.host) (void)hipHostFree(scratch.host);
     }
 };
 
@@ -134,10 +136,8 @@ void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st);
 void radix_sort(uint64_t *keys, int *vals, uint64_t *keys_tmp, int *vals_tmp, int64_t n, int bits, Tree::Scratch &scr,
                 hipStream_t st);
 
-// Device-wide exclusive scan of int32 (in place allowed); returns the total
-// (one wait for the stream).
-int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp);
-// The same scan left in flight on the stream (no total, no wait).
+// Device-wide exclusive scan of int32 (in place allowed), left in flight on
+// the stream (no wait).
 void exclusive_scan_async(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp);
 
 }  // namespace bfm

@@ -99,13 +99,54 @@ __global__ void k_bbox_partial(const double *xyz, int64_t n, double *part) {
         }
 }
 
-__global__ void k_morton(const double *xyz, int64_t n, double ox, double oy, double oz,
-                         double inv_cell, uint64_t *key, int *idx) {
+// The cube from the partial boxes, on the device (the Morton pass reads it
+// without a wait for the host): geo = (origin x, y, z, side, 2^kKeyBits /
+// side, all bounds finite ? 1 : 0). The cube is the box's largest extent
+// enlarged by 1e-9 relative, centred on the box.
+__global__ void __launch_bounds__(256) k_bbox_final(const double *part, int nbb, double *geo) {
+    __shared__ double smin[3][256], smax[3][256];
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int b = threadIdx.x; b < nbb; b += 256)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = fmin(mn[d], part[6 * b + d]);
+            mx[d] = fmax(mx[d], part[6 * b + 3 + d]);
+        }
+    for (int d = 0; d < 3; ++d) {
+        smin[d][threadIdx.x] = mn[d];
+        smax[d][threadIdx.x] = mx[d];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int d = 0; d < 3; ++d) {
+                smin[d][threadIdx.x] = fmin(smin[d][threadIdx.x], smin[d][threadIdx.x + s]);
+                smax[d][threadIdx.x] = fmax(smax[d][threadIdx.x], smax[d][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double ext = 0.0;
+        bool fin = true;
+        for (int d = 0; d < 3; ++d) {
+            fin = fin && isfinite(smin[d][0]) && isfinite(smax[d][0]);
+            ext = fmax(ext, smax[d][0] - smin[d][0]);
+        }
+        if (!(ext > 0.0)) ext = 1.0;
+        const double side = ext * (1.0 + 1e-9) + 1e-300;
+        for (int d = 0; d < 3; ++d) geo[d] = 0.5 * (smin[d][0] + smax[d][0]) - 0.5 * side;
+        geo[3] = side;
+        geo[4] = (double)(1 << kKeyBits) / side;
+        geo[5] = fin ? 1.0 : 0.0;
+    }
+}
+
+__global__ void k_morton(const double *xyz, int64_t n, const double *geo, uint64_t *key, int *idx) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int lim = (1 << kKeyBits) - 1;
     int c[3];
-    const double o[3] = {ox, oy, oz};
+    const double o[3] = {geo[0], geo[1], geo[2]};
+    const double inv_cell = geo[4];
     for (int d = 0; d < 3; ++d) {
         double f = floor((xyz[3 * i + d] - o[d]) * inv_cell);
         int v = (int)fmin(fmax(f, 0.0), (double)lim);
@@ -310,22 +351,6 @@ void exclusive_scan_async(const int *in, int *out, int64_t n, hipStream_t st, De
     scan_rec(in, out, n, st, scan_scratch(n, tmp));
 }
 
-int64_t exclusive_scan(const int *in, int *out, int64_t n, hipStream_t st, DevBuf<int> &tmp) {
-    if (n <= 0) return 0;
-    int64_t slot = 0;
-    int *t = scan_scratch(n, tmp, &slot);
-    int *dtotal = t + slot;
-    k_scan_last<<<1, 64, 0, st>>>(in, n, dtotal);
-    BFM_LAUNCHED();
-    scan_rec(in, out, n, st, t);
-    k_scan_total<<<1, 64, 0, st>>>(out, n, dtotal);
-    BFM_LAUNCHED();
-    int total = 0;
-    BFM_HIP(hipMemcpyAsync(&total, dtotal, sizeof(int), hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipStreamSynchronize(st));
-    return total;
-}
-
 // ---------------------------------------------------------------------------
 // Levels
 
@@ -345,26 +370,33 @@ __global__ void k_level_counts(const uint64_t *key, int64_t n, int lmax, unsigne
         atomicAdd(&counts[threadIdx.x], (unsigned long long)c[threadIdx.x]);
 }
 
-__global__ void k_level_flags(const uint64_t *key, int64_t n, int shift, int *flag) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    flag[i] = (i == 0 || (key[i] >> shift) != (key[i - 1] >> shift)) ? 1 : 0;
+// Boxes of every level 0..lmax in one pass. Entry e = l n + i flags point i
+// when it opens a box of level l (its key differs from point i-1's at that
+// level). Levels are numbered one after the other, so an exclusive scan over
+// all (lmax + 1) n flags gives every box its global index directly.
+__global__ void k_level_flags(const uint64_t *key, int64_t n, int lmax, int *flag) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)(lmax + 1) * n) return;
+    const int l = (int)(e / n);
+    const int64_t i = e - (int64_t)l * n;
+    const int shift = 3 * (kKeyBits - l);
+    flag[e] = (i == 0 || (key[i] >> shift) != (key[i - 1] >> shift)) ? 1 : 0;
 }
 
-__global__ void k_level_scatter(const uint64_t *key, int64_t n, int shift, const int *flag,
-                                const int *pos, int64_t box0, int level, uint64_t *box_key,
-                                int *box_level, int *box_pt0) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n || !flag[i]) return;
-    const int64_t b = box0 + pos[i];
-    box_key[b] = key[i] >> shift;
-    box_level[b] = level;
+// Box key, level and first point of every box; pt_leaf[i] = leaf (level
+// lmax box, counted from leaf0) of point i.
+__global__ void k_level_scatter(const uint64_t *key, int64_t n, int lmax, const int *flag, const int *pos,
+                                int64_t leaf0, uint64_t *box_key, int *box_level, int *box_pt0, int *pt_leaf) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)(lmax + 1) * n) return;
+    const int l = (int)(e / n);
+    const int64_t i = e - (int64_t)l * n;
+    if (l == lmax) pt_leaf[i] = (int)(pos[e] + flag[e] - 1 - leaf0);  // inclusive count - 1
+    if (!flag[e]) return;
+    const int64_t b = pos[e];
+    box_key[b] = key[i] >> (3 * (kKeyBits - l));
+    box_level[b] = l;
     box_pt0[b] = (int)i;
-}
-
-__global__ void k_pt_leaf(const int *flag, const int *pos, int64_t n, int *pt_leaf) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) pt_leaf[i] = pos[i] + flag[i] - 1;  // inclusive prefix - 1
 }
 
 __device__ inline int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t v) {
@@ -564,14 +596,9 @@ __device__ inline void child_range(const uint64_t *box_key, const LevelInfo &li,
     c1 = lower_bound_u64(box_key, li.off[l + 1], li.off[l + 2], (k + 1) << 3);
 }
 
-// mode 0: count the M2L pairs of every (target box, parent-neighbour slot);
-// mode 1: write them. One thread per (box, slot), so a level's boxes give 27
-// times as many threads; the pairs come out ordered by box, then slot.
-__global__ void k_m2l_pairs(int mode, int64_t b0, int64_t b1, LevelInfo li, const uint64_t *box_key,
-                            const int *box_level, const int *box_parent, const int *nbr, int *count,
-                            const int *offs, int *tsrc, int *tdst, int *top) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (b1 - b0) * 27) return;
+__device__ inline void m2l_pairs_one(int mode, int64_t t, int64_t b0, const LevelInfo &li, const uint64_t *box_key,
+                                     const int *box_level, const int *box_parent, const int *nbr, int *count,
+                                     const int *offs, int *tsrc, int *tdst, int *top, int *lh) {
     const int64_t b = b0 + t / 27;
     const int s = (int)(t % 27);
     const int q = nbr[27 * (int64_t)box_parent[b] + s];
@@ -589,9 +616,11 @@ __global__ void k_m2l_pairs(int mode, int64_t b0, int64_t b1, LevelInfo li, cons
             const int dx = ix - jx, dy = iy - jy, dz = iz - jz;
             if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
             if (mode == 1) {
+                const int op = c_m2l_lut[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)];
                 tsrc[w] = (int)cc;
                 tdst[w] = (int)b;
-                top[w] = c_m2l_lut[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)];
+                top[w] = op;
+                atomicAdd(&lh[op], 1);
                 ++w;
             }
             ++c;
@@ -600,27 +629,75 @@ __global__ void k_m2l_pairs(int mode, int64_t b0, int64_t b1, LevelInfo li, cons
     if (mode == 0) count[t] = c;
 }
 
-// Tasks of one level's M2M/L2L: child box c (level l) <-> parent.
-__global__ void k_tree_pairs(int64_t b0, int64_t b1, const uint64_t *box_key, const int *box_parent,
-                             int *tsrc, int *tdst, int *top) {
-    int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= b1) return;
-    tsrc[b - b0] = (int)b;
-    tdst[b - b0] = box_parent[b];
-    top[b - b0] = (int)(box_key[b] & 7);
+// mode 0: count the M2L pairs of every (target box, parent-neighbour slot);
+// mode 1: write them. One thread per (box, slot), so a level's boxes give 27
+// times as many threads; the pairs come out ordered by box, then slot.
+// Mode 1 also counts the tasks of every operator (hist, kNumM2LOps bins,
+// counted per workgroup in LDS first).
+__global__ void __launch_bounds__(256) k_m2l_pairs(int mode, int64_t b0, int64_t b1, LevelInfo li,
+                                                   const uint64_t *box_key, const int *box_level,
+                                                   const int *box_parent, const int *nbr, int *count,
+                                                   const int *offs, int *tsrc, int *tdst, int *top, int *hist) {
+    __shared__ int lh[kNumM2LOps];
+    if (mode == 1) {
+        for (int o = threadIdx.x; o < kNumM2LOps; o += blockDim.x) lh[o] = 0;
+        __syncthreads();
+    }
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < (b1 - b0) * 27) m2l_pairs_one(mode, t, b0, li, box_key, box_level, box_parent, nbr, count, offs, tsrc,
+                                          tdst, top, lh);
+    if (mode == 1) {
+        __syncthreads();
+        for (int o = threadIdx.x; o < kNumM2LOps; o += blockDim.x)
+            if (lh[o]) atomicAdd(&hist[o], lh[o]);
+    }
 }
 
-// Tasks per operator: counted in LDS per workgroup (nops ints of dynamic
-// shared memory), then one global atomic per (workgroup, non-empty bin).
-__global__ void __launch_bounds__(1024) k_op_hist(const int *top, int64_t n, int nops, int *hist) {
-    extern __shared__ int lh[];
-    for (int o = threadIdx.x; o < nops; o += blockDim.x) lh[o] = 0;
+// Tasks of the M2M/L2L lists of every child level 3..lmax in one pass over
+// the boxes b0..b1 of those levels (level by level): child box b <-> its
+// parent, operator = the child's octant; hist[8 (level - 3) + octant] counts
+// the tasks of every (level, operator), per workgroup in LDS first.
+__global__ void __launch_bounds__(256) k_tree_pairs(int64_t b0, int64_t b1, const uint64_t *box_key,
+                                                    const int *box_level, const int *box_parent, int nlev,
+                                                    int *tsrc, int *tdst, int *top, int *hist) {
+    __shared__ int lh[8 * kKeyBits];
+    for (int o = threadIdx.x; o < 8 * nlev; o += blockDim.x) lh[o] = 0;
     __syncthreads();
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&lh[top[i]], 1);
+    const int64_t b = b0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b < b1) {
+        const int op = (int)(box_key[b] & 7);
+        tsrc[b - b0] = (int)b;
+        tdst[b - b0] = box_parent[b];
+        top[b - b0] = op;
+        atomicAdd(&lh[8 * (box_level[b] - 3) + op], 1);
+    }
     __syncthreads();
-    for (int o = threadIdx.x; o < nops; o += blockDim.x)
+    for (int o = threadIdx.x; o < 8 * nlev; o += blockDim.x)
         if (lh[o]) atomicAdd(&hist[o], lh[o]);
+}
+
+// op_off = exclusive prefix of the per-operator task counts (one workgroup,
+// 256 operators at a time); op_off[nops] = the task count.
+__global__ void __launch_bounds__(256) k_hist_offsets(const int *hist, int nops, int *op_off) {
+    __shared__ int s[256];
+    const int tid = threadIdx.x;
+    int carry = 0;
+    for (int base = 0; base < nops; base += 256) {
+        const int o = base + tid;
+        const int v = (o < nops) ? hist[o] : 0;
+        s[tid] = v;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int t = (tid >= d) ? s[tid - d] : 0;
+            __syncthreads();
+            s[tid] += t;
+            __syncthreads();
+        }
+        if (o < nops) op_off[o] = carry + s[tid] - v;
+        carry += s[255];
+        __syncthreads();
+    }
+    if (tid == 0) op_off[nops] = carry;
 }
 
 // Group by operator keeping the input order within each group: one block
@@ -684,9 +761,12 @@ __global__ void k_op_gather(const int *order, const int *src, const int *dst, in
 
 // Group tasks by operator, keeping the input order within each group: a
 // per-operator scan for a few operators, a stable radix sort on the operator
-// index for many.
-static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst, const int *top,
-                        int64_t n, Tree::Scratch &scr, hipStream_t st, bool keep_positions = false) {
+// index for many. The per-operator task counts were formed with the tasks:
+// hist_d on the device, hist_h its host copy.
+static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst, const int *top, int64_t n,
+                        const int *hist_d, const int *hist_h, Tree::Scratch &scr, hipStream_t st,
+                        bool keep_positions = false) {
+    BFM_CHECK(nops <= 8192, BFM_EINVAL, "too many translation operators");
     tl.nops = nops;
     tl.ntasks = n;
     tl.op_off_h.assign(nops + 1, 0);
@@ -695,22 +775,10 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
         tl.ntiles[c] = 0;
         tl.tiles_ready[c] = false;
     }
-    DevBuf<int> &hist = scr.hist;
-    hist.ensure(nops);
-    k_fill_int<<<nblk(nops, 256), 256, 0, st>>>(hist.get(), nops, 0);
+    for (int o = 0; o < nops; ++o) tl.op_off_h[o + 1] = tl.op_off_h[o] + hist_h[o];
+    BFM_CHECK(tl.op_off_h[nops] == n, BFM_EDEVICE, "translation task counts disagree");
+    k_hist_offsets<<<1, 256, 0, st>>>(hist_d, nops, tl.op_off.get());
     BFM_LAUNCHED();
-    if (n > 0) {
-        BFM_CHECK(nops <= 8192, BFM_EINVAL, "too many translation operators");
-        const unsigned nb = (unsigned)std::min<int64_t>(64, (n + 1023) / 1024);
-        k_op_hist<<<nb, 1024, sizeof(int) * nops, st>>>(top, n, nops, hist.get());
-        BFM_LAUNCHED();
-    }
-    std::vector<int> h(nops);
-    BFM_HIP(hipMemcpyAsync(h.data(), hist.get(), sizeof(int) * nops, hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipStreamSynchronize(st));
-    for (int o = 0; o < nops; ++o) tl.op_off_h[o + 1] = tl.op_off_h[o] + h[o];
-    BFM_HIP(hipMemcpyAsync(tl.op_off.get(), tl.op_off_h.data(), sizeof(int) * (nops + 1),
-                           hipMemcpyHostToDevice, st));
     tl.src.ensure(n > 0 ? n : 1);
     tl.dst.ensure(n > 0 ? n : 1);
     if (n > 0 && nops <= 16) {
@@ -805,44 +873,57 @@ __global__ void k_sort_geom(const double *s, const double *nrm, const int *perm,
 }
 
 
+// Host round trips. The build waits for its stream twice: once for the
+// level counts (the depth and the box counts size everything after them;
+// the bounding cube comes back with them) and once for the sizes of the
+// work lists (near-field pair count, largest leaf, item counts, M2L task
+// count and the per-operator task counts of every translation list). The
+// M2L and M2M/L2L tasks are written before that wait into buffers sized by
+// the per-box bounds (at most 216 M2L candidates per box, one M2M task per
+// child box). A depth beyond the first sort's ten levels costs a third wait.
+namespace {
+// layout of the pinned host block the two waits read into
+struct HostSizes {
+    unsigned long long cnt[kKeyBits + 1];  // boxes per level
+    double geo[8];                         // cube (k_bbox_final)
+    unsigned long long npairs;             // near-field pairs
+    int mo[5];                             // largest leaf, split flag, three item counts
+    int m2l_total;
+    int hist[kNumM2LOps + 8 * kKeyBits];   // tasks per operator: M2L, then M2M levels 3..lmax
+};
+}  // namespace
+
+static HostSizes *host_sizes(Tree::Scratch &scr) {
+    if (!scr.host) {
+        void *p = nullptr;
+        BFM_HIP(hipHostMalloc(&p, sizeof(HostSizes), hipHostMallocDefault));
+        scr.host = p;
+    }
+    return static_cast<HostSizes *>(scr.host);
+}
+
 void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target, hipStream_t st) {
     BFM_CHECK(n >= 1, BFM_EINVAL, "tree of no points");
     t.valid = false;
     t.n = n;
-    // bounding cube
+    Tree::Scratch &scr = t.scratch;
+    HostSizes *hs = host_sizes(scr);
+    // device block: [0, 6 nbb) partial boxes, then the cube (8 doubles)
     const int nbb = 256;
-    DevBuf<double> &part = t.scratch.bbox;
-    part.ensure(6 * nbb);
-    k_bbox_partial<<<nbb, 256, 0, st>>>(xyz, n, part.get());
+    double *part = scr.bbox.ensure(6 * nbb + 8);
+    double *geo = part + 6 * nbb;
+    k_bbox_partial<<<nbb, 256, 0, st>>>(xyz, n, part);
     BFM_LAUNCHED();
-    std::vector<double> ph(6 * nbb);
-    BFM_HIP(hipMemcpyAsync(ph.data(), part.get(), sizeof(double) * 6 * nbb, hipMemcpyDeviceToHost, st));
-    BFM_HIP(hipStreamSynchronize(st));
-    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-    for (int b = 0; b < nbb; ++b)
-        for (int d = 0; d < 3; ++d) {
-            mn[d] = std::min(mn[d], ph[6 * b + d]);
-            mx[d] = std::max(mx[d], ph[6 * b + 3 + d]);
-        }
-    double ext = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        BFM_CHECK(std::isfinite(mn[d]) && std::isfinite(mx[d]), BFM_EMESH, "non-finite vertex coordinate");
-        ext = std::max(ext, mx[d] - mn[d]);
-    }
-    if (!(ext > 0.0)) ext = 1.0;
-    t.side = ext * (1.0 + 1e-9) + 1e-300;
-    for (int d = 0; d < 3; ++d) t.origin[d] = 0.5 * (mn[d] + mx[d]) - 0.5 * t.side;
-    const double inv_cell = (double)(1 << kKeyBits) / t.side;
+    k_bbox_final<<<1, 256, 0, st>>>(part, nbb, geo);
+    BFM_LAUNCHED();
 
     // keys + sort
     t.key_a.ensure(n);
     t.key_b.ensure(n);
     t.idx_a.ensure(n);
     t.idx_b.ensure(n);
-    k_morton<<<nblk(n, 256), 256, 0, st>>>(xyz, n, t.origin[0], t.origin[1], t.origin[2], inv_cell,
-                                           t.key_a.get(), t.idx_a.get());
+    k_morton<<<nblk(n, 256), 256, 0, st>>>(xyz, n, geo, t.key_a.get(), t.idx_a.get());
     BFM_LAUNCHED();
-    Tree::Scratch &scr = t.scratch;
     // Sort by the keys' top 30 bits first (levels 1..10: four 8-bit passes
     // instead of six). The boxes of every level <= 10 are then contiguous,
     // which is all an octree of depth <= 10 needs (points inside a level-10
@@ -853,17 +934,17 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     int sorted_levels = kSortedLevels;
     DevBuf<int> &tmp = scr.tmp;
 
-    // boxes per level (exact for the sorted levels)
+    // boxes per level (exact for the sorted levels), read back with the cube
     DevBuf<unsigned long long> &cnt = scr.cnt;
     cnt.ensure(kKeyBits + 1);
-    std::vector<unsigned long long> ch(kKeyBits + 1);
+    const unsigned long long *ch = hs->cnt;
     auto count_levels = [&]() {
         k_fill_u64<<<1, 64, 0, st>>>(cnt.get(), kKeyBits + 1, 0ull);
         BFM_LAUNCHED();
         k_level_counts<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, kKeyBits, cnt.get());
         BFM_LAUNCHED();
-        BFM_HIP(hipMemcpyAsync(ch.data(), cnt.get(), sizeof(unsigned long long) * (kKeyBits + 1),
-                               hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipMemcpyAsync(hs->cnt, cnt.get(), sizeof(hs->cnt), hipMemcpyDeviceToHost, st));
+        BFM_HIP(hipMemcpyAsync(hs->geo, geo, sizeof(hs->geo), hipMemcpyDeviceToHost, st));
         BFM_HIP(hipStreamSynchronize(st));
     };
     // the requested depth, else the deepest sorted level whose mean leaf
@@ -876,6 +957,9 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
         return d;
     };
     count_levels();
+    BFM_CHECK(hs->geo[5] == 1.0, BFM_EMESH, "non-finite vertex coordinate");
+    for (int d = 0; d < 3; ++d) t.origin[d] = hs->geo[d];
+    t.side = hs->geo[3];
     int lmax = pick();
     if (lmax > kSortedLevels || (lmax_req <= 0 && lmax == kSortedLevels)) {
         // a deeper octree is asked for, or the occupancy rule may go deeper
@@ -901,39 +985,33 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     t.box_centre.ensure(3 * t.nbox);
     t.nbr.ensure(27 * t.nbox);
     DevBuf<int> &flag = scr.flag, &pos = scr.pos;
-    flag.ensure(n);
-    pos.ensure(n);
-    for (int l = 0; l <= lmax; ++l) {
-        const int shift = 3 * (kKeyBits - l);
-        k_level_flags<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, shift, flag.get());
-        BFM_LAUNCHED();
-        exclusive_scan_async(flag.get(), pos.get(), n, st, tmp);  // the level's box count is known
-        k_level_scatter<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, shift, flag.get(), pos.get(),
-                                                      t.lvl_off[l], l, t.box_key.get(),
-                                                      t.box_level.get(), t.box_pt0.get());
-        BFM_LAUNCHED();
-        if (l == lmax) {
-            t.pt_leaf.ensure(n);
-            k_pt_leaf<<<nblk(n, 256), 256, 0, st>>>(flag.get(), pos.get(), n, t.pt_leaf.get());
-            BFM_LAUNCHED();
-        }
-    }
+    const int64_t nflag = (int64_t)(lmax + 1) * n;
+    BFM_CHECK(nflag < ((int64_t)1 << 31), BFM_EINVAL, "too many points for the octree depth");
+    flag.ensure(nflag);
+    pos.ensure(nflag);
+    t.pt_leaf.ensure(n);
+    k_level_flags<<<nblk(nflag, 256), 256, 0, st>>>(t.key_a.get(), n, lmax, flag.get());
+    BFM_LAUNCHED();
+    exclusive_scan_async(flag.get(), pos.get(), nflag, st, tmp);
+    k_level_scatter<<<nblk(nflag, 256), 256, 0, st>>>(t.key_a.get(), n, lmax, flag.get(), pos.get(), t.lvl_off[lmax],
+                                                      t.box_key.get(), t.box_level.get(), t.box_pt0.get(),
+                                                      t.pt_leaf.get());
+    BFM_LAUNCHED();
     k_box_meta<<<nblk(27 * t.nbox, 256), 256, 0, st>>>(t.nbox, lmax, li, t.origin[0], t.origin[1],
                                                        t.origin[2], t.box_key.get(), t.box_level.get(),
                                                        t.box_parent.get(), t.box_centre.get(), t.nbr.get());
     BFM_LAUNCHED();
-    // leaves: point ranges, near-field pair count and ranges, and the work
-    // item lists of P2M/L2P, the one-sided and the symmetric near field; the
-    // sizes the host needs (pair count, largest leaf, item counts) come back
-    // together after one wait
+    // leaves: point ranges, near-field pair count and ranges, and the counts
+    // of the work item lists of P2M/L2P, the one-sided and the symmetric near
+    // field
     t.leaf_pt.ensure(t.nleaf + 1);
     DevBuf<unsigned long long> &np = scr.np;
     np.ensure(1);
     DevBuf<int> &mo = scr.mo;
-    mo.ensure(5);  // largest leaf, some leaf's sources split, three item counts
+    mo.ensure(6);  // largest leaf, some leaf's sources split, three item counts, M2L task count
     k_fill_u64<<<1, 64, 0, st>>>(np.get(), 1, 0ull);
     BFM_LAUNCHED();
-    k_fill_int<<<1, 64, 0, st>>>(mo.get(), 5, 0);
+    k_fill_int<<<1, 64, 0, st>>>(mo.get(), 6, 0);
     BFM_LAUNCHED();
     k_leaf_near<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.box_pt0.get(), n,
                                                     t.nbr.get(), t.leaf_pt.get(), np.get(), mo.get());
@@ -943,41 +1021,102 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     k_leaf_ranges<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.leaf_pt.get(), t.nbr.get(),
                                                       t.near_rng.get(), t.near_cnt.get());
     BFM_LAUNCHED();
+    // counts and offsets: leaf items (icnt, ioff), one-sided near-field
+    // pieces (flag, pos; free after the levels, n >= nleaf entries) and
+    // symmetric items (lcnt, loff)
+    DevBuf<int> &icnt = scr.icnt, &ioff = scr.ioff, &lcnt = scr.lcnt, &loff = scr.loff;
+    icnt.ensure(t.nleaf);
+    ioff.ensure(t.nleaf);
+    lcnt.ensure(t.nleaf);
+    loff.ensure(t.nleaf);
+    int *pcnt = flag.get(), *poff = pos.get();
+    k_item_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), icnt.get());
+    BFM_LAUNCHED();
+    k_piece_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(),
+                                                     pcnt, mo.get() + 1);
+    BFM_LAUNCHED();
+    k_sym_items<false><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
+                                                           t.near_cnt.get(), lcnt.get(), nullptr, nullptr);
+    BFM_LAUNCHED();
+    exclusive_scan_async(icnt.get(), ioff.get(), t.nleaf, st, tmp);
+    exclusive_scan_async(pcnt, poff, t.nleaf, st, tmp);
+    exclusive_scan_async(lcnt.get(), loff.get(), t.nleaf, st, tmp);
+    k_scan_totals3<<<1, 64, 0, st>>>(icnt.get(), ioff.get(), pcnt, poff, lcnt.get(), loff.get(), t.nleaf,
+                                     mo.get() + 2);
+    BFM_LAUNCHED();
+
+    // M2L tasks over levels 2..lmax, and the per-operator counts
     {
-        // counts and offsets: leaf items (icnt, ioff), one-sided near-field
-        // pieces (flag, pos; free after the levels, n >= nleaf entries) and
-        // symmetric items (count, offs)
-        DevBuf<int> &icnt = scr.icnt, &ioff = scr.ioff, &ccnt = scr.count, &coff = scr.offs;
-        icnt.ensure(t.nleaf);
-        ioff.ensure(t.nleaf);
-        // (count and offs later hold the M2L pair counts: sized for both now)
-        const int64_t ncw = std::max<int64_t>(t.nleaf, 27 * (t.lvl_off[lmax + 1] - t.lvl_off[2]));
-        ccnt.ensure(ncw);
-        coff.ensure(ncw);
-        int *pcnt = flag.get(), *poff = pos.get();
-        k_item_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), icnt.get());
+        static int lut_done = 0;  // one bit per device ordinal < 32
+        int dev = 0;
+        BFM_HIP(hipGetDevice(&dev));
+        if (dev >= 32 || !((lut_done >> dev) & 1)) {
+            signed short lut[343];
+            for (int a = -3; a <= 3; ++a)
+                for (int b = -3; b <= 3; ++b)
+                    for (int c = -3; c <= 3; ++c)
+                        lut[(a + 3) * 49 + (b + 3) * 7 + (c + 3)] = (signed short)m2l_op_index(a, b, c);
+            BFM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_m2l_lut), lut, sizeof(lut)));
+            if (dev < 32) lut_done |= 1 << dev;
+        }
+    }
+    const int nlev = std::max(0, lmax - 2);  // M2M/L2L child levels 3..lmax
+    const int nhist = kNumM2LOps + 8 * nlev;
+    int *hist = scr.hist.ensure(nhist);
+    k_fill_int<<<nblk(nhist, 256), 256, 0, st>>>(hist, nhist, 0);
+    BFM_LAUNCHED();
+    const int64_t mb0 = t.lvl_off[2], mb1 = t.lvl_off[lmax + 1];
+    const int64_t mnb = mb1 - mb0;
+    DevBuf<int> &count = scr.count, &offs = scr.offs;
+    count.ensure(27 * mnb);
+    offs.ensure(27 * mnb);
+    k_m2l_pairs<<<nblk(27 * mnb, 256), 256, 0, st>>>(0, mb0, mb1, li, t.box_key.get(), t.box_level.get(),
+                                                    t.box_parent.get(), t.nbr.get(), count.get(), nullptr, nullptr,
+                                                    nullptr, nullptr, nullptr);
+    BFM_LAUNCHED();
+    {
+        int64_t slot = 0;
+        int *sc = scan_scratch(27 * mnb, tmp, &slot);
+        int *dtotal = mo.get() + 5;
+        k_scan_last<<<1, 64, 0, st>>>(count.get(), 27 * mnb, dtotal);
         BFM_LAUNCHED();
-        k_piece_count<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                         t.near_cnt.get(), pcnt, mo.get() + 1);
+        scan_rec(count.get(), offs.get(), 27 * mnb, st, sc);
+        k_scan_total<<<1, 64, 0, st>>>(offs.get(), 27 * mnb, dtotal);
         BFM_LAUNCHED();
-        k_sym_items<false><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                               t.near_cnt.get(), ccnt.get(), nullptr, nullptr);
+    }
+    const int64_t m2l_cap = 216 * mnb;  // 27 parent neighbours x 8 children per box
+    DevBuf<int> &ts = scr.ts, &td = scr.td, &to = scr.to;
+    ts.ensure(m2l_cap + 1);
+    td.ensure(m2l_cap + 1);
+    to.ensure(m2l_cap + 1);
+    k_m2l_pairs<<<nblk(27 * mnb, 256), 256, 0, st>>>(1, mb0, mb1, li, t.box_key.get(), t.box_level.get(),
+                                                    t.box_parent.get(), t.nbr.get(), count.get(), offs.get(),
+                                                    ts.get(), td.get(), to.get(), hist);
+    BFM_LAUNCHED();
+    // M2M/L2L tasks of child levels 3..lmax
+    const int64_t cb0 = t.lvl_off[std::min(3, lmax + 1)], cb1 = t.lvl_off[lmax + 1];
+    DevBuf<int> &cs = scr.cs, &cd = scr.cd, &co = scr.co;
+    cs.ensure(cb1 - cb0 + 1);
+    cd.ensure(cb1 - cb0 + 1);
+    co.ensure(cb1 - cb0 + 1);
+    if (cb1 > cb0) {
+        k_tree_pairs<<<nblk(cb1 - cb0, 256), 256, 0, st>>>(cb0, cb1, t.box_key.get(), t.box_level.get(),
+                                                          t.box_parent.get(), nlev, cs.get(), cd.get(), co.get(),
+                                                          hist + kNumM2LOps);
         BFM_LAUNCHED();
-        exclusive_scan_async(icnt.get(), ioff.get(), t.nleaf, st, tmp);
-        exclusive_scan_async(pcnt, poff, t.nleaf, st, tmp);
-        exclusive_scan_async(ccnt.get(), coff.get(), t.nleaf, st, tmp);
-        k_scan_totals3<<<1, 64, 0, st>>>(icnt.get(), ioff.get(), pcnt, poff, ccnt.get(), coff.get(), t.nleaf,
-                                         mo.get() + 2);
-        BFM_LAUNCHED();
-        unsigned long long npairs = 0;
-        int hm[5] = {0, 0, 0, 0, 0};
-        BFM_HIP(hipMemcpyAsync(&npairs, np.get(), sizeof(npairs), hipMemcpyDeviceToHost, st));
-        BFM_HIP(hipMemcpyAsync(hm, mo.get(), sizeof(hm), hipMemcpyDeviceToHost, st));
-        BFM_HIP(hipStreamSynchronize(st));
-        t.npairs_near = (int64_t)npairs;
-        t.max_leaf = hm[0];
-        t.near_split = hm[1] != 0;
-        const int64_t ni = hm[2], nn = hm[3], ns = hm[4];
+    }
+
+    // the second wait: every size the rest needs
+    BFM_HIP(hipMemcpyAsync(&hs->npairs, np.get(), sizeof(hs->npairs), hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipMemcpyAsync(hs->mo, mo.get(), sizeof(int) * 6, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipMemcpyAsync(hs->hist, hist, sizeof(int) * nhist, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    t.npairs_near = (int64_t)hs->npairs;
+    t.max_leaf = hs->mo[0];
+    t.near_split = hs->mo[1] != 0;
+    const int64_t ni = hs->mo[2], nn = hs->mo[3], ns = hs->mo[4], total = hs->mo[5];
+    BFM_CHECK(total >= 0 && total <= m2l_cap, BFM_EDEVICE, "M2L task count out of range");
+    {
         // leaf chunks of at most kLeafChunk points (P2M, L2P)
         t.leaf_items.ensure(ni > 0 ? ni : 1);
         k_item_fill<<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), ioff.get(), t.leaf_items.get());
@@ -993,52 +1132,17 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
         // symmetric near-field items
         t.sym_items.ensure(ns > 0 ? ns : 1);
         k_sym_items<true><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                              t.near_cnt.get(), nullptr, coff.get(), t.sym_items.get());
+                                                              t.near_cnt.get(), nullptr, loff.get(), t.sym_items.get());
         BFM_LAUNCHED();
         t.n_sym_items = ns;
     }
-
-    // M2L lists over levels 2..lmax
-    {
-        {
-            static int lut_done = 0;  // one bit per device ordinal < 32
-            int dev = 0;
-            BFM_HIP(hipGetDevice(&dev));
-            if (dev >= 32 || !((lut_done >> dev) & 1)) {
-                signed short lut[343];
-                for (int a = -3; a <= 3; ++a)
-                    for (int b = -3; b <= 3; ++b)
-                        for (int c = -3; c <= 3; ++c)
-                            lut[(a + 3) * 49 + (b + 3) * 7 + (c + 3)] = (signed short)m2l_op_index(a, b, c);
-                BFM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_m2l_lut), lut, sizeof(lut)));
-                if (dev < 32) lut_done |= 1 << dev;
-            }
-        }
-        const int64_t b0 = t.lvl_off[2], b1 = t.lvl_off[lmax + 1];
-        const int64_t nb = b1 - b0;
-        DevBuf<int> &count = scr.count, &offs = scr.offs;
-        count.ensure(27 * nb);
-        offs.ensure(27 * nb);
-        k_m2l_pairs<<<nblk(27 * nb, 256), 256, 0, st>>>(0, b0, b1, li, t.box_key.get(), t.box_level.get(),
-                                                       t.box_parent.get(), t.nbr.get(), count.get(),
-                                                       nullptr, nullptr, nullptr, nullptr);
-        BFM_LAUNCHED();
-        const int64_t total = exclusive_scan(count.get(), offs.get(), 27 * nb, st, tmp);
-        DevBuf<int> &ts = scr.ts, &td = scr.td, &to = scr.to;
-        ts.ensure(total + 1);
-        td.ensure(total + 1);
-        to.ensure(total + 1);
-        k_m2l_pairs<<<nblk(27 * nb, 256), 256, 0, st>>>(1, b0, b1, li, t.box_key.get(), t.box_level.get(),
-                                                       t.box_parent.get(), t.nbr.get(), count.get(),
-                                                       offs.get(), ts.get(), td.get(), to.get());
-        BFM_LAUNCHED();
-        group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, scr, st, true);
-        t.m2l.dst_box0 = b0;
-        t.m2l.dst_nbox = nb;
-        t.m2l.dst_off.ensure(nb + 1);
-        k_dst_off<<<nblk(nb + 1, 256), 256, 0, st>>>(offs.get(), nb, total, t.m2l.dst_off.get());
-        BFM_LAUNCHED();
-    }
+    // M2L lists grouped by operator
+    group_tasks(t.m2l, kNumM2LOps, ts.get(), td.get(), to.get(), total, hist, hs->hist, scr, st, true);
+    t.m2l.dst_box0 = mb0;
+    t.m2l.dst_nbox = mnb;
+    t.m2l.dst_off.ensure(mnb + 1);
+    k_dst_off<<<nblk(mnb + 1, 256), 256, 0, st>>>(offs.get(), mnb, total, t.m2l.dst_off.get());
+    BFM_LAUNCHED();
     // M2M / L2L lists: child levels 3..lmax (index l)
     // task lists are reused between builds (their buffers only grow)
     for (size_t l = lmax + 1; l < t.m2m.size(); ++l) {
@@ -1047,17 +1151,10 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     }
     t.m2m.resize(lmax + 1, nullptr);
     for (int l = 3; l <= lmax; ++l) {
-        const int64_t b0 = t.lvl_off[l], b1 = t.lvl_off[l + 1];
-        const int64_t nb = b1 - b0;
-        DevBuf<int> &ts = scr.ts, &td = scr.td, &to = scr.to;
-        ts.ensure(nb);
-        td.ensure(nb);
-        to.ensure(nb);
-        k_tree_pairs<<<nblk(nb, 128), 128, 0, st>>>(b0, b1, t.box_key.get(), t.box_parent.get(),
-                                                    ts.get(), td.get(), to.get());
-        BFM_LAUNCHED();
+        const int64_t o = t.lvl_off[l] - cb0, nb = t.lvl_off[l + 1] - t.lvl_off[l];
+        const int hk = kNumM2LOps + 8 * (l - 3);
         if (!t.m2m[l]) t.m2m[l] = new TaskList();
-        group_tasks(*t.m2m[l], 8, ts.get(), td.get(), to.get(), nb, scr, st);
+        group_tasks(*t.m2m[l], 8, cs.get() + o, cd.get() + o, co.get() + o, nb, hist + hk, hs->hist + hk, scr, st);
     }
     // sorted positions
     t.iperm.ensure(n);
@@ -1067,8 +1164,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     k_sort_points<<<nblk(n, 256), 256, 0, st>>>(xyz, t.idx_a.get(), n, t.px.get(), t.py.get(),
                                                 t.pz.get(), t.iperm.get());
     BFM_LAUNCHED();
-    BFM_HIP(hipStreamSynchronize(st));
-    t.valid = true;
+    t.valid = true;  // (the work above stays in flight: later launches are stream-ordered)
 }
 
 void sort_geometry(Tree &t, const double *s, const double *nrm, hipStream_t st) {

@@ -371,7 +371,7 @@ def test_two_level_solve_after_a_failed_solve(c100):
     q2, i2 = fresh.solve(phi)
     assert i1["converged"] and i2["converged"]
     assert i1["iterations"] == i2["iterations"] and rel(q1, q2) < 1e-10, (i1, i2, rel(q1, q2))
-    # later builds replay the coarse build's recorded launches on new positions
+    # later builds on new positions
     for scale in (1.02, 0.97):
         xyz = cl.xyz * scale
         two.set_positions(xyz)
