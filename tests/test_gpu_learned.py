@@ -190,11 +190,15 @@ def test_errors_without_template_or_training(tiny):
 
 def test_training_on_gpu_gives_a_useful_guess():
     """Train on solved states of a 30-bubble cluster, then solve an unseen
-    state from the learned guess: same solution, no more iterations, and a
-    guess closer to q than the zero guess. (The features see only a
-    bubble's own shape and potential and its neighbours' positions, not the
-    potentials of the other bubbles, so the collective part of q is left to
-    GMRES.)"""
+    state from the learned guess: the same solution, a guess whose error is
+    at most half the zero guess's (measured: 0.40), and fewer GMRES
+    iterations (measured: 70 or 71 against 72, runs differing in the order
+    of the training's atomic reductions). The gain is small: the features
+    see only a bubble's own shape and potential and its neighbours'
+    positions, not the potentials of the other bubbles, so the collective
+    part of q is left to GMRES. On the time-stepped 1000-bubble cluster the
+    network's guess saves 0.3 iterations per solve, less than it costs, and
+    the previous step's q saves 2.4."""
     import torch
     nb, side = 30, 28.0
     sv = bfm.Solver(gmres_tol=1e-10)
@@ -223,6 +227,5 @@ def test_training_on_gpu_gives_a_useful_guess():
           f"loss {l_first:.3e} -> {l_last:.3e}; guess {i1['t_guess_ms']:.3f} ms")
     assert i1["converged"] and i1["t_guess_ms"] > 0
     assert np.linalg.norm(q1 - q0) / np.linalg.norm(q0) < 1e-8
-    # closer than the zero guess, and never costs iterations
-    assert err < 0.7
-    assert i1["iterations"] <= i0["iterations"]
+    assert err < 0.5
+    assert i1["iterations"] < i0["iterations"]
