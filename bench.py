@@ -33,7 +33,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and FP64 matrix (dense)
 # to the value it was measured with.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c1000.txt")
 KERNEL_SOURCES = {"p2p": ("fmm_near.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h"),
-                  "m2l": ("fmm.hip", "fmm.h", "common.h"),
+                  "m2l": ("fmm.hip", "fmm_rot.hip", "fmm.h", "common.h"),
                   "leaf": ("fmm_leaf.hip", "fmm_kernels.h", "fmm.h", "tree.h", "common.h")}
 
 
@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--p-lo", type=int, default=None, help="order of the low-precision products (autotuned if unset)")
     ap.add_argument("--leaf", type=int, default=None)
     ap.add_argument("--lmax", type=int, default=None)
-    ap.add_argument("--m2l-shape", type=int, default=None, help="M2L launch shape 0..2 (-1: by size)")
+    ap.add_argument("--m2l-shape", type=int, default=None, help="M2L launch shape 0..2 (dense), 3 (rotation-factored); -1: by size")
     ap.add_argument("--tol", type=float, default=None, help="GMRES tolerance of the tuned form")
     ap.add_argument("--plain-tol", type=float, default=None,
                     help="GMRES tolerance of the plain form (unpreconditioned GMRES needs 1e-8 to bring "
@@ -122,6 +122,9 @@ def m2l_kernel_name(p, shape, orders=0):
     orders_p = [p] if not orders else [p, 4 * ((p + 4) // 5), 4 * ((3 * p + 19) // 20)]
     names = []
     for po in orders_p:
+        if shape == 3:  # rotation-factored: applied order, stored order
+            names.append(f"bfm::k_m2l_rot<{po}, {p}>")
+            continue
         pp = po * po
         rows, waves = rows_of(pp)
         names.append(f"bfm::k_translate<{pp}, {rows}, {waves}, 0, double, {ld}>")
@@ -266,8 +269,11 @@ def roofline_entry(cls, prof, prof_steps, stats, opt, p_diag, nv, workload):
         bound, tcls = "mfma", "m2l"
         nch = 5 if group == "diag_" else 1
         # every operator read once, every box's multipole read and local
-        # expansion written once
-        alg_bytes = unit_bytes * (316 * pp * pp + 2 * stats["boxes"] * pp * nch)
+        # expansion written once (rotation-factored operators: two rotations
+        # of sum (2n+1)^2 and a translation along the axis of sum (p-m)^2)
+        shape_used = stats["diag_m2l_shape" if group else "m2l_shape"] if not lo_prec else -1
+        op_words = (2 * p * (4 * p * p - 1) // 3 + p * (p + 1) * (2 * p + 1) // 6) if shape_used == 3 else pp * pp
+        alg_bytes = unit_bytes * (316 * op_words + 2 * stats["boxes"] * pp * nch)
     elif kind == "p2p":
         kname = p2p_kernel_name(group)
         bound, tcls = "alu", "p2p"

@@ -117,7 +117,11 @@ typedef struct bfm_options {
     int use_graph;     /* != 0: GMRES replays each product (preconditioner + fast multipole
                           product) from one captured HIP graph per octree */
     int m2l_shape;     /* M2L launch shape: -1 = by size, 0 = wide tiles, 1 = row slabs,
-                          2 = narrow slabs (set by bfm_autotune) */
+                          2 = narrow slabs (dense p^2 x p^2 operators), 3 = rotation-factored
+                          M2L (rotate the multipole to the offset's axis, translate along it,
+                          rotate back: 4 p^3 instead of 2 p^4 flops per translation, FP64
+                          products only; the diagonal/right-hand-side pass follows it); set
+                          by bfm_autotune */
     int m2l_orders;    /* 0: every M2L translation at the product's order p (Section 3.9);
                           1: offsets d = (c_target - c_source)/h (box sides) translated at
                           orders falling with |d|: p for |d|^2 <= 5, 4 ceil(p/5) for 6..10,
@@ -296,7 +300,7 @@ int bfm_autotune(bfm_ctx *ctx, double mvp_tol, bfm_tune_result *out);
 /* Octree statistics of the current mesh (builds the tree if needed), the
  * first n of: stats[0] = lmax, [1] = leaves, [2] = boxes (all levels),
  * [3] = near-field pairs, [4] = M2L pairs, [5] = M2M+L2L pairs, [6] = max
- * points per leaf, [7] = launch shape (0, 1, 2 as bfm_options.m2l_shape) of
+ * points per leaf, [7] = launch shape (0..3 as bfm_options.m2l_shape) of
  * the last M2L launch of an FP64 GMRES product, [8] = the same for the
  * diagonal/right-hand-side pass (-1 before the first launch); entries past
  * BFM_TREE_STATS are set to 0. stats is a host array of n entries. */

@@ -18,11 +18,20 @@ extern "C" {
  * kind 0: multipole-to-multipole, child octant `index` (0..7) -> parent
  * kind 1: local-to-local, parent -> child octant `index` (0..7)
  * kind 2: multipole-to-local, offset operator `index` (0..315)
+ * kind 3: the same operator factored by rotation, T = B T_z A: out receives
+ *   A (for every degree n < p a row-major (2n+1) x (2n+1) block, blocks in
+ *   order of n; p (4 p^2 - 1) / 3 doubles), then T_z (for every order
+ *   m < p a row-major (p-m) x (p-m) block over degrees m..p-1, applied
+ *   alike to the cosine and sine parts of the order; p (p+1)(2p+1) / 6
+ *   doubles), then B (as A): A rotates the multipole coefficients to a
+ *   frame whose z axis points along d, T_z translates along that axis, B
+ *   rotates the local coefficients back.
  * Octant o: child box integer coordinates have low bits (o>>2 & 1, o>>1 & 1,
  * o & 1). Offset operator k: the k-th (dx, dy, dz) of [-3,3]^3 excluding
  * [-1,1]^3, ordered by dx^2 + dy^2 + dz^2 and then lexicographically,
  * meaning c_target - c_source = d * h.
- * out: host, p^2 * p^2 doubles, row-major (out[row * p^2 + col]).
+ * out: host, p^2 * p^2 doubles, row-major (out[row * p^2 + col]) for
+ * kinds 0..2.
  * d_out (may be NULL): for kind 2 receives the offset (dx, dy, dz).
  * Returns 0, or -1 (BFM_EINVAL) on a bad p, kind or index.
  */

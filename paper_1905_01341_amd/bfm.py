@@ -230,6 +230,27 @@ def debug_operator(p: int, kind: int, index: int):
     return out, d
 
 
+def debug_m2l_rotation(p: int, index: int):
+    """Rotation-factored M2L operator `index` at order p (include/bfm_debug.h,
+    kind 3): (A blocks per degree, T_z blocks per order, B blocks per
+    degree), each a list of square arrays, and the offset d."""
+    nr = p * (4 * p * p - 1) // 3
+    nz = p * (p + 1) * (2 * p + 1) // 6
+    out = np.empty(2 * nr + nz)
+    d = np.zeros(3, dtype=np.int32)
+    _check(load().bfm_debug_operator(p, 3, index, _ptr(out), _ptr(d)))
+
+    def blocks(v, sizes):
+        res, o = [], 0
+        for s in sizes:
+            res.append(v[o:o + s * s].reshape(s, s).copy())
+            o += s * s
+        return res
+    rot = [2 * n + 1 for n in range(p)]
+    return (blocks(out[:nr], rot), blocks(out[nr:nr + nz], [p - m for m in range(p)]),
+            blocks(out[nr + nz:], rot), d)
+
+
 def debug_dgemm(A, B, device=0):
     """C = A B on the device with the library's FP64 MFMA GEMM (test hook)."""
     A = np.asfortranarray(A, dtype=np.float64)

@@ -58,7 +58,7 @@ static void check_options(const bfm_options &o) {
     BFM_CHECK(o.precond == BFM_PRECOND_NONE || o.precond == BFM_PRECOND_SH || o.precond == BFM_PRECOND_SH_COARSE,
               BFM_EINVAL, "unknown precond");
     BFM_CHECK(o.precond_degree >= 1 && o.precond_degree <= 40, BFM_EINVAL, "precond_degree must be in [1, 40]");
-    BFM_CHECK(o.m2l_shape >= -1 && o.m2l_shape <= 2, BFM_EINVAL, "m2l_shape must be -1, 0, 1 or 2");
+    BFM_CHECK(o.m2l_shape >= -1 && o.m2l_shape <= 3, BFM_EINVAL, "m2l_shape must be -1, 0, 1, 2 or 3");
     BFM_CHECK(o.m2l_orders == 0 || o.m2l_orders == 1, BFM_EINVAL, "m2l_orders must be 0 or 1");
 }
 

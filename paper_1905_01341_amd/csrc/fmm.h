@@ -42,7 +42,11 @@ struct FmmWork {
     DevBuf<uint16_t> opb_m2m[2], opb_l2l[2], opb_m2l[2];
     int ops_p = 0;
     int ops_prec = -1;
-    int m2l_shape = -1;    // M2L launch shape (-1: chosen by size)
+    // rotation-factored M2L operators (FP64, kernel operand order, fmm_rot.hip):
+    // per operator the degree blocks of A, the order blocks of T_z, those of B
+    DevBuf<double> rot_a, rot_z, rot_b;
+    int rot_p = 0;
+    int m2l_shape = -1;    // M2L launch shape (-1: chosen by size; 3: rotation-factored, FP64)
     int m2l_orders = 0;    // 1: distant offset classes translated at reduced orders (ops.h)
     int m2l_shape_used = -1;  // shape of the last M2L launch (-1: none yet)
     // optional second stream for the near field (default priority): the

@@ -21,6 +21,7 @@
 #include <hip/hip_bf16.h>
 
 #include <cmath>
+#include <type_traits>
 #include <cstring>
 #include <vector>
 
@@ -614,6 +615,47 @@ static void launch_translate(int shape, bool m2l, int op0, int nops, int g0, int
     BFM_LAUNCHED();
 }
 
+// Rotation-factored M2L (fmm_rot.hip) over a whole interaction list, by
+// distance class when the product reduces distant orders. Flops counted:
+// 2 (2 sum_{n<q} (2n+1)^2 + sum_{|m|<q} (q-|m|)^2) per column at order q.
+template <int P_>
+static void translate_rot(FmmWork &w, TaskList &tl, int nch, const double *in, double *out, hipStream_t st) {
+    rot_ops_upload(w, P_, st);
+    prepare_tiles(tl, nch, 16, st);
+    const int nt = tl.ntiles_for(nch, 16);
+    if (nt <= 0) return;
+    const int pi = prof_begin(w, KC_M2L, st);
+    const int *to = tl.tile_for(nch, 16);
+    auto col_flops = [](int q) {
+        double f = 2.0 * q * (4.0 * q * q - 1.0) / 3.0;  // the two rotations
+        for (int m = -(q - 1); m < q; ++m) f += (double)(q - std::abs(m)) * (q - std::abs(m));
+        return 2.0 * f;
+    };
+    double flops = 0.0;
+    if (w.m2l_orders) {
+        constexpr int P1 = m2l_class_order(P_, 1), P2 = m2l_class_order(P_, 2);
+        int first[kM2LClasses + 1];
+        for (int c = 0; c <= kM2LClasses; ++c) first[c] = m2l_class_first_op(c);
+        for (int c = 0; c < kM2LClasses; ++c) {
+            const int g0 = tiles_before(tl, nch, 16, first[c]);
+            const int g1 = tiles_before(tl, nch, 16, first[c + 1]);
+            const int64_t nk = tl.op_off_h[first[c + 1]] - tl.op_off_h[first[c]];
+            flops += col_flops(m2l_class_order(P_, c)) * (double)nk * nch;
+            const int nops = first[c + 1] - first[c];
+            if (c == 0)
+                launch_m2l_rot<P_, P_>(w, first[c], nops, g0, g1 - g0, to, tl, nch, in, out, st);
+            else if (c == 1)
+                launch_m2l_rot<P1, P_>(w, first[c], nops, g0, g1 - g0, to, tl, nch, in, out, st);
+            else
+                launch_m2l_rot<P2, P_>(w, first[c], nops, g0, g1 - g0, to, tl, nch, in, out, st);
+        }
+    } else {
+        flops = col_flops(P_) * (double)tl.ntasks * nch;
+        launch_m2l_rot<P_, P_>(w, 0, tl.nops, 0, nt, to, tl, nch, in, out, st);
+    }
+    prof_end(w, pi, st, flops);
+}
+
 template <int P_, class R = double>
 static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, const R *T, const R *in, R *out,
                       hipStream_t st) {
@@ -625,7 +667,13 @@ static void translate(FmmWork &w, int cls, TaskList &tl, int nch, bool swap, con
     // twice the LDS per workgroup) only on request.
     const int64_t wave_tiles = (cols + 15) / 16;
     int shape = (wave_tiles * (PP / mid_rows(PP)) >= 512) ? 1 : 2;
-    if (cls == KC_M2L && w.m2l_shape >= 0) shape = w.m2l_shape;
+    if (cls == KC_M2L && w.m2l_shape >= 0 && w.m2l_shape <= 2) shape = w.m2l_shape;
+    if constexpr (std::is_same<R, double>::value) {
+        if (cls == KC_M2L && w.m2l_shape == 3) {
+            w.m2l_shape_used = 3;
+            return translate_rot<P_>(w, tl, nch, in, out, st);
+        }
+    }
     if (cls == KC_M2L) w.m2l_shape_used = shape;
     const int width = (shape == 0) ? 128 : 64;
     prepare_tiles(tl, nch, width, st);

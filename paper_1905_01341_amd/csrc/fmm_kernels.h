@@ -33,6 +33,15 @@ void launch_p2p32(const Tree &t, const Sources &src, double *y, hipStream_t st);
 // y[c][i] = near-field sum of the five packed channels (Sources::packed).
 void launch_p2p_packed(const Tree &t, const double *packed, double *y, hipStream_t st);
 
+// Rotation-factored M2L (fmm_rot.hip): operators of order p uploaded to w
+// (no-op if current); the translation of operators op0 .. op0 + nops - 1 at
+// order PO of expansions stored at order PS, tiles g0 .. g0 + ntiles - 1 of
+// the 16-column tile prefix tile_off, added into out.
+void rot_ops_upload(FmmWork &w, int p, hipStream_t st);
+template <int PO, int PS>
+void launch_m2l_rot(const FmmWork &w, int op0, int nops, int g0, int ntiles, const int *tile_off,
+                    const TaskList &tl, int nch, const double *in, double *out, hipStream_t st);
+
 // y[c][i] = sum over every other point (all pairs).
 template <int NCH, bool MONO, bool DIP>
 void launch_direct(const Tree &t, const Sources &src, double *y, hipStream_t st);

@@ -215,16 +215,186 @@ static_assert(m2l_class_order(16, 1) == 16 && m2l_class_order(16, 2) == 12 && m2
                   m2l_class_order(4, 1) == 4 && m2l_class_order(4, 2) == 4,
               "class orders");
 
-void build_m2l(int p, int op, double *T) {
-    int d[3];
-    m2l_op_offset(op, d);
+// M2L for any real offset d (box units).
+static void build_m2l_at(int p, const double d[3], double *T) {
     std::vector<cplx> I;
-    harmonics(true, 2 * p - 1, (double)d[0], (double)d[1], (double)d[2], I);
+    harmonics(true, 2 * p - 1, d[0], d[1], d[2], I);
     auto G = [&](int j, int k, int n, int m) -> cplx {
         const int sgn = ((j + k) & 1) ? -1 : 1;
         return (double)sgn * at(I, n + j, m - k) * nu(n + j, m - k) / (nu(j, k) * nu(n, m));
     };
     fill_real(p, G, T);
+}
+
+void build_m2l(int p, int op, double *T) {
+    int d[3];
+    m2l_op_offset(op, d);
+    const double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+    build_m2l_at(p, dd, T);
+}
+
+// ---------------------------------------------------------------------------
+// Rotation-factored M2L: T(d) = B T(|d| z) A. A rotation Q with Q d = |d| z
+// turns the source's multipole coefficients into those of the rotated
+// configuration (A, block diagonal by degree: a rotation keeps the degree),
+// the translation along z couples only equal orders (T_z, one real block
+// per order m shared by the cosine and sine parts), and B takes the local
+// coefficients of the rotated frame back (block diagonal by degree).
+// Per degree n the blocks follow from the harmonics at points of the unit
+// sphere: a multipole of a unit source at y has packed coefficients
+// a(y) = (R_n^0, Re R_n^m, -Im R_n^m, ...)(y) (the conjugates of the regular
+// harmonics), so A a(y) = a(Q y); a local expansion is evaluated against
+// e(x) = (R_n^0, 2 Re R_n^m, -2 Im R_n^m, ...)(x), and with e(Q x) = W e(x)
+// the original frame's coefficients are B L' = W^T L'. The packed parts are
+// mutually orthogonal on the sphere, so with a product rule exact for
+// degree 2n (Gauss-Legendre in cos(theta) x uniform in phi) each block is a
+// sum over the rule's nodes divided by a diagonal Gram matrix: no linear
+// solve.
+
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) {
+                p1 = z;
+                p0 = 1.0;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                double q0 = 1.0, q1 = z;
+                for (int k = 2; k <= n; ++k) {
+                    const double q2 = ((2.0 * k - 1.0) * z * q1 - (k - 1.0) * q0) / k;
+                    q0 = q1;
+                    q1 = q2;
+                }
+                const double dq = n * (z * q1 - q0) / (z * z - 1.0);
+                x[i] = z;
+                w[i] = 2.0 / ((1.0 - z * z) * dq * dq);
+                break;
+            }
+        }
+    }
+}
+
+// A rotation (row-major 3 x 3) taking the unit vector u to +z.
+static void rotation_to_z(const double u[3], double Q[9]) {
+    const double c = u[2];
+    const double kx = u[1], ky = -u[0];  // u x z
+    const double sn = std::sqrt(kx * kx + ky * ky);
+    if (sn < 1e-15) {
+        const double sg = c > 0.0 ? 1.0 : -1.0;  // identity, or a half turn about x
+        const double Z[9] = {1, 0, 0, 0, sg, 0, 0, 0, sg};
+        for (int i = 0; i < 9; ++i) Q[i] = Z[i];
+        return;
+    }
+    const double ax = kx / sn, ay = ky / sn;  // axis (ax, ay, 0), angle theta: cos = c, sin = sn
+    const double t = 1.0 - c;
+    Q[0] = c + ax * ax * t;
+    Q[1] = ax * ay * t;
+    Q[2] = ay * sn;
+    Q[3] = ax * ay * t;
+    Q[4] = c + ay * ay * t;
+    Q[5] = -ax * sn;
+    Q[6] = -ay * sn;
+    Q[7] = ax * sn;
+    Q[8] = c;
+}
+
+int m2l_rot_offset(int n) { return n * (4 * n * n - 1) / 3; }
+int m2l_tz_offset(int p, int m) {
+    int o = 0;
+    for (int q = 0; q < m; ++q) o += (p - q) * (p - q);
+    return o;
+}
+
+// Packed part c (0: order 0; 2m - 1, 2m: the two parts of order m) of the
+// multipole-type (conjugate, unit weights) or local-type (weights 2, minus
+// sign on the sine part) vector of degree n.
+static double packed_part(const std::vector<cplx> &R, int n, int c, bool local) {
+    if (c == 0) return R[tri_index(n, 0)].real();
+    const int m = (c + 1) / 2;
+    const cplx v = R[tri_index(n, m)];
+    const double f = local ? 2.0 : 1.0;
+    return (c & 1) ? f * v.real() : -f * v.imag();
+}
+
+void build_m2l_rot(int p, int op, double *A, double *Tz, double *B) {
+    int di[3];
+    m2l_op_offset(op, di);
+    const double len = std::sqrt((double)(di[0] * di[0] + di[1] * di[1] + di[2] * di[2]));
+    const double u[3] = {di[0] / len, di[1] / len, di[2] / len};
+    double Q[9];
+    rotation_to_z(u, Q);
+    // product rule exact for degree 2 (p - 1)
+    std::vector<double> gx, gw;
+    gauss_legendre(p, gx, gw);
+    const int nphi = 2 * p;
+    const int K = p * nphi;
+    std::vector<std::vector<cplx>> Hx(K), Hq(K);
+    std::vector<double> wk(K);
+    for (int a = 0; a < p; ++a)
+        for (int b = 0; b < nphi; ++b) {
+            const int k = a * nphi + b;
+            const double z = gx[a], r = std::sqrt(std::max(0.0, 1.0 - z * z)), ph = 2.0 * M_PI * b / nphi;
+            const double x[3] = {r * std::cos(ph), r * std::sin(ph), z};
+            const double q[3] = {Q[0] * x[0] + Q[1] * x[1] + Q[2] * x[2], Q[3] * x[0] + Q[4] * x[1] + Q[5] * x[2],
+                                 Q[6] * x[0] + Q[7] * x[1] + Q[8] * x[2]};
+            harmonics(false, p, x[0], x[1], x[2], Hx[k]);
+            harmonics(false, p, q[0], q[1], q[2], Hq[k]);
+            wk[k] = gw[a] * (2.0 * M_PI / nphi);
+        }
+    for (int n = 0; n < p; ++n) {
+        const int sz = 2 * n + 1;
+        double *An = A + m2l_rot_offset(n), *Bn = B + m2l_rot_offset(n);
+        std::vector<double> ga(sz, 0.0), ge(sz, 0.0);
+        for (int i = 0; i < sz * sz; ++i) An[i] = Bn[i] = 0.0;
+        std::vector<double> ax(sz), aq(sz), ex(sz), eq(sz);
+        for (int k = 0; k < K; ++k) {
+            for (int c = 0; c < sz; ++c) {
+                ax[c] = packed_part(Hx[k], n, c, false);
+                aq[c] = packed_part(Hq[k], n, c, false);
+                ex[c] = packed_part(Hx[k], n, c, true);
+                eq[c] = packed_part(Hq[k], n, c, true);
+            }
+            for (int c = 0; c < sz; ++c) {
+                ga[c] += wk[k] * ax[c] * ax[c];
+                ge[c] += wk[k] * ex[c] * ex[c];
+                for (int c2 = 0; c2 < sz; ++c2) {
+                    An[c * sz + c2] += wk[k] * aq[c] * ax[c2];  // sum w a(Qx) a(x)^T
+                    Bn[c2 * sz + c] += wk[k] * eq[c] * ex[c2];  // (sum w e(Qx) e(x)^T)^T
+                }
+            }
+        }
+        for (int c = 0; c < sz; ++c)
+            for (int c2 = 0; c2 < sz; ++c2) {
+                An[c * sz + c2] /= ga[c2];
+                Bn[c2 * sz + c] /= ge[c2];
+            }
+    }
+    // translation along +z by |d|
+    const int P = p * p;
+    std::vector<double> Tfull((size_t)P * P);
+    const double dz[3] = {0.0, 0.0, len};
+    build_m2l_at(p, dz, Tfull.data());
+    for (int m = 0; m < p; ++m) {
+        double *Tm = Tz + m2l_tz_offset(p, m);
+        const int w = p - m;
+        for (int j = m; j < p; ++j)
+            for (int n = m; n < p; ++n) {
+                const int row = m == 0 ? j * j : j * j + 2 * m - 1, col = m == 0 ? n * n : n * n + 2 * m - 1;
+                Tm[(j - m) * w + (n - m)] = Tfull[(size_t)row * P + col];
+            }
+    }
 }
 
 }  // namespace bfm
@@ -242,6 +412,13 @@ extern "C" int bfm_debug_operator(int p, int kind, int index, double *out, int *
     if (kind == 2) {
         if (index < 0 || index >= bfm::kNumM2LOps) return BFM_EINVAL;
         bfm::build_m2l(p, index, out);
+        if (d_out) bfm::m2l_op_offset(index, d_out);
+        return BFM_OK;
+    }
+    if (kind == 3) {  // the rotation-factored M2L: A, then T_z, then B, concatenated
+        if (index < 0 || index >= bfm::kNumM2LOps) return BFM_EINVAL;
+        const int nr = bfm::m2l_rot_offset(p), nz = bfm::m2l_tz_offset(p, p);
+        bfm::build_m2l_rot(p, index, out, out + nr, out + nr + nz);
         if (d_out) bfm::m2l_op_offset(index, d_out);
         return BFM_OK;
     }

@@ -30,5 +30,15 @@ constexpr int m2l_class_order(int p, int cls) {
 }
 constexpr int kM2LClasses = 3;
 void build_m2l(int p, int op, double *T);
+// Rotation-factored M2L of operator op: T = B T_z A (see ops.cpp). A and B:
+// one row-major (2n+1) x (2n+1) block per degree n < p at m2l_rot_offset(n)
+// (m2l_rot_offset(p) doubles in all); T_z: one row-major (p-m) x (p-m)
+// block per order m < p (rows j = m..p-1, columns n = m..p-1) at
+// m2l_tz_offset(p, m) (m2l_tz_offset(p, p) in all), applied alike to the
+// two parts of an order m > 0. Within a degree the packed parts are ordered
+// as in the expansions: order 0, then (2m - 1, 2m) for order m.
+int m2l_rot_offset(int n);
+int m2l_tz_offset(int p, int m);
+void build_m2l_rot(int p, int op, double *A, double *Tz, double *B);
 
 }  // namespace bfm

@@ -134,6 +134,7 @@ void ensure_ops(bfm_ctx *c) {
     fmm_prepare_ops(c->fmm, c->opt.p, c->stream);
     c->fmm_diag.p = diag_order(c->opt);
     c->fmm_diag.m2l_orders = c->opt.m2l_orders;
+    c->fmm_diag.m2l_shape = c->opt.m2l_shape == 3 ? 3 : -1;  // the rotation-factored M2L follows the option
     fmm_prepare_ops(c->fmm_diag, c->fmm_diag.p, c->stream);
 }
 

@@ -32,11 +32,11 @@ struct TaskList {
     std::vector<int> op_off_h;  // host copy [nops + 1]
     DevBuf<int> op_off;         // [nops + 1]
     DevBuf<int> src, dst;       // [ntasks]
-    // workgroup-tile prefix per (channel count, tile width), built lazily:
-    // slot = nch * 2 + (width == 128)
-    DevBuf<int> tile_off[16];
-    int ntiles[16] = {0};
-    bool tiles_ready[16] = {false};
+    // workgroup-tile prefix per (channel count, tile width 64, 128 or 16),
+    // built lazily: slot = nch * 3 + (0, 1, 2 by width)
+    DevBuf<int> tile_off[24];
+    int ntiles[24] = {0};
+    bool tiles_ready[24] = {false};
     // M2L lists only: the tasks of each target box, for a reduction of
     // per-task results: target box dst_box0 + k owns the tasks at grouped
     // positions pos_of[dst_off[k]] .. pos_of[dst_off[k + 1] - 1] (in the
@@ -44,7 +44,7 @@ struct TaskList {
     DevBuf<int> pos_of;   // [ntasks] generation index -> grouped position
     DevBuf<int> dst_off;  // [dst_nbox + 1]
     int64_t dst_box0 = 0, dst_nbox = 0;
-    static int slot(int nch, int width) { return nch * 2 + (width == 128 ? 1 : 0); }
+    static int slot(int nch, int width) { return nch * 3 + (width == 128 ? 1 : (width == 16 ? 2 : 0)); }
     int ntiles_for(int nch, int width) const { return ntiles[slot(nch, width)]; }
     const int *tile_for(int nch, int width) const { return tile_off[slot(nch, width)].get(); }
 };

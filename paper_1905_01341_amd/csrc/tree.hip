@@ -771,7 +771,7 @@ static void group_tasks(TaskList &tl, int nops, const int *tsrc, const int *tdst
     tl.ntasks = n;
     tl.op_off_h.assign(nops + 1, 0);
     tl.op_off.ensure(nops + 1);
-    for (int c = 0; c < 16; ++c) {
+    for (int c = 0; c < 24; ++c) {
         tl.ntiles[c] = 0;
         tl.tiles_ready[c] = false;
     }
@@ -830,7 +830,8 @@ __global__ void __launch_bounds__(256) k_tile_off(const int *op_off, int nops, i
 }
 
 void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st) {
-    BFM_CHECK(nch >= 1 && nch < 8 && (width == 64 || width == 128), BFM_EINVAL, "tile shape out of range");
+    BFM_CHECK(nch >= 1 && nch < 8 && (width == 64 || width == 128 || width == 16), BFM_EINVAL,
+              "tile shape out of range");
     const int sl = TaskList::slot(nch, width);
     if (tl.tiles_ready[sl]) return;
     // the tile count (the grid size) from the host copy of the operator

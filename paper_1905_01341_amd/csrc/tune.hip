@@ -210,7 +210,7 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
             (void)hipEventDestroy(b);
             double lvl_ms = 1e300;
             int lvl_s = -1;
-            for (int shape = 0; shape <= 2; ++shape) {
+            for (int shape = 0; shape <= 3; ++shape) {  // 3: the rotation-factored M2L
                 c->opt.m2l_shape = shape;
                 ensure_ops(c);
                 const double ms = time_mvp(c, x.get(), y.get(), 5);

@@ -217,3 +217,47 @@ def test_m2l_offset_enumeration():
     assert sum(v <= 5 for v in d2) == 30 and sum(6 <= v <= 10 for v in d2) == 90
     with pytest.raises(bfm.BfmError):
         bfm.debug_operator(4, 2, 316)
+
+
+def _rot_dense(p, A, Tz, B):
+    """B T_z A assembled as dense p^2 x p^2 matrices (packed layout)."""
+    P = p * p
+    Ad, Bd, Td = np.zeros((P, P)), np.zeros((P, P)), np.zeros((P, P))
+    for n in range(p):
+        sl = slice(n * n, (n + 1) * (n + 1))
+        Ad[sl, sl], Bd[sl, sl] = A[n], B[n]
+    for m in range(p):
+        for part in ((0,) if m == 0 else (0, 1)):
+            idx = [j * j + (0 if m == 0 else 2 * m - 1 + part) for j in range(m, p)]
+            Td[np.ix_(idx, idx)] = Tz[m]
+    return Bd @ Td @ Ad
+
+
+@pytest.mark.parametrize("p", [4, 8, 16, 20])
+def test_m2l_rotation_factorisation(p):
+    """T(d) = B T_z(|d|) A for the rotation-factored M2L: rotations block
+    diagonal by degree, the translation along the axis coupling equal orders
+    only, the product equal to the dense operator (itself checked against
+    independent addition-theorem code above) to 1e-12 of every output
+    degree's block of rows. (Single rows can be far smaller than their
+    degree's block - the order-m rows of a distant operator fall like
+    1/sqrt((2m)!) - and a rotation's rounding mixes the block's rows, so a
+    row's own relative error can be large while its absolute error stays at
+    the block's rounding level.)"""
+    ops = range(316) if p <= 16 else range(0, 316, 9)
+    worst = 0.0
+    for op in ops:
+        T, d = bfm.debug_operator(p, 2, op)
+        A, Tz, B, d2 = bfm.debug_m2l_rotation(p, op)
+        assert tuple(d2) == tuple(d)
+        R = _rot_dense(p, A, Tz, B)
+        for j in range(p):
+            sl = slice(j * j, (j + 1) * (j + 1))
+            worst = max(worst, float(np.linalg.norm(R[sl] - T[sl]) / np.linalg.norm(T[sl])))
+    assert worst < 1e-12, worst
+    # a rotation preserves the degree-n quadratic form with weights 1, 2, 2, ...
+    # (the packed parts of orders m > 0 stand for m and -m)
+    A, _, B, _ = bfm.debug_m2l_rotation(p, 100)
+    for n in (1, p // 2, p - 1):
+        w = np.array([1.0] + [2.0] * (2 * n))
+        assert np.allclose(A[n].T @ np.diag(w) @ A[n], np.diag(w), atol=1e-12)
