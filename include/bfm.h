@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BFM_ABI_VERSION 4
+#define BFM_ABI_VERSION 5
 
 enum {
     BFM_OK = 0,
@@ -129,6 +129,10 @@ typedef struct bfm_options {
                           p = 16) - the truncation error of a translation falls
                           geometrically with |d|, so distant offsets reach the nearest
                           ones' accuracy at lower order. Applies to every product */
+    int p2p_shape;     /* work items of the symmetric one-channel near field (receivers per
+                          chunk, sources per piece of the chunk's own block, per piece of the
+                          rest): -1 or 0 = (256, 128, 192), 1 = (128, 128, 128), 2 = (256, 128,
+                          384); set by bfm_autotune */
 } bfm_options;
 
 typedef struct bfm_solve_info {
@@ -281,19 +285,28 @@ int bfm_direct_dev_noalloc(int64_t n, const double *xyz, const double *s, const 
  * mvp_tol (relative 2-norm) of the p = 20 product (p = 20 if none); with
  * iterative refinement (precision FP32 or BF16X3) also p_lo = the smallest
  * of 8, 12, 16 whose low-precision product is within ir_tol of that
- * reference; then the octree depth (the depth chosen from leaf_target and
- * one level either side) that minimises one diagonal/right-hand-side pass
- * plus the products of a typical solve (ten FP64 products, or two FP64 and
- * eight low-precision ones), and the M2L launch shape with the fastest
- * product at that depth, timed with HIP events after a warm-up. The choice
- * is stored in the handle's options (p, p_lo, lmax, m2l_shape; p_diag is
- * left as set). out may be NULL. */
+ * reference; when p_diag is 0, p_diag = the smallest of 12, 16 (not below
+ * p) whose diagonal pass is within 10 mvp_tol of the pass at order 20 (L_ii
+ * in relative 2-norm, M_ii in largest difference over 1/2), else 20; then
+ * the octree depth (the depth chosen from leaf_target and two levels
+ * either side) that minimises one diagonal/right-hand-side pass plus the
+ * products of a typical solve (ten FP64 products, or two FP64 and eight
+ * low-precision ones), and the M2L launch shape (dense shapes 0..2 and the
+ * rotation-factored 3) with the fastest product at that depth, and the
+ * near-field work item shape (p2p_shape 0..2) with the fastest near field
+ * of the products GMRES runs most (the low-precision ones under
+ * refinement), timed with HIP events after a warm-up. The choice is stored
+ * in the handle's options (p, p_lo, p_diag, lmax, m2l_shape, p2p_shape).
+ * out may be NULL. */
 typedef struct bfm_tune_result {
     int p, lmax, m2l_shape; /* chosen */
     int candidates;         /* configurations timed */
     double mvp_ms;          /* time of one FP64 product with the chosen configuration */
     double p_err;           /* relative difference of the chosen p's product from p = 20 */
     int p_lo;               /* chosen order of the low-precision products (0 without refinement) */
+    int p_diag;             /* order of the diagonal/right-hand-side pass (as set, or chosen) */
+    double diag_err;        /* the chosen p_diag's difference from order 20 (0 if 20 or set) */
+    int p2p_shape;          /* chosen near-field work item shape (bfm_options.p2p_shape) */
 } bfm_tune_result;
 int bfm_autotune(bfm_ctx *ctx, double mvp_tol, bfm_tune_result *out);
 

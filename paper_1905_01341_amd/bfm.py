@@ -25,7 +25,7 @@ PRECOND_SH_COARSE = 2
 GUESS_ZERO = 0
 GUESS_GIVEN = 1
 GUESS_LEARNED = 2
-ABI_VERSION = 4
+ABI_VERSION = 5
 MLP_INPUTS = 174
 MLP_OUTPUTS = 81
 MLP_NUM_PARAMS = 656465
@@ -64,6 +64,9 @@ class TuneResult(ctypes.Structure):
         ("mvp_ms", ctypes.c_double),
         ("p_err", ctypes.c_double),
         ("p_lo", ctypes.c_int),
+        ("p_diag", ctypes.c_int),
+        ("diag_err", ctypes.c_double),
+        ("p2p_shape", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -103,6 +106,7 @@ class Options(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("m2l_shape", ctypes.c_int),
         ("m2l_orders", ctypes.c_int),
+        ("p2p_shape", ctypes.c_int),
     ]
 
 
@@ -418,6 +422,8 @@ class Solver:
         r = TuneResult()
         _check(self.lib.bfm_autotune(self.h, float(mvp_tol), ctypes.byref(r)))
         self.opt.p, self.opt.lmax, self.opt.m2l_shape = r.p, r.lmax, r.m2l_shape
+        self.opt.p_diag = r.p_diag
+        self.opt.p2p_shape = r.p2p_shape
         if r.p_lo:
             self.opt.p_lo = r.p_lo
         return r.as_dict()

@@ -60,6 +60,7 @@ static void check_options(const bfm_options &o) {
     BFM_CHECK(o.precond_degree >= 1 && o.precond_degree <= 40, BFM_EINVAL, "precond_degree must be in [1, 40]");
     BFM_CHECK(o.m2l_shape >= -1 && o.m2l_shape <= 3, BFM_EINVAL, "m2l_shape must be -1, 0, 1, 2 or 3");
     BFM_CHECK(o.m2l_orders == 0 || o.m2l_orders == 1, BFM_EINVAL, "m2l_orders must be 0 or 1");
+    BFM_CHECK(o.p2p_shape >= -1 && o.p2p_shape < kSymShapeCount, BFM_EINVAL, "p2p_shape must be -1, 0, 1 or 2");
 }
 
 struct DeviceScope {
@@ -190,6 +191,7 @@ int bfm_default_options(bfm_options *opt) {
     opt->precond_degree = 12;
     opt->use_graph = 0;
     opt->m2l_shape = -1;
+    opt->p2p_shape = -1;
     return BFM_OK;
 }
 
@@ -280,7 +282,8 @@ int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
         BFM_CHECK(c && opt, BFM_EINVAL, "null argument");
         check_options(*opt);
         BFM_CHECK(opt->device == c->device, BFM_EINVAL, "cannot change the device of a handle");
-        const bool tree_change = opt->lmax != c->opt.lmax || opt->leaf_target != c->opt.leaf_target;
+        const bool tree_change = opt->lmax != c->opt.lmax || opt->leaf_target != c->opt.leaf_target ||
+                                 opt->p2p_shape != c->opt.p2p_shape;
         const bool p_change =
             opt->p != c->opt.p || opt->p_diag != c->opt.p_diag || opt->m2l_orders != c->opt.m2l_orders;
         // (p_lo and precision take effect at the next low-precision product)

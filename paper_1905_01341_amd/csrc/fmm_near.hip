@@ -390,7 +390,7 @@ __device__ inline void p2p_sym_item(int leaf, int r0, int r1, int s0, int s1, co
     const double scale = -0.5;  // the sums hold -2 / r
     if (s1 <= r1 - r0) {
         // the chunk's own points, in blocks of 64 aligned with the receiver
-        // groups (pieces start at multiples of kSymDiagPiece)
+        // groups (pieces of the own block start at multiples of 64)
         for (int base = s0; base < s1; base += kP2PThreads) {
             const int j = r0 + base + lane;
             const bool ok = base + lane < s1;
@@ -441,16 +441,16 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_sym(const int4 *__restrict_
                                                          const double *__restrict__ px,
                                                          const double *__restrict__ py,
                                                          const double *__restrict__ pz, int64_t n,
-                                                         const double *__restrict__ q, double *__restrict__ y) {
+                                                         const double *__restrict__ q, int chunk,
+                                                         double *__restrict__ y) {
     static_assert(kSymChunk == 4 * kP2PThreads, "at most four receivers per lane");
-    static_assert(kSymDiagPiece % kP2PThreads == 0, "diagonal pieces start at receiver-group bounds");
     __shared__ double2 sxy[kP2PThreads], szq[kP2PThreads];
     __shared__ double sacc[kP2PThreads];
     const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
     const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
     const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
     const int leaf = it.x, r0 = it.y, s0 = it.z, s1 = it.w;
-    const int r1 = min(r0 + kSymChunk, leaf_pt[leaf + 1]);
+    const int r1 = min(r0 + chunk, leaf_pt[leaf + 1]);
     switch ((r1 - r0 + kP2PThreads - 1) / kP2PThreads) {
         case 1:
             p2p_sym_item<1>(leaf, r0, r1, s0, s1, near_rng, near_cnt, px, py, pz, n, q, y, sxy, szq, sacc);
@@ -579,14 +579,15 @@ __global__ void __launch_bounds__(kP2PThreads) k_p2p_sym32(const int4 *__restric
                                                            const double *__restrict__ px,
                                                            const double *__restrict__ py,
                                                            const double *__restrict__ pz,
-                                                           const double *__restrict__ q, double *__restrict__ y) {
+                                                           const double *__restrict__ q, int chunk,
+                                                           double *__restrict__ y) {
     __shared__ float4 src[kP2PThreads];
     __shared__ double sacc[kP2PThreads];
     const int nblock = gridDim.x, per = nblock / kXcdCount, rem = nblock % kXcdCount;
     const int xcd = blockIdx.x % kXcdCount, idx = blockIdx.x / kXcdCount;
     const int4 it = items[xcd * per + (xcd < rem ? xcd : rem) + idx];
     const int leaf = it.x, r0 = it.y, s0 = it.z, s1 = it.w;
-    const int r1 = min(r0 + kSymChunk, leaf_pt[leaf + 1]);
+    const int r1 = min(r0 + chunk, leaf_pt[leaf + 1]);
     const double *c = centre + 3 * (leaf0 + leaf);
     const double ox = c[0], oy = c[1], oz = c[2];
     switch ((r1 - r0 + kP2PThreads - 1) / kP2PThreads) {
@@ -744,7 +745,8 @@ void launch_p2p(const Tree &t, const Sources &src, double *y, hipStream_t st) {
         BFM_LAUNCHED();
         k_p2p_sym<<<(unsigned)t.n_sym_items, kP2PThreads, 0, st>>>(t.sym_items.get(), t.leaf_pt.get(),
                                                                    t.near_rng.get(), t.near_cnt.get(), t.px.get(),
-                                                                   t.py.get(), t.pz.get(), t.n, src.q, y);
+                                                                   t.py.get(), t.pz.get(), t.n, src.q, t.sym_chunk,
+                                                                   y);
         BFM_LAUNCHED();
         return;
     }
@@ -791,7 +793,7 @@ void launch_p2p32(const Tree &t, const Sources &src, double *y, hipStream_t st) 
         BFM_LAUNCHED();
         k_p2p_sym32<<<(unsigned)t.n_sym_items, kP2PThreads, 0, st>>>(
             t.sym_items.get(), t.leaf_pt.get(), t.near_rng.get(), t.near_cnt.get(), t.box_centre.get(), leaf0,
-            t.px.get(), t.py.get(), t.pz.get(), src.q, y);
+            t.px.get(), t.py.get(), t.pz.get(), src.q, t.sym_chunk, y);
         BFM_LAUNCHED();
         return;
     }

@@ -111,7 +111,8 @@ void ensure_tree(bfm_ctx *c) {
         return;
     }
     const int pi = c->prof.begin(KC_TREE, c->stream);
-    build_tree(c->tree, c->xyz.get(), c->nv, c->opt.lmax, c->opt.leaf_target, c->stream);
+    build_tree(c->tree, c->xyz.get(), c->nv, c->opt.lmax, c->opt.leaf_target,
+               c->opt.p2p_shape < 0 ? 0 : c->opt.p2p_shape, c->stream);
     // the build has waited for the stream after the flag's copy (its bounding
     // box is read back first): no extra round trip
     geometry_check(c, true);

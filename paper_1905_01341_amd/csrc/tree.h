@@ -18,9 +18,15 @@ constexpr int kP2PPiece = 384;   // near-field sources per work item at most (a 
 // symmetric near field (one channel of monopoles): receivers per chunk (up
 // to four per lane), and the positions per work item at most in the chunk's
 // diagonal block and in the two-sided rest of its list
-constexpr int kSymChunk = 256;
-constexpr int kSymDiagPiece = 128;
-constexpr int kSymPiece = 192;
+constexpr int kSymChunk = 256;  // receivers per chunk at most (four per lane)
+// work item shapes (bfm_options.p2p_shape): receivers per chunk, positions
+// per piece of the chunk's own block (a multiple of 64: pieces start at
+// receiver-group bounds) and per piece of the rest of its list
+struct SymShape {
+    int chunk, dpiece, piece;
+};
+constexpr int kSymShapeCount = 3;
+constexpr SymShape kSymShapes[kSymShapeCount] = {{256, 128, 192}, {128, 128, 128}, {256, 128, 384}};
 
 // Translation tasks grouped by operator: tasks op_off[o]..op_off[o+1] use
 // operator o; task t moves expansion src[t] into expansion dst[t] (global
@@ -94,6 +100,7 @@ struct Tree {
     // clipped to start at r0 (the chunk itself first), in leaf order
     DevBuf<int4> sym_items;
     int64_t n_sym_items = 0;
+    int sym_shape = 0, sym_chunk = kSymChunk;  // shape the items were built with
 
     // sorted point data (per tree): positions, weights, normals
     DevBuf<double> px, py, pz;  // [n]
@@ -122,7 +129,7 @@ struct Tree {
 // Build (or rebuild) the tree for the points xyz (device, [n][3] AoS).
 // lmax_req > 0 fixes the depth; otherwise the deepest level whose mean leaf
 // occupancy is >= leaf_target is used (at least 2).
-void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target,
+void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target, int sym_shape,
                 hipStream_t st);
 
 // Sorted-order copies of per-vertex geometry (s, n SoA in original order).

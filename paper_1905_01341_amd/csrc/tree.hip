@@ -558,9 +558,10 @@ __global__ void k_piece_fill(int64_t nleaf, const int *leaf_pt, const int *off, 
         for (int p = 0; p < pieces; ++p, ++o) items[o] = make_int4((int)i, r, min(src, p * ps), min(src, (p + 1) * ps));
 }
 
-// Symmetric near-field items: chunk [r0, r1) of leaf i takes its near ranges
-// clipped to start at r0; positions [0, r1 - r0) are the chunk itself (split
-// into pieces of kSymDiagPiece), the rest into pieces of kSymPiece.
+// Symmetric near-field items: chunk [r0, r1) (at most `chunk` receivers) of
+// leaf i takes its near ranges clipped to start at r0; positions [0, r1 - r0)
+// are the chunk itself (split into pieces of dpiece), the rest into pieces of
+// `piece`.
 __device__ inline int sym_list_len(int64_t i, int r0, const int2 *rng, const int *rcnt) {
     int len = 0;
     for (int k = 0; k < rcnt[i]; ++k) len += max(0, rng[27 * i + k].y - max(rng[27 * i + k].x, r0));
@@ -568,19 +569,19 @@ __device__ inline int sym_list_len(int64_t i, int r0, const int2 *rng, const int
 }
 
 template <bool FILL>
-__global__ void k_sym_items(int64_t nleaf, const int *leaf_pt, const int2 *rng, const int *rcnt, int *cnt,
-                            const int *off, int4 *items) {
+__global__ void k_sym_items(int64_t nleaf, const int *leaf_pt, const int2 *rng, const int *rcnt, SymShape sh,
+                            int *cnt, const int *off, int4 *items) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
     const int p0 = leaf_pt[i], p1 = leaf_pt[i + 1];
     int o = FILL ? off[i] : 0;
-    for (int r0 = p0; r0 < p1; r0 += kSymChunk) {
-        const int d = min(r0 + kSymChunk, p1) - r0;
+    for (int r0 = p0; r0 < p1; r0 += sh.chunk) {
+        const int d = min(r0 + sh.chunk, p1) - r0;
         const int len = sym_list_len(i, r0, rng, rcnt);
-        for (int s = 0; s < d; s += kSymDiagPiece, ++o)
-            if (FILL) items[o] = make_int4((int)i, r0, s, min(d, s + kSymDiagPiece));
-        for (int s = d; s < len; s += kSymPiece, ++o)
-            if (FILL) items[o] = make_int4((int)i, r0, s, min(len, s + kSymPiece));
+        for (int s = 0; s < d; s += sh.dpiece, ++o)
+            if (FILL) items[o] = make_int4((int)i, r0, s, min(d, s + sh.dpiece));
+        for (int s = d; s < len; s += sh.piece, ++o)
+            if (FILL) items[o] = make_int4((int)i, r0, s, min(len, s + sh.piece));
     }
     if (!FILL) cnt[i] = o;
 }
@@ -903,10 +904,20 @@ static HostSizes *host_sizes(Tree::Scratch &scr) {
     return static_cast<HostSizes *>(scr.host);
 }
 
-void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target, hipStream_t st) {
+void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_target, int sym_shape,
+                hipStream_t st) {
     BFM_CHECK(n >= 1, BFM_EINVAL, "tree of no points");
+    BFM_CHECK(sym_shape >= 0 && sym_shape < kSymShapeCount, BFM_EINVAL, "near-field item shape out of range");
     t.valid = false;
     t.n = n;
+    const SymShape sh = kSymShapes[sym_shape];
+    static_assert(kSymShapes[0].dpiece % 64 == 0 && kSymShapes[1].dpiece % 64 == 0 && kSymShapes[2].dpiece % 64 == 0,
+                  "pieces of a chunk's own block start at receiver-group bounds");
+    static_assert(kSymShapes[0].chunk <= kSymChunk && kSymShapes[1].chunk <= kSymChunk &&
+                      kSymShapes[2].chunk <= kSymChunk && kSymShapes[1].chunk % 64 == 0,
+                  "at most four receivers per lane");
+    t.sym_shape = sym_shape;
+    t.sym_chunk = sh.chunk;
     Tree::Scratch &scr = t.scratch;
     HostSizes *hs = host_sizes(scr);
     // device block: [0, 6 nbb) partial boxes, then the cube (8 doubles)
@@ -1037,7 +1048,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
                                                      pcnt, mo.get() + 1);
     BFM_LAUNCHED();
     k_sym_items<false><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                           t.near_cnt.get(), lcnt.get(), nullptr, nullptr);
+                                                           t.near_cnt.get(), sh, lcnt.get(), nullptr, nullptr);
     BFM_LAUNCHED();
     exclusive_scan_async(icnt.get(), ioff.get(), t.nleaf, st, tmp);
     exclusive_scan_async(pcnt, poff, t.nleaf, st, tmp);
@@ -1133,7 +1144,8 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
         // symmetric near-field items
         t.sym_items.ensure(ns > 0 ? ns : 1);
         k_sym_items<true><<<nblk(t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.leaf_pt.get(), t.near_rng.get(),
-                                                              t.near_cnt.get(), nullptr, loff.get(), t.sym_items.get());
+                                                              t.near_cnt.get(), sh, nullptr, loff.get(),
+                                                              t.sym_items.get());
         BFM_LAUNCHED();
         t.n_sym_items = ns;
     }

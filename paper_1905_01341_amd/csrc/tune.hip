@@ -102,6 +102,16 @@ static double diff_host(const double *a, const double *b, int64_t n, hipStream_t
     return std::sqrt(s);
 }
 
+static double maxdiff_host(const double *a, const double *b, int64_t n, hipStream_t st) {
+    std::vector<double> ha(n), hb(n);
+    BFM_HIP(hipMemcpyAsync(ha.data(), a, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipMemcpyAsync(hb.data(), b, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    BFM_HIP(hipStreamSynchronize(st));
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) m = std::max(m, std::fabs(ha[i] - hb[i]));
+    return m;
+}
+
 static double time_mvp(bfm_ctx *c, const double *x, double *y, int reps, int prec = BFM_PREC_FP64) {
     hipStream_t st = c->stream;
     matvec_sorted(c, 1.0, x, 0.0, nullptr, y, false, prec, false);  // warm-up
@@ -177,6 +187,46 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
             }
             c->opt.p_lo = best_plo;
         }
+        // 1c. order of the diagonal/right-hand-side pass (when not set): the
+        // smallest of 12, 16 (not below p) whose L_ii and M_ii are within
+        // 10 mvp_tol of the pass at order 20 (L_ii: relative 2-norm; M_ii:
+        // largest difference over 1/2, the size of the sums it comes from).
+        // L_ii is the difference of two sums of the size of a bubble radius
+        // (the translation-free form), so it needs the highest order of all
+        // the pass's outputs; the tolerance is ten times the product's
+        // because the solution carries about half of L_ii's relative error.
+        int best_pd = saved.p_diag;
+        double best_derr = 0.0;
+        if (saved.p_diag <= 0) {
+            best_pd = 20;
+            c->opt.p_diag = 20;
+            c->diag_valid = false;
+            diagonal_pass(c, nullptr);
+            DevBuf<double> lref, mref;
+            lref.ensure(n);
+            mref.ensure(n);
+            BFM_HIP(hipMemcpyAsync(lref.get(), c->lii_s.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            BFM_HIP(hipMemcpyAsync(mref.get(), c->mii_s.get(), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            const double lnorm = norm2_host(lref.get(), n, st);
+            for (int pd : {12, 16}) {
+                if (pd < c->opt.p) continue;
+                c->opt.p_diag = pd;
+                ensure_ops(c);
+                c->diag_valid = false;
+                diagonal_pass(c, nullptr);
+                const double el = diff_host(c->lii_s.get(), lref.get(), n, st) / lnorm;
+                const double em = maxdiff_host(c->mii_s.get(), mref.get(), n, st) / 0.5;
+                const double e = std::max(el, em);
+                if (e <= 10.0 * mvp_tol) {
+                    best_pd = pd;
+                    best_derr = e;
+                    break;
+                }
+            }
+            c->opt.p_diag = best_pd;
+            ensure_ops(c);
+            c->diag_valid = false;
+        }
         // 2. octree depth and M2L launch shape: the depth minimises one
         // diagonal/right-hand-side pass plus the products of a typical solve
         // (ten FP64 products; with refinement two FP64 and eight
@@ -187,7 +237,7 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
         double best_cost = 1e300, best_ms = 1e300;
         int best_l = auto_lmax, best_s = -1, cand = 0;
         bool warm = false;
-        for (int l = std::max(2, auto_lmax - 1); l <= std::min(15, auto_lmax + 1); ++l) {
+        for (int l = std::max(2, auto_lmax - 2); l <= std::min(15, auto_lmax + 2); ++l) {
             c->opt.lmax = l;
             c->opt.m2l_shape = -1;
             c->tree_valid = false;
@@ -230,8 +280,52 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
                 best_s = lvl_s;
             }
         }
+        // 3. near-field work item shape: the symmetric near field of the
+        // products GMRES runs most (the low-precision ones under refinement),
+        // timed alone with the library's kernel timing (which runs the near
+        // field in line) at the chosen depth and M2L shape
+        int best_ps = saved.p2p_shape;
+        if (saved.p2p_shape < 0) {
+            best_ps = 0;
+            if (!c->prof.on) {
+                c->opt.p = best_p;
+                c->opt.lmax = best_l;
+                c->opt.m2l_shape = best_s;
+                const int prec = ir ? saved.precision : BFM_PREC_FP64;
+                const int cls = (ir ? kLoBase : 0) + KC_P2P;
+                double best_near = 1e300;
+                for (int ps = 0; ps < kSymShapeCount; ++ps) {
+                    c->opt.p2p_shape = ps;
+                    c->tree_valid = false;
+                    ensure_tree(c);
+                    ensure_ops(c);
+                    matvec_sorted(c, 1.0, x.get(), 0.0, nullptr, y.get(), false, prec, false);  // warm-up
+                    BFM_HIP(hipStreamSynchronize(st));
+                    c->prof.reset();
+                    c->prof.on = true;
+                    for (int r = 0; r < 3; ++r) matvec_sorted(c, 1.0, x.get(), 0.0, nullptr, y.get(), false, prec, false);
+                    BFM_HIP(hipStreamSynchronize(st));
+                    double ms = 0.0;
+                    for (const auto &rec : c->prof.recs)
+                        if (rec.cls == cls) {
+                            float e = 0.f;
+                            BFM_HIP(hipEventElapsedTime(&e, rec.a, rec.b));
+                            ms += e;
+                        }
+                    c->prof.on = false;
+                    c->prof.reset();
+                    ++cand;
+                    if (ms < best_near) {
+                        best_near = ms;
+                        best_ps = ps;
+                    }
+                }
+            }
+        }
         c->opt = saved;
         c->opt.p = best_p;
+        c->opt.p2p_shape = best_ps;
+        c->opt.p_diag = best_pd;
         c->opt.lmax = best_l;
         c->opt.m2l_shape = best_s;
         if (ir) c->opt.p_lo = best_plo;
@@ -246,6 +340,9 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
             out->candidates = cand;
             out->mvp_ms = best_ms;
             out->p_err = best_err;
+            out->p_diag = best_pd;
+            out->diag_err = best_derr;
+            out->p2p_shape = best_ps;
         }
     } catch (...) {
         c->opt = saved;
