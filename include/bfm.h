@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BFM_ABI_VERSION 5
+#define BFM_ABI_VERSION 6
 
 enum {
     BFM_OK = 0,
@@ -133,6 +133,14 @@ typedef struct bfm_options {
                           chunk, sources per piece of the chunk's own block, per piece of the
                           rest): -1 or 0 = (256, 128, 192), 1 = (128, 128, 128), 2 = (256, 128,
                           384); set by bfm_autotune */
+    int near_corr;     /* != 0: add near-field correction matrices to every product, the
+                          singular diagonals and b (Section 3.9): for each collocation point
+                          i the triangles touching i or its mesh neighbours are integrated
+                          with a conical 8 x 8 Gauss rule (collapsed at the vertex nearest
+                          r_i, exact for the weakly singular self term) and the nodal rule's
+                          share of them is taken out; one sparse row per vertex (about 18
+                          columns on a regular mesh), values rebuilt with the geometry,
+                          pattern with the mesh. 0 = the nodal rule alone */
 } bfm_options;
 
 typedef struct bfm_solve_info {

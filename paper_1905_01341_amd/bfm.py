@@ -25,7 +25,7 @@ PRECOND_SH_COARSE = 2
 GUESS_ZERO = 0
 GUESS_GIVEN = 1
 GUESS_LEARNED = 2
-ABI_VERSION = 5
+ABI_VERSION = 6
 MLP_INPUTS = 174
 MLP_OUTPUTS = 81
 MLP_NUM_PARAMS = 656465
@@ -107,6 +107,7 @@ class Options(ctypes.Structure):
         ("m2l_shape", ctypes.c_int),
         ("m2l_orders", ctypes.c_int),
         ("p2p_shape", ctypes.c_int),
+        ("near_corr", ctypes.c_int),
     ]
 
 

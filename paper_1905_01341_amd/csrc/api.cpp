@@ -61,6 +61,7 @@ static void check_options(const bfm_options &o) {
     BFM_CHECK(o.m2l_shape >= -1 && o.m2l_shape <= 3, BFM_EINVAL, "m2l_shape must be -1, 0, 1, 2 or 3");
     BFM_CHECK(o.m2l_orders == 0 || o.m2l_orders == 1, BFM_EINVAL, "m2l_orders must be 0 or 1");
     BFM_CHECK(o.p2p_shape >= -1 && o.p2p_shape < kSymShapeCount, BFM_EINVAL, "p2p_shape must be -1, 0, 1 or 2");
+    BFM_CHECK(o.near_corr == 0 || o.near_corr == 1, BFM_EINVAL, "near_corr must be 0 or 1");
 }
 
 struct DeviceScope {
@@ -192,6 +193,7 @@ int bfm_default_options(bfm_options *opt) {
     opt->use_graph = 0;
     opt->m2l_shape = -1;
     opt->p2p_shape = -1;
+    opt->near_corr = 0;
     return BFM_OK;
 }
 
@@ -284,8 +286,8 @@ int bfm_set_options(bfm_ctx *c, const bfm_options *opt) {
         BFM_CHECK(opt->device == c->device, BFM_EINVAL, "cannot change the device of a handle");
         const bool tree_change = opt->lmax != c->opt.lmax || opt->leaf_target != c->opt.leaf_target ||
                                  opt->p2p_shape != c->opt.p2p_shape;
-        const bool p_change =
-            opt->p != c->opt.p || opt->p_diag != c->opt.p_diag || opt->m2l_orders != c->opt.m2l_orders;
+        const bool p_change = opt->p != c->opt.p || opt->p_diag != c->opt.p_diag ||
+                              opt->m2l_orders != c->opt.m2l_orders || opt->near_corr != c->opt.near_corr;
         // (p_lo and precision take effect at the next low-precision product)
         void *keep_stream = c->opt.stream;
         c->opt = *opt;
@@ -345,6 +347,7 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
             to = {0, nt};
         }
         c->tri_h.assign(tri, tri + 3 * nt);
+        corr_invalidate(c, true);
         step_mesh_changed(c);
         c->tri0_h.clear();
         for (int64_t k = 3 * to[0]; k < 3 * to[1]; ++k) c->tri0_h.push_back(tri[k] - (int)vo[0]);

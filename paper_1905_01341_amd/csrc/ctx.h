@@ -35,6 +35,22 @@ struct Precond {
     DevBuf<double> Ainv, gj_row, gj_col, gj_piv;  // inverse coarse matrix [nb x nb] and Gauss-Jordan work
     DevBuf<double> csum, cy;           // per-bubble sums [3][nb], coarse correction [nb]
 };
+// Near-field correction matrices (corr.hip). Pattern, original order: per
+// vertex i the near triangles tv[tptr[i]..tptr[i+1]) as (v0, v1, v2, the
+// row slots of the three packed in bytes, 255 for i itself) and the
+// columns col[rptr[i]..rptr[i+1]) (j != i ascending). Values, per octree
+// in sorted order, ELL layout of width w (entry k of sorted row r at
+// k * nv + r): sorted column in ecol (padding: the row itself with zero
+// values)
+struct NearCorr {
+    DevBuf<int> tptr, tv, rptr, col;  // tv: 4 ints per entry
+    DevBuf<int> ecol;
+    DevBuf<double> ecl, ecm;
+    int64_t nnz = 0;
+    int w = 0;
+    bool pattern = false;  // tptr/tv/rptr/col current for the mesh
+    bool values = false;   // ecol/ecl/ecm current for the geometry and the octree's order
+};
 struct Mlp;      // learned initial guess (learn.hip)
 struct CoarseWorker;  // host thread queueing the coarse build (precond.hip)
 struct Stepper;  // captured product (tune.hip)
@@ -90,6 +106,7 @@ struct bfm_ctx {
     bfm::DevBuf<double> ysum;           // channel sums
     bfm::DevBuf<double> mii_s, lii_s, b_s, phi_s;
     bool diag_valid = false;            // mii_s / lii_s current for the mesh
+    bfm::NearCorr corr;                 // near-field corrections (opt.near_corr)
 
     bfm::Precond pre;
     std::vector<int> tri0_h;  // first bubble's triangles (local indices), kept for templates
@@ -131,6 +148,16 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
 
 // GMRES in sorted order: solves L x = b_s, x_s in/out.
 void gmres_sorted(bfm_ctx *c, double *x_s, bool use_guess, bfm_solve_info *info);
+
+// Near-field correction matrices (corr.hip); every call is a no-op unless
+// opt.near_corr. corr_invalidate drops the values (and with mesh the
+// pattern); ensure_corr builds what is missing; corr_apply adds
+// f CL x_s + g CM y_s to out_s; corr_diagonals corrects mii_s, lii_s and,
+// with phi_s non-null, b_s (all sorted)
+void corr_invalidate(bfm_ctx *c, bool mesh);
+void ensure_corr(bfm_ctx *c);
+void corr_apply(bfm_ctx *c, double f, const double *x_s, double g, const double *y_s, double *out_s);
+void corr_diagonals(bfm_ctx *c, const double *phi_s);
 
 // Spherical-harmonic preconditioner (precond.hip)
 // weighted: G+ = (G^T W G)^{-1} G^T W with W the template vertex areas; else plain least squares

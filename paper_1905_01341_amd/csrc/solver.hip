@@ -88,6 +88,7 @@ void ensure_geometry(bfm_ctx *c, bool check_now) {
                                                     flag);
     BFM_LAUNCHED();
     BFM_HIP(hipMemcpyAsync(c->host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    corr_invalidate(c, false);
     c->geom_valid = true;
     c->geom_unchecked = true;
     if (check_now) geometry_check(c);
@@ -120,6 +121,7 @@ void ensure_tree(bfm_ctx *c) {
     c->prof.end(pi, c->stream, 0.0, 0.0);
     c->tree_valid = true;
     c->diag_valid = false;
+    corr_invalidate(c, false);  // the corrections are stored in the octree's order
     graph_invalidate(c);
 }
 
@@ -267,6 +269,7 @@ void diagonal_pass(bfm_ctx *c, const double *phi_dev) {
                                                   t.pny.get(), t.pnz.get(), phs, n, X, Y, Z,
                                                   c->mii_s.get(), c->lii_s.get(), c->b_s.get());
     BFM_LAUNCHED();
+    corr_diagonals(c, phs);
     c->prof.end(pi, st, 0.0, 0.0);
     c->diag_valid = true;
 }
@@ -302,6 +305,7 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
     if (!direct) ensure_ops(c);
     if (lo) ensure_ops_lo(c, precision);
     if (add_diag && !c->diag_valid) diagonal_pass(c, nullptr);
+    ensure_corr(c);
     hipStream_t st = c->stream;
     Tree &t = c->tree;
     const int64_t n = c->nv;
@@ -327,6 +331,7 @@ void matvec_sorted(bfm_ctx *c, double f, const double *x_s, double g, const doub
                                                  add_diag ? c->lii_s.get() : nullptr,
                                                  add_diag ? c->mii_s.get() : nullptr, out_s);
     BFM_LAUNCHED();
+    corr_apply(c, f, mono ? x_s : nullptr, g, dip ? y_s : nullptr, out_s);
 }
 
 // ---------------------------------------------------------------------------

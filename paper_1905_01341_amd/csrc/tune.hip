@@ -243,6 +243,7 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out) {
             c->tree_valid = false;
             ensure_tree(c);
             ensure_ops(c);
+            ensure_corr(c);  // the corrections' values follow the octree: not part of the timed pass
             if (!warm) {  // first pass uploads the diagonal pass's operators
                 diagonal_pass(c, xo.get());
                 warm = true;

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_and_errors_without_gpu():
     o = bfm.default_options()
     assert o.abi_version == bfm.ABI_VERSION and o.p == 16 and o.p_diag == 0 and o.gmres_restart == 30
-    assert o.p2p_shape == -1 and o.m2l_shape == -1
+    assert o.p2p_shape == -1 and o.m2l_shape == -1 and o.near_corr == 0
     lib = bfm.load()
     # null arguments are rejected with EINVAL and a message
     assert lib.bfm_create(None, None) == -1
