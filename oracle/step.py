@@ -7,6 +7,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring). Follows the paper:
   F = G (G^T G)^{-1} G^T per bubble, G the real harmonics of degree
   0..p_f-1 at the template directions of the bubble's vertices; applied to
   r and phi before the right-hand side and to dr/dt and dphi/dt after it;
+  for toroidal bubbles (genus 1, spherical7) G is the real trigonometric
+  basis of the two angles of each vertex on the template torus, degrees
+  0..p_f/2 in each (p_f even, (p_f + 1)^2 columns);
 * geometry (Section 3.2, ns1) and bubble volumes by the divergence theorem
   over the flat triangles, V = sum r1 . (r2 x r3) / 6 (about the bubble's
   own first vertex);
@@ -65,6 +68,30 @@ class Physics:
 def filter_matrix(dirs, pf):
     """F = G (G^T G)^{-1} G^T for harmonics of degree 0..pf-1 (eq3_25)."""
     G = real_sh(pf - 1, dirs)
+    return G @ np.linalg.solve(G.T @ G, G.T)
+
+
+def torus_basis(angles, pf):
+    """Real trigonometric basis of bandwidth pf (pf even) at (theta, phi):
+    every product of {1, cos k theta, sin k theta : k = 1..pf/2} with the
+    same set in phi - the real form of e^{i(n theta + m phi)}, |n|, |m| <=
+    pf/2 (spherical7). [nd, (pf + 1)^2]."""
+    if pf % 2:
+        raise ValueError("the toroidal filter needs an even bandwidth")
+    th, ph = np.asarray(angles, dtype=np.float64).T
+
+    def one(x):
+        cols = [np.ones_like(x)]
+        for k in range(1, pf // 2 + 1):
+            cols += [np.cos(k * x), np.sin(k * x)]
+        return np.stack(cols, axis=1)
+    A, B = one(th), one(ph)
+    return (A[:, :, None] * B[:, None, :]).reshape(len(th), -1)
+
+
+def filter_matrix_torus(angles, pf):
+    """F = G (G^T G)^{-1} G^T with the toroidal basis (spherical7)."""
+    G = torus_basis(angles, pf)
     return G @ np.linalg.solve(G.T @ G, G.T)
 
 
@@ -159,20 +186,23 @@ class Mesh:
     tri: np.ndarray
     vtx_off: np.ndarray
     tri_off: np.ndarray
-    dirs: np.ndarray          # template directions [nd, 3]
+    dirs: np.ndarray          # template directions [nd, 3] (spheres) or angles [nd, 2] (tori)
     nb: int
     nd: int
     rings: list = field(default=None)
     F: np.ndarray = field(default=None)
 
 
-def make_mesh(tri, vtx_off, tri_off, dirs, pf):
+def make_mesh(tri, vtx_off, tri_off, dirs, pf, torus=False):
+    """Connectivity, one-rings and the filter of bandwidth pf; dirs are the
+    template's unit directions [nd, 3], or with torus its angles [nd, 2]."""
     nb = len(vtx_off) - 1
     nd = int(vtx_off[1] - vtx_off[0])
     nv = nb * nd
     m = Mesh(np.asarray(tri), np.asarray(vtx_off), np.asarray(tri_off), np.asarray(dirs), nb, nd)
     m.rings = one_ring(m.tri, nv)
-    m.F = filter_matrix(dirs, pf) if pf > 0 else None
+    if pf > 0:
+        m.F = filter_matrix_torus(dirs, pf) if torus else filter_matrix(dirs, pf)
     return m
 
 

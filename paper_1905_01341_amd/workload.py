@@ -20,6 +20,14 @@ vertices per bubble, clusters of up to thousands of bubbles):
                >= 0.5 at bounding radius 1.05 R, shapes perturbed by real
                spherical harmonics of degree 2..8 (amplitude 0.05 R)
 * ``c5000``    as ``c1000`` with 5000 bubbles in a cube of side 160
+* ``torus1``   one toroidal bubble (genus 1, Section 3.7): major radius 1,
+               tube radius 0.35, a 48 x 16 grid in the two angles (768
+               vertices), phi = 1 + U[-0.1, 0.1]
+* ``t100``     100 such tori, scales U[0.5, 1], random orientations, cube of
+               side 30, bounding spheres >= 0.5 apart, phi ~ U[-1, 1]
+* ``t1000``    1000 tori on a 42 x 14 grid (588 vertices each), cube of side
+               90, phi per torus = U[-1, 1] + 0.1 x (random trigonometric
+               polynomial of degree 1..3 in each angle, max-normalised)
 """
 from __future__ import annotations
 
@@ -31,7 +39,8 @@ import scipy.special
 SEED_BASE = 1905013410
 
 # (name, seed offset) - seed = SEED_BASE + offset
-WORKLOAD_SEEDS = {"single": 0, "c100": 1, "c1000": 2, "learned": 3, "c5000": 4}
+WORKLOAD_SEEDS = {"single": 0, "c100": 1, "c1000": 2, "learned": 3, "c5000": 4, "torus1": 5, "t100": 6,
+                  "t1000": 7}
 
 
 @dataclasses.dataclass
@@ -45,6 +54,10 @@ class Cluster:
     centres  float64 [nb, 3]   bubble centres used for placement
     radii    float64 [nb]      unperturbed radii
     dirs     float64 [nv, 3]   unit direction of each vertex on its icosphere
+                               (spherical bubbles; None for tori)
+    angles   float64 [nv, 2]   (theta, phi) of each vertex on the unit torus:
+                               theta around the tube, phi around the axis
+                               (toroidal bubbles; None for spheres)
     """
 
     xyz: np.ndarray
@@ -53,7 +66,8 @@ class Cluster:
     tri_off: np.ndarray
     centres: np.ndarray
     radii: np.ndarray
-    dirs: np.ndarray
+    dirs: np.ndarray | None
+    angles: np.ndarray | None = None
 
     @property
     def nv(self) -> int:
@@ -208,6 +222,67 @@ def cluster(nb: int, level: int, side: float, rmin: float, rmax: float,
     return Cluster(xyz, tri, vtx_off, tri_off, centres, radii, dirs)
 
 
+TORUS_TUBE = 0.35  # tube radius of the template torus (major radius 1)
+
+
+def torus(n_phi: int, n_theta: int, tube: float = TORUS_TUBE):
+    """Torus of major radius 1 and tube radius ``tube`` on an n_phi x n_theta
+    grid of the angles: vertex (i, k) at phi = 2 pi i / n_phi (around the
+    axis z), theta = 2 pi k / n_theta (around the tube), position
+    ((1 + tube cos theta) cos phi, (1 + tube cos theta) sin phi,
+    tube sin theta), index i * n_theta + k. Each grid cell is split along
+    its (i, k)-(i+1, k+1) diagonal; triangles are counter-clockwise seen
+    from outside the tube. Returns (xyz, tri, angles [(theta, phi)])."""
+    i, k = np.meshgrid(np.arange(n_phi), np.arange(n_theta), indexing="ij")
+    ph = 2.0 * np.pi * i.ravel() / n_phi
+    th = 2.0 * np.pi * k.ravel() / n_theta
+    rho = 1.0 + tube * np.cos(th)
+    xyz = np.stack([rho * np.cos(ph), rho * np.sin(ph), tube * np.sin(th)], axis=1)
+    tri = []
+    for a in range(n_phi):
+        for b in range(n_theta):
+            v00 = a * n_theta + b
+            v10 = ((a + 1) % n_phi) * n_theta + b
+            v01 = a * n_theta + (b + 1) % n_theta
+            v11 = ((a + 1) % n_phi) * n_theta + (b + 1) % n_theta
+            tri += [(v00, v10, v11), (v00, v11, v01)]
+    tri = np.array(tri, dtype=np.int32)
+    return xyz, tri, np.stack([th, ph], axis=1)
+
+
+def _rotation(rng: np.random.Generator) -> np.ndarray:
+    """A rotation matrix from a normalised Gaussian quaternion."""
+    q = rng.standard_normal(4)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def torus_cluster(nb: int, n_phi: int, n_theta: int, side: float, smin: float, smax: float,
+                  gap: float, seed: int) -> Cluster:
+    """nb toroidal bubbles: the template torus scaled by U[smin, smax],
+    rotated at random and placed like ``cluster`` (bounding spheres of
+    radius (1 + tube) x scale at least ``gap`` apart). ``radii`` holds the
+    scales."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    v0, f0, a0 = torus(n_phi, n_theta)
+    nd = v0.shape[0]
+    if nb == 1:
+        centres, scales = np.zeros((1, 3)), np.array([smax])
+        rots = [np.eye(3)]
+    else:
+        centres, scales = _place(rng, nb, side, smin, smax, gap, 1.0 + TORUS_TUBE)
+        rots = [_rotation(rng) for _ in range(nb)]
+    xyz = np.empty((nb * nd, 3))
+    for b in range(nb):
+        xyz[b * nd:(b + 1) * nd] = centres[b] + scales[b] * (v0 @ rots[b].T)
+    tri = (f0[None, :, :] + (np.arange(nb, dtype=np.int64) * nd)[:, None, None]).reshape(-1, 3).astype(np.int32)
+    vtx_off = np.arange(nb + 1, dtype=np.int64) * nd
+    tri_off = np.arange(nb + 1, dtype=np.int64) * f0.shape[0]
+    return Cluster(xyz, tri, vtx_off, tri_off, centres, scales, None, np.tile(a0, (nb, 1)))
+
+
 def make(name: str) -> tuple[Cluster, np.ndarray]:
     """Named workload -> (cluster, phi)."""
     seed = SEED_BASE + WORKLOAD_SEEDS[name]
@@ -224,7 +299,42 @@ def make(name: str) -> tuple[Cluster, np.ndarray]:
         nb, side = (1000, 90.0) if name == "c1000" else (5000, 160.0)
         cl = cluster(nb, 3, side, 0.5, 1.0, 0.5, seed, perturb=0.05)
         return cl, smooth_phi(cl, seed + 1000)
+    if name == "torus1":
+        cl = torus_cluster(1, 48, 16, 0.0, 1.0, 1.0, 0.0, seed)
+        rng = np.random.default_rng(np.random.PCG64(seed + 1000))
+        return cl, 1.0 + rng.uniform(-0.1, 0.1, size=cl.nv)
+    if name == "t100":
+        cl = torus_cluster(100, 48, 16, 30.0, 0.5, 1.0, 0.5, seed)
+        rng = np.random.default_rng(np.random.PCG64(seed + 1000))
+        return cl, rng.uniform(-1.0, 1.0, size=cl.nv)
+    if name == "t1000":
+        cl = torus_cluster(1000, 42, 14, 90.0, 0.5, 1.0, 0.5, seed)
+        return cl, smooth_torus_phi(cl, seed + 1000)
     raise KeyError(name)
+
+
+def smooth_torus_phi(cl: Cluster, seed: int, amp: float = 0.1, degree: int = 3) -> np.ndarray:
+    """Per-torus potential: a uniform level U[-1, 1] plus a smooth variation
+    (a random real trigonometric polynomial of degree 1..degree in each
+    angle, max amplitude ``amp``)."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    nd = int(cl.vtx_off[1] - cl.vtx_off[0])
+    th, ph = cl.angles[:nd, 0], cl.angles[:nd, 1]
+    cols = []
+    for n in range(degree + 1):
+        for m in range(degree + 1):
+            if n == 0 and m == 0:
+                continue
+            for fa in ((np.cos, np.sin) if n else (np.cos,)):
+                for fb in ((np.cos, np.sin) if m else (np.cos,)):
+                    cols.append(fa(n * th) * fb(m * ph))
+    basis = np.stack(cols, axis=1)
+    phi = np.empty(cl.nv)
+    for b in range(cl.nb):
+        f = basis @ rng.standard_normal(basis.shape[1])
+        f /= np.max(np.abs(f))
+        phi[cl.vtx_off[b]:cl.vtx_off[b + 1]] = rng.uniform(-1.0, 1.0) + amp * f
+    return phi
 
 
 def smooth_phi(cl: Cluster, seed: int, amp: float = 0.1) -> np.ndarray:
