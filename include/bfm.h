@@ -201,6 +201,22 @@ int bfm_set_mesh(bfm_ctx *ctx, int64_t nv, const double *xyz, int64_t nt, const 
  */
 int bfm_set_sphere_template(bfm_ctx *ctx, int32_t nd, const double *dirs);
 
+/*
+ * Torus template for toroidal (genus-1) bubbles (Section 3.7: the shape
+ * filter of a torus-like bubble uses the 2D Fourier basis e^{i(n theta +
+ * m phi)} of the angles that place each vertex on a unit torus): every
+ * bubble has nd vertices numbered like the template, whose angles are
+ * angles (host, [nd][2]: theta around the tube, phi around the axis, in
+ * radians). It replaces a sphere template; the time-step harness then
+ * filters with the real trigonometric basis of degree <= filter_degree / 2
+ * in each angle. The solve itself does not depend on the genus; the
+ * harmonic preconditioners and the learned guess need a sphere template and
+ * fail with BFM_EINVAL under this one. Errors: BFM_EINVAL when a bubble
+ * range does not hold nd vertices, an angle is not finite or the mesh has
+ * not been set.
+ */
+int bfm_set_torus_template(bfm_ctx *ctx, int32_t nd, const double *angles);
+
 /* Move the vertices (same connectivity): xyz host [nv][3] or device
  * (_dev, FP64 [nv][3]). Geometry and octree are rebuilt at the next use. */
 int bfm_set_positions(bfm_ctx *ctx, const double *xyz);

@@ -5,7 +5,10 @@
  *   1. shape filter of bandwidth p_f on r and phi (Section 3.7, eq3_24 and
  *      spherical6): per bubble, plain least squares onto the real
  *      spherical harmonics of degree 0..p_f-1 at the template directions
- *      (bfm_set_sphere_template), F = G (G^T G)^{-1} G^T;
+ *      (bfm_set_sphere_template), F = G (G^T G)^{-1} G^T; for toroidal
+ *      bubbles (bfm_set_torus_template, spherical7) onto the real
+ *      trigonometric basis of degree 0..p_f/2 in each template angle
+ *      (p_f even, (p_f + 1)^2 functions);
  *   2. geometry (Section 3.2), bubble volumes V_m = sum over the bubble's
  *      triangles of r1 . (r2 x r3) / 6, mean curvature H by the paraboloid
  *      through five one-ring neighbours (Section 3.5, parab1/parab2; the
@@ -25,9 +28,9 @@
  * from the filtered state passed to bfm_state_set.
  *
  * Requirements: a mesh whose bubbles are copies of one triangulation of a
- * sphere (bubble b holds vertices b*nd .. b*nd+nd-1 and triangles in the same
- * local order), with the template set by bfm_set_sphere_template; every
- * vertex has at least five neighbours.
+ * sphere or a torus (bubble b holds vertices b*nd .. b*nd+nd-1 and triangles
+ * in the same local order), with the template set by bfm_set_sphere_template
+ * or bfm_set_torus_template; every vertex has at least five neighbours.
  *
  * State (positions and potential) lives on the device; host arrays are
  * copied in or out before the call returns. Errors: BFM_EINVAL (bad

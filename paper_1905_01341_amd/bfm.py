@@ -161,6 +161,7 @@ def load(path: str = LIB_PATH):
         "bfm_set_mesh": ([P, I64, P, I64, P, ctypes.c_int32, P, P], I),
         "bfm_set_positions": ([P, P], I),
         "bfm_set_sphere_template": ([P, ctypes.c_int32, P], I),
+        "bfm_set_torus_template": ([P, ctypes.c_int32, P], I),
         "bfm_set_positions_dev": ([P, P], I),
         "bfm_geometry": ([P, P, P], I),
         "bfm_diagonals": ([P, P, P, P, P], I),
@@ -346,11 +347,18 @@ class Solver:
         self.set_mesh(cl.xyz, cl.tri, cl.vtx_off, cl.tri_off)
         nd = int(cl.vtx_off[1] - cl.vtx_off[0])
         if template and cl.nb * nd == cl.nv:
-            self.set_sphere_template(cl.dirs[:nd])
+            if getattr(cl, "angles", None) is not None:
+                self.set_torus_template(cl.angles[:nd])
+            else:
+                self.set_sphere_template(cl.dirs[:nd])
 
     def set_sphere_template(self, dirs):
         d = np.ascontiguousarray(dirs, dtype=np.float64)
         _check(self.lib.bfm_set_sphere_template(self.h, d.shape[0], _ptr(d)))
+
+    def set_torus_template(self, angles):
+        a = np.ascontiguousarray(angles, dtype=np.float64)
+        _check(self.lib.bfm_set_torus_template(self.h, a.shape[0], _ptr(a)))
 
     def set_positions(self, xyz):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)

@@ -122,7 +122,7 @@ void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm
     // beside the octree build, whose short kernels and host round trips leave
     // most of the device free (beside the diagonal pass its serial chain of
     // small kernels would wait for every wave of the pass's large launches)
-    if (c->opt.precond == BFM_PRECOND_SH_COARSE && c->pre.nd > 0) {
+    if (c->opt.precond == BFM_PRECOND_SH_COARSE && c->pre.nd > 0 && c->pre.genus == 0) {
         coarse_mark(c);
         coarse_launch(c);
     }
@@ -352,6 +352,7 @@ int bfm_set_mesh(bfm_ctx *c, int64_t nv, const double *xyz, int64_t nt, const in
         c->tri0_h.clear();
         for (int64_t k = 3 * to[0]; k < 3 * to[1]; ++k) c->tri0_h.push_back(tri[k] - (int)vo[0]);
         c->pre.nd = 0;
+        c->pre.genus = 0;
         c->pre.ready = false;
         c->pre.gen += 1;
         c->vtx_off = vo;
@@ -385,10 +386,34 @@ int bfm_set_sphere_template(bfm_ctx *c, int32_t nd, const double *dirs) {
             BFM_CHECK(std::fabs(r - 1.0) < 1e-6, BFM_EINVAL, "template directions must be unit vectors");
         }
         c->pre.dirs_h.assign(dirs, dirs + 3 * (size_t)nd);
+        c->pre.ang_h.clear();
+        c->pre.genus = 0;
         c->pre.tri_h = c->tri0_h;
         c->pre.nd = nd;
         c->pre.ready = false;
         c->pre.gen += 1;  // rebuild every harmonic basis for the new template
+        step_mesh_changed(c);
+    });
+}
+
+int bfm_set_torus_template(bfm_ctx *c, int32_t nd, const double *angles) {
+    return guarded([&] {
+        BFM_CHECK(c && angles, BFM_EINVAL, "null argument");
+        BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
+        BFM_CHECK(nd >= 4 && (int64_t)nd * c->nb == c->nv, BFM_EINVAL,
+                  "every bubble must hold nd vertices (nv = nb * nd)");
+        for (int b = 0; b <= c->nb; ++b)
+            BFM_CHECK(c->vtx_off[b] == (int64_t)b * nd, BFM_EINVAL, "bubble vertex ranges must be b * nd");
+        for (int v : c->tri0_h) BFM_CHECK(v >= 0 && v < nd, BFM_EINVAL, "first bubble's triangles leave its range");
+        for (int v = 0; v < 2 * nd; ++v)
+            BFM_CHECK(std::isfinite(angles[v]), BFM_EINVAL, "template angles must be finite");
+        c->pre.ang_h.assign(angles, angles + 2 * (size_t)nd);
+        c->pre.dirs_h.clear();
+        c->pre.genus = 1;
+        c->pre.tri_h = c->tri0_h;
+        c->pre.nd = nd;
+        c->pre.ready = false;
+        c->pre.gen += 1;
         step_mesh_changed(c);
     });
 }

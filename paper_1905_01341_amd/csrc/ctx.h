@@ -15,6 +15,7 @@ namespace bfm {
 // projector (Gp, column-major [nc x nd]).
 struct ShBasis {
     int nmax = -1, nc = 0, nd = 0, weighted = 1;
+    int genus = 0;     // 0: spherical harmonics of degree <= nmax; 1: trigonometric, degree <= nmax per angle
     uint64_t gen = 0;  // template generation the basis was built for
     DevBuf<double> G, Gp;
 };
@@ -23,7 +24,9 @@ struct Precond {
     uint64_t gen = 1;  // bumped whenever the template changes (invalidates every ShBasis)
     double cc = 0.0;
     bool ready = false;
+    int genus = 0;               // 0: sphere template (dirs_h), 1: torus template (ang_h)
     std::vector<double> dirs_h;  // template directions [nd][3]
+    std::vector<double> ang_h;   // template torus angles (theta around the tube, phi around the axis) [nd][2]
     std::vector<int> tri_h;      // template triangles (first bubble, local indices)
     ShBasis basis;
     DevBuf<double> fac, R, X, C, Y;
@@ -162,6 +165,9 @@ void corr_diagonals(bfm_ctx *c, const double *phi_s);
 // Spherical-harmonic preconditioner (precond.hip)
 // weighted: G+ = (G^T W G)^{-1} G^T W with W the template vertex areas; else plain least squares
 void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st, bool weighted = true);
+// torus template: plain least squares onto the real trigonometric basis of
+// degree <= h in each angle ((2h + 1)^2 functions)
+void torus_basis_build(const Precond &P, int h, ShBasis &B, hipStream_t st);
 void precond_build(bfm_ctx *c);
 void precond_radii(bfm_ctx *c);
 void precond_apply(bfm_ctx *c, const double *in_s, double *out_s);

@@ -619,7 +619,8 @@ void mlp_features(bfm_ctx *c, const double *phi_dev, const double *q_dev, float 
     Mlp &net = mlp_get(c);
     Precond &P = c->pre;
     hipStream_t st = c->stream;
-    BFM_CHECK(P.nd > 0, BFM_EINVAL, "the learned guess needs a sphere template (bfm_set_sphere_template)");
+    BFM_CHECK(P.nd > 0 && P.genus == 0, BFM_EINVAL,
+              "the learned guess needs a sphere template (bfm_set_sphere_template)");
     ensure_geometry(c);
     sh_basis_build(P, Mlp::kDegree, net.sh, st);
     const int nd = P.nd, nb = c->nb, nc = net.sh.nc;

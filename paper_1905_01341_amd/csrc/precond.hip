@@ -68,7 +68,7 @@ static void cholesky_solve(int n, std::vector<double> &S, std::vector<double> &B
     for (int j = 0; j < n; ++j) {
         double d = S[(size_t)j * n + j];
         for (int p = 0; p < j; ++p) d -= S[(size_t)j * n + p] * S[(size_t)j * n + p];
-        BFM_CHECK(d > 0.0, BFM_EINVAL, "spherical-harmonic template: Gram matrix not positive definite");
+        BFM_CHECK(d > 0.0, BFM_EINVAL, "template basis: Gram matrix not positive definite");
         d = std::sqrt(d);
         S[(size_t)j * n + j] = d;
         for (int i = j + 1; i < n; ++i) {
@@ -91,29 +91,10 @@ static void cholesky_solve(int n, std::vector<double> &S, std::vector<double> &B
     }
 }
 
-void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st, bool weighted) {
-    const int nd = P.nd;
-    BFM_CHECK(nd > 0 && !P.dirs_h.empty(), BFM_EINVAL, "no sphere template set");
-    BFM_CHECK(nmax >= 0 && (nmax + 1) * (nmax + 1) <= nd, BFM_EINVAL,
-              "harmonic degree must satisfy (degree + 1)^2 <= vertices per bubble");
-    if (B.nmax == nmax && B.nd == nd && B.weighted == (int)weighted && B.gen == P.gen) return;
-    const int nc = (nmax + 1) * (nmax + 1);
-    // weights: template vertex areas from the first bubble's triangles on the
-    // unit directions, or all ones (plain least squares)
-    std::vector<double> wv(nd, weighted ? 0.0 : 1.0);
-    for (size_t k = 0; weighted && k + 2 < P.tri_h.size(); k += 3) {
-        const double *a = &P.dirs_h[3 * P.tri_h[k]], *b = &P.dirs_h[3 * P.tri_h[k + 1]],
-                     *d = &P.dirs_h[3 * P.tri_h[k + 2]];
-        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-        const double e2[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
-        const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
-                     cz = e1[0] * e2[1] - e1[1] * e2[0];
-        const double A = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
-        for (int t = 0; t < 3; ++t) wv[P.tri_h[k + t]] += A / 3.0;
-    }
-    std::vector<double> G((size_t)nd * nc);  // row-major [nd][nc]
-    for (int v = 0; v < nd; ++v) sh_row(nmax, &P.dirs_h[3 * v], &G[(size_t)v * nc]);
-    // S = G^T W G ; R = G^T W  -> G+ = S^{-1} R  ([nc][nd])
+// Uploads G (row-major [nd][nc] on the host) and its least-squares
+// projector Gp = (G^T W G)^{-1} G^T W (W = diag(wv)) in the device layouts.
+static void basis_upload(int nd, int nc, const std::vector<double> &G, const std::vector<double> &wv, ShBasis &B,
+                         hipStream_t st) {
     std::vector<double> S((size_t)nc * nc, 0.0), R((size_t)nc * nd, 0.0);
     for (int i = 0; i < nc; ++i)
         for (int v = 0; v < nd; ++v) R[(size_t)i * nd + v] = G[(size_t)v * nc + i] * wv[v];
@@ -136,10 +117,69 @@ void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st, bool
     BFM_HIP(hipMemcpyAsync(B.G.get(), Gc.data(), sizeof(double) * Gc.size(), hipMemcpyHostToDevice, st));
     BFM_HIP(hipMemcpyAsync(B.Gp.get(), Gpc.data(), sizeof(double) * Gpc.size(), hipMemcpyHostToDevice, st));
     BFM_HIP(hipStreamSynchronize(st));
-    B.nmax = nmax;
     B.nc = nc;
     B.nd = nd;
+}
+
+// Real trigonometric basis of the torus angles (Section 3.7, spherical7: the
+// real form of e^{i(n theta + m phi)}, |n|, |m| <= h): the products of
+// {1, cos k theta, sin k theta : k = 1..h} with the same set in phi, theta
+// functions slowest.
+static void trig_row(int h, double th, double ph, double *row) {
+    const int w = 2 * h + 1;
+    std::vector<double> a(w), b(w);
+    a[0] = b[0] = 1.0;
+    for (int k = 1; k <= h; ++k) {
+        a[2 * k - 1] = std::cos(k * th);
+        a[2 * k] = std::sin(k * th);
+        b[2 * k - 1] = std::cos(k * ph);
+        b[2 * k] = std::sin(k * ph);
+    }
+    for (int i = 0; i < w; ++i)
+        for (int j = 0; j < w; ++j) row[i * w + j] = a[i] * b[j];
+}
+
+void torus_basis_build(const Precond &P, int h, ShBasis &B, hipStream_t st) {
+    const int nd = P.nd;
+    BFM_CHECK(nd > 0 && P.genus == 1 && !P.ang_h.empty(), BFM_EINVAL, "no torus template set");
+    const int nc = (2 * h + 1) * (2 * h + 1);
+    BFM_CHECK(h >= 0 && nc <= nd, BFM_EINVAL, "trigonometric degree must satisfy (2 degree + 1)^2 <= vertices per bubble");
+    if (B.genus == 1 && B.nmax == h && B.nd == nd && B.weighted == 0 && B.gen == P.gen) return;
+    std::vector<double> G((size_t)nd * nc), wv(nd, 1.0);
+    for (int v = 0; v < nd; ++v) trig_row(h, P.ang_h[2 * v], P.ang_h[2 * v + 1], &G[(size_t)v * nc]);
+    basis_upload(nd, nc, G, wv, B, st);
+    B.nmax = h;
+    B.weighted = 0;
+    B.genus = 1;
+    B.gen = P.gen;
+}
+
+void sh_basis_build(const Precond &P, int nmax, ShBasis &B, hipStream_t st, bool weighted) {
+    const int nd = P.nd;
+    BFM_CHECK(nd > 0 && P.genus == 0 && !P.dirs_h.empty(), BFM_EINVAL, "no sphere template set");
+    BFM_CHECK(nmax >= 0 && (nmax + 1) * (nmax + 1) <= nd, BFM_EINVAL,
+              "harmonic degree must satisfy (degree + 1)^2 <= vertices per bubble");
+    if (B.genus == 0 && B.nmax == nmax && B.nd == nd && B.weighted == (int)weighted && B.gen == P.gen) return;
+    const int nc = (nmax + 1) * (nmax + 1);
+    // weights: template vertex areas from the first bubble's triangles on the
+    // unit directions, or all ones (plain least squares)
+    std::vector<double> wv(nd, weighted ? 0.0 : 1.0);
+    for (size_t k = 0; weighted && k + 2 < P.tri_h.size(); k += 3) {
+        const double *a = &P.dirs_h[3 * P.tri_h[k]], *b = &P.dirs_h[3 * P.tri_h[k + 1]],
+                     *d = &P.dirs_h[3 * P.tri_h[k + 2]];
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double e2[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                     cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double A = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        for (int t = 0; t < 3; ++t) wv[P.tri_h[k + t]] += A / 3.0;
+    }
+    std::vector<double> G((size_t)nd * nc);  // row-major [nd][nc]
+    for (int v = 0; v < nd; ++v) sh_row(nmax, &P.dirs_h[3 * v], &G[(size_t)v * nc]);
+    basis_upload(nd, nc, G, wv, B, st);
+    B.nmax = nmax;
     B.weighted = (int)weighted;
+    B.genus = 0;
     B.gen = P.gen;
 }
 

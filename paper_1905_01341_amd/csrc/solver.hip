@@ -537,7 +537,8 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
     const bool use_graph = c->opt.use_graph != 0 && !c->prof.on;
     double *Z = nullptr, *Tv = nullptr;
     if (pc) {
-        BFM_CHECK(c->pre.nd > 0, BFM_EINVAL, "the harmonic preconditioner needs bfm_set_sphere_template");
+        BFM_CHECK(c->pre.nd > 0 && c->pre.genus == 0, BFM_EINVAL,
+                  "the harmonic preconditioner needs a sphere template (bfm_set_sphere_template)");
         precond_build(c);
         precond_radii(c);
         if (c->opt.precond == BFM_PRECOND_SH_COARSE) {

@@ -27,7 +27,7 @@ struct Stepper {
     bool rings_ready = false;
     DevBuf<int> ring5;          // five one-ring neighbours per vertex [nv][5]
     DevBuf<int> tri_off;        // per-bubble triangle ranges [nb + 1]
-    ShBasis filt;               // plain least-squares basis, degree p_f - 1
+    ShBasis filt;               // plain least-squares basis of the shape filter
     bool state_set = false;
     double t = 0.0;
     int steps = 0;
@@ -327,12 +327,25 @@ static void build_rings(bfm_ctx *c, Stepper &S) {
 
 static void check_ready(bfm_ctx *c, Stepper &S) {
     BFM_CHECK(c->nv > 0, BFM_EINVAL, "no mesh set");
-    BFM_CHECK(c->pre.nd > 0, BFM_EINVAL, "the time-step harness needs bfm_set_sphere_template");
+    BFM_CHECK(c->pre.nd > 0, BFM_EINVAL,
+              "the time-step harness needs a template (bfm_set_sphere_template or bfm_set_torus_template)");
     BFM_CHECK(S.ph_set, BFM_EINVAL, "no physics set (bfm_set_physics)");
     const int pf = S.ph.filter_degree;
-    BFM_CHECK(pf >= 0 && (int64_t)pf * pf <= c->pre.nd, BFM_EINVAL, "filter_degree^2 must not exceed nd");
+    if (c->pre.genus == 0) {
+        BFM_CHECK(pf >= 0 && (int64_t)pf * pf <= c->pre.nd, BFM_EINVAL, "filter_degree^2 must not exceed nd");
+    } else {
+        BFM_CHECK(pf >= 0 && pf % 2 == 0 && (int64_t)(pf + 1) * (pf + 1) <= c->pre.nd, BFM_EINVAL,
+                  "toroidal filter: filter_degree must be even with (filter_degree + 1)^2 <= nd");
+    }
     build_rings(c, S);
-    if (pf > 0) sh_basis_build(c->pre, pf - 1, S.filt, c->stream, false);
+    if (pf > 0) {
+        // spherical: harmonics of degree 0..p_f-1; toroidal (spherical7): degree
+        // 0..p_f/2 in each angle
+        if (c->pre.genus == 0)
+            sh_basis_build(c->pre, pf - 1, S.filt, c->stream, false);
+        else
+            torus_basis_build(c->pre, pf / 2, S.filt, c->stream);
+    }
 }
 
 // in -> out = F in for packed arrays (out may not alias in)
