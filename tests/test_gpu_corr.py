@@ -151,3 +151,46 @@ def test_corrections_follow_the_mesh():
     with pytest.raises(bfm.BfmError):
         sv.set_options(near_corr=2)
     sv.close()
+
+
+def _bipyramid(n):
+    """Closed bipyramid: apexes (0, 0, +-1) over n equator points; each apex
+    has n neighbours, so its correction row has n + 1 columns."""
+    ang = 2.0 * np.pi * np.arange(n) / n
+    xyz = np.concatenate([[[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]],
+                          np.stack([np.cos(ang), np.sin(ang), 0.05 * np.sin(3 * ang)], axis=1)])
+    tri = []
+    for k in range(n):
+        a, b = 2 + k, 2 + (k + 1) % n
+        tri += [(0, a, b), (1, b, a)]
+    return xyz, np.array(tri, dtype=np.int32)
+
+
+@pytest.mark.parametrize("n", [24, 48])
+def test_wide_rows(n):
+    """Rows wider than the LDS accumulators hold (48 equator points: 49
+    columns at the apexes) take the in-place path; both match the oracle."""
+    xyz, tri = _bipyramid(n)
+    nv = len(xyz)
+    s, nrm, _ = oracle.geometry(xyz, tri)
+    corr = oc.corrections(xyz, tri, s, nrm)
+    assert max(len(c) for c, _, _ in corr.values()) == n + 1
+    x, y = _vec(nv, 4), _vec(nv, 5)
+    phi = np.cos(np.arange(nv) * 0.3)
+    sv = bfm.Solver(p=16, leaf_target=8)
+    sv.set_mesh(xyz, tri)
+    a = sv.matvec(0.7, x, -1.3, y, direct=True)
+    M0, L0, b0 = sv.diagonals(phi)
+    sv.set_options(near_corr=1)
+    b = sv.matvec(0.7, x, -1.3, y, direct=True)
+    M1, L1, b1 = sv.diagonals(phi)
+    sv.close()
+    ref = oc.apply(corr, 0.7, x, -1.3, y)
+    e = float(np.max(np.abs((b - a) - ref)) / np.max(np.abs(a)))
+    z = np.zeros(nv)
+    dM, dL, db = oc.corrected_diagonals(xyz, nrm, phi, corr, z, z, z)
+    ed = max(float(np.max(np.abs(g - w)) / np.max(np.abs(base)))
+             for g, w, base in ((M1 - M0, dM, M0), (L1 - L0, dL, L0), (b1 - b0, db, b0)))
+    print(f"bipyramid n={n}: product correction error {e:.2e}, diagonals {ed:.2e}")
+    assert e < 1e-12 and ed < 1e-12
+
