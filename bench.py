@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-probe", action="store_true", help="skip the ceiling probes (measured peaks of each mix)")
     ap.add_argument("--form", choices=["tuned", "plain"], default="tuned")
     ap.add_argument("--precond-degree", type=int, default=None)
     ap.add_argument("--plain-steps", type=int, default=2)
@@ -289,6 +290,11 @@ def roofline_entry(cls, prof, prof_steps, stats, opt, p_diag, nv, workload):
         alg_bytes = (168.0 if group == "diag_" else 40.0) * nv
     else:
         return None
+    # the ceiling probe of the same instruction mix (bench.py --probe runs)
+    if kind == "m2l":
+        probe = {0: ("fp64_mfma", 1.0), 2: ("bf16_mfma", 3.0)}.get(lo_prec)
+    else:
+        probe = {"": ("fp64_pair", 1.0), "lo_": ("fp32_pair", 1.0)}.get(group)
     avg_ms = d["ms"] / d["launches"]
     ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
     tr = measured_traffic(tcls, kname, workload, stats["lmax"], p) if kname else None
@@ -301,7 +307,39 @@ def roofline_entry(cls, prof, prof_steps, stats, opt, p_diag, nv, workload):
             "algorithmic_bytes": alg_bytes,
             "avg_launch_ms": round(avg_ms, 4), "launches": d["launches"],
             "ms_per_step": round(d["ms"] / prof_steps, 4),
-            "flops_per_launch": d["flops"] / d["launches"]}
+            "flops_per_launch": d["flops"] / d["launches"],
+            "probe": None if probe is None else {"mix": probe[0], "divisor": probe[1]}}
+
+
+# ceiling probes (include/bfm_debug.h bfm_debug_probe): kind, iterations per
+# lane (each launch takes a few milliseconds)
+PROBES = {"fp64_mfma": (0, 100), "fp64_fma": (1, 10000), "fp32_fma": (2, 10000), "fp64_pair": (3, 30),
+          "fp32_pair": (4, 60), "bf16_mfma": (5, 400)}
+
+
+def run_probes():
+    """Achieved TFLOP/s of every ceiling probe (pair probes: 11 flops per pair)."""
+    from paper_1905_01341_amd import bfm
+    out = {}
+    for name, (kind, iters) in PROBES.items():
+        ms, ops = bfm.debug_probe(kind, iters)
+        out[name] = {"tflops": round(ops / (ms * 1e-3) / 1e12, 2), "ms": round(ms, 3)}
+    return out
+
+
+def attach_probe(entry, probes):
+    """probe_peak / probe_frac of a roofline entry from the measured ceilings."""
+    if entry is None:
+        return entry
+    pr = entry.pop("probe", None)
+    if pr is None or probes is None or pr["mix"] not in probes:
+        entry["probe_peak"] = entry["probe_frac"] = None
+        return entry
+    peak = probes[pr["mix"]]["tflops"] / pr["divisor"]
+    entry["probe_mix"] = pr["mix"] + (f" / {pr['divisor']:g}" if pr["divisor"] != 1.0 else "")
+    entry["probe_peak"] = round(peak, 2)
+    entry["probe_frac"] = round(entry["achieved"] / peak, 4) if peak > 0 else None
+    return entry
 
 
 def main():
@@ -413,10 +451,14 @@ def main():
                    "reference_iterations": info_ref["iterations"]}
         q_t.copy_(q_timed)
 
+    # measured ceilings of the hot kernels' instruction mixes, after the timed
+    # region (a few milliseconds of probe kernels)
+    probes = None if a.no_probe else run_probes()
     roof, roof_p2p = None, None
     if prof:
         named = [c for c in ("m2l", "p2p", "diag_m2l", "diag_p2p", "lo_m2l", "lo_p2p") if prof[c]["launches"] > 0]
-        entries = {c: roofline_entry(c, prof, prof_steps, stats, sv.opt, p_diag, cl.nv, a.workload)
+        entries = {c: attach_probe(roofline_entry(c, prof, prof_steps, stats, sv.opt, p_diag, cl.nv, a.workload),
+                                   probes)
                    for c in named}
         entries = {c: e for c, e in entries.items() if e is not None}
         if entries:
@@ -453,6 +495,7 @@ def main():
         },
         "roofline": roof,
         "roofline_p2p": roof_p2p,
+        "probes_tflops": None if probes is None else {k: v["tflops"] for k, v in probes.items()},
     }
     if prof:
         out["kernels_ms_per_step"] = {k: round(v["ms"] / prof_steps, 3) for k, v in prof.items()

@@ -49,6 +49,21 @@ int bfm_debug_operator(int p, int kind, int index, double *out, int *d_out);
 int bfm_debug_dgemm(int device, int M, int N, int K, const double *A, const double *B, double *C);
 int bfm_debug_spd_inverse(int device, int n, const double *A, double *Ainv);
 
+/*
+ * Ceiling probe: one launch of a kernel that issues a single instruction mix
+ * back to back on every CU (4096 workgroups of 256 lanes, each lane `iters`
+ * rounds), timed with HIP events after a warm-up launch, so that a hot
+ * kernel's throughput can be compared with what the device delivers for
+ * the same mix. kind: 0 FP64 MFMA (v_mfma_f64_16x16x4f64), 1 FP64 FMA,
+ * 2 FP32 FMA (not packed), 3 the FP64 near-field pair step (r^2, the 1/sqrt
+ * estimate with one Newton step, two fma; 11 algorithmic flops per pair),
+ * 4 the FP32 pair step (estimate only), 5 BF16 MFMA
+ * (v_mfma_f32_16x16x32_bf16). ms receives the launch time, ops the flops it
+ * performed (pair probes: pairs x 11). Returns BFM_OK or BFM_EINVAL (kind
+ * not 0..5, iters not in [1, 2^16]) / BFM_EDEVICE.
+ */
+int bfm_debug_probe(int device, int kind, int iters, double *ms, double *ops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -173,6 +173,7 @@ def load(path: str = LIB_PATH):
         "bfm_debug_operator": ([I, I, I, P, P], I),
         "bfm_debug_dgemm": ([I, I, I, I, P, P, P], I),
         "bfm_debug_spd_inverse": ([I, I, P, P], I),
+        "bfm_debug_probe": ([I, I, I, P, P], I),
         "bfm_profile": ([P, I], I),
         "bfm_profile_read": ([P, I, P, P, P], I),
         "bfm_autotune": ([P, D, ctypes.POINTER(TuneResult)], I),
@@ -255,6 +256,16 @@ def debug_m2l_rotation(p: int, index: int):
     rot = [2 * n + 1 for n in range(p)]
     return (blocks(out[:nr], rot), blocks(out[nr:nr + nz], [p - m for m in range(p)]),
             blocks(out[nr + nz:], rot), d)
+
+
+PROBE_KINDS = {0: "fp64_mfma", 1: "fp64_fma", 2: "fp32_fma", 3: "fp64_pair", 4: "fp32_pair", 5: "bf16_mfma"}
+
+
+def debug_probe(kind: int, iters: int, device: int = 0):
+    """(ms, ops) of one ceiling-probe launch (include/bfm_debug.h)."""
+    ms, ops = ctypes.c_double(), ctypes.c_double()
+    _check(load().bfm_debug_probe(device, kind, iters, ctypes.byref(ms), ctypes.byref(ops)))
+    return ms.value, ops.value
 
 
 def debug_dgemm(A, B, device=0):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbfm.so")
-SOURCES = ["api.cpp", "ops.cpp", "tree.hip", "fmm.hip", "fmm_rot.hip", "fmm_near.hip", "fmm_leaf.hip", "solver.hip", "precond.hip", "learn.hip", "step.hip", "tune.hip", "direct.hip", "corr.hip"]
+SOURCES = ["api.cpp", "ops.cpp", "tree.hip", "fmm.hip", "fmm_rot.hip", "fmm_near.hip", "fmm_leaf.hip", "solver.hip", "precond.hip", "learn.hip", "step.hip", "tune.hip", "direct.hip", "corr.hip", "probe.hip"]
 ARCH = os.environ.get("BFM_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every device pass (the compiler

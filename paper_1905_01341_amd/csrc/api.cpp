@@ -837,6 +837,14 @@ int bfm_debug_spd_inverse(int device, int n, const double *A, double *Ainv) {
     });
 }
 
+int bfm_debug_probe(int device, int kind, int iters, double *ms, double *ops) {
+    return guarded([&] {
+        BFM_CHECK(ms && ops, BFM_EINVAL, "null argument");
+        DeviceScope ds(device);
+        probe_run(kind, iters, ms, ops);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Time-step harness (include/bfm_step.h)
 

@@ -206,6 +206,9 @@ void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out);
 
 // time-step harness (step.hip)
 void step_free(bfm_ctx *c);
+
+// ceiling probe (probe.hip): one timed launch of instruction mix `kind`
+void probe_run(int kind, int iters, double *ms, double *ops);
 void step_mesh_changed(bfm_ctx *c);
 void step_set_physics(bfm_ctx *c, const bfm_physics &ph);
 void step_state_set(bfm_ctx *c, const double *xyz_h, const double *phi_h, double t);
