@@ -122,15 +122,6 @@ __device__ inline double inv_sqrt(double x) {
     return y;
 }
 
-// XCD-aware row blocks: workgroups are dealt round-robin to the 8 XCDs, so
-// XCD x takes a contiguous run of logical blocks (neighbouring rows, which
-// share triangles and vertices, stay in one L2)
-__device__ inline int64_t corr_block() {
-    const int nblock = gridDim.x, per = nblock / 8, rem = nblock % 8;
-    const int xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
-    return xcd * per + (xcd < rem ? xcd : rem) + idx;
-}
-
 // One sorted row per thread: the corrections of row r (vertex i = perm[r]),
 // written to the ELL slots k * nv + r in the pattern's column order. Each
 // near triangle comes as (v0, v1, v2, packed slots), read one triangle
@@ -155,7 +146,7 @@ __global__ void __launch_bounds__(64) k_corr_values(int64_t nv, const int *__res
                                                     double *__restrict__ ecl, double *__restrict__ ecm) {
     extern __shared__ double lacc[];  // LDS: [2][w][64]
     const int lane = threadIdx.x;
-    const int64_t r = corr_block() * blockDim.x + lane;
+    const int64_t r = xcd_block() * blockDim.x + lane;
     if (r >= nv) return;
     const int i = perm[r];
     const int r0 = rptr[i], r1 = rptr[i + 1];
@@ -297,7 +288,7 @@ __global__ void __launch_bounds__(256) k_corr_apply(int64_t nv, int w, const int
                                                     const double *__restrict__ ecl, const double *__restrict__ ecm,
                                                     double f, const double *__restrict__ x, double g,
                                                     const double *__restrict__ y, double *__restrict__ out) {
-    const int64_t r = corr_block() * blockDim.x + threadIdx.x;
+    const int64_t r = xcd_block() * blockDim.x + threadIdx.x;
     if (r >= nv) return;
     double ax = 0.0, ay = 0.0;
 #pragma unroll 6
@@ -341,7 +332,7 @@ __global__ void __launch_bounds__(256) k_corr_diag(int64_t nv, int w, const int 
                                                    const double *__restrict__ pny, const double *__restrict__ pnz,
                                                    const double *__restrict__ phi, double *__restrict__ mii,
                                                    double *__restrict__ lii, double *__restrict__ b) {
-    const int64_t r = corr_block() * blockDim.x + threadIdx.x;
+    const int64_t r = xcd_block() * blockDim.x + threadIdx.x;
     if (r >= nv) return;
     double sm = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, sb = 0.0;
     const double rx = px[r], ry = py[r], rz = pz[r];

@@ -89,7 +89,8 @@ struct bfm_ctx {
     bfm::DevBuf<int> v2t_off, v2t;  // vertex -> incident triangles (ascending)
 
     // geometry (original order): s [nv], normals SoA [3][nv]
-    bfm::DevBuf<double> s, nrm, tri_hc, tri_area;
+    bfm::DevBuf<double> s, nrm;
+    bfm::DevBuf<double> tri_rec;  // per triangle (half cross product x, y, z, area) [nt][4]
     bfm::DevBuf<int> flag;
     int *host_flag = nullptr;     // pinned copy of the geometry checks
     bool geom_valid = false;

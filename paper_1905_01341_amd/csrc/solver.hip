@@ -15,15 +15,16 @@ static unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 // Geometry (Section 3.2, ns1): per triangle c = (r2 - r1) x (r3 - r1),
 // A = |c|/2, N A = c/2; per vertex s = sum A/3, n = (sum N A)/|sum N A|.
 
-__global__ void k_tri_geom(const double *xyz, const int *tri, int64_t nt, int64_t nv, double *hc,
-                           double *area, int *flag) {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Per triangle: half the cross product (the area-weighted normal) and the
+// area, one 32-byte record (x, y, z, area) so that a vertex gathers each of
+// its triangles with one load
+__global__ void k_tri_geom(const double *xyz, const int *tri, int64_t nt, int64_t nv, double4 *rec, int *flag) {
+    const int64_t k = xcd_block() * blockDim.x + threadIdx.x;  // a bubble's vertices stay in one L2
     if (k >= nt) return;
     const int a = tri[3 * k], b = tri[3 * k + 1], c = tri[3 * k + 2];
     if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) {
         atomicOr(flag, 2);
-        hc[3 * k] = hc[3 * k + 1] = hc[3 * k + 2] = 0.0;
-        area[k] = 0.0;
+        rec[k] = make_double4(0.0, 0.0, 0.0, 0.0);
         return;
     }
     const double e1x = xyz[3 * b] - xyz[3 * a], e1y = xyz[3 * b + 1] - xyz[3 * a + 1],
@@ -36,25 +37,24 @@ __global__ void k_tri_geom(const double *xyz, const int *tri, int64_t nt, int64_
     // gives a cross product of rounding size, not exactly zero, under FMA)
     const double scale = sqrt((e1x * e1x + e1y * e1y + e1z * e1z) * (e2x * e2x + e2y * e2y + e2z * e2z));
     if (!(len > 1e-12 * scale)) atomicOr(flag, 1);
-    hc[3 * k] = 0.5 * cx;
-    hc[3 * k + 1] = 0.5 * cy;
-    hc[3 * k + 2] = 0.5 * cz;
-    area[k] = 0.5 * len;
+    rec[k] = make_double4(0.5 * cx, 0.5 * cy, 0.5 * cz, 0.5 * len);
 }
 
 __global__ void k_fill_flag(int *flag) { *flag = 0; }
 
-__global__ void k_vertex_geom(const int *v2t_off, const int *v2t, const double *hc, const double *area,
-                              int64_t nv, double *s, double *nrm, int *flag) {
-    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ void k_vertex_geom(const int *v2t_off, const int *v2t, const double4 *rec, int64_t nv, double *s,
+                              double *nrm, int *flag) {
+    const int64_t j = xcd_block() * blockDim.x + threadIdx.x;  // a bubble's triangles stay in one L2
     if (j >= nv) return;
     double sa = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
-    for (int e = v2t_off[j]; e < v2t_off[j + 1]; ++e) {
-        const int k = v2t[e];
-        sa += area[k];
-        mx += hc[3 * (int64_t)k];
-        my += hc[3 * (int64_t)k + 1];
-        mz += hc[3 * (int64_t)k + 2];
+    const int e0 = v2t_off[j], e1 = v2t_off[j + 1];
+#pragma unroll 4
+    for (int e = e0; e < e1; ++e) {  // ascending triangle index: a fixed summation order
+        const double4 r = rec[v2t[e]];
+        mx += r.x;
+        my += r.y;
+        mz += r.z;
+        sa += r.w;
     }
     const double len = sqrt(mx * mx + my * my + mz * mz);
     if (!(len > 0.0)) atomicOr(flag, 4);
@@ -74,18 +74,16 @@ void ensure_geometry(bfm_ctx *c, bool check_now) {
     hipStream_t st = c->stream;
     c->s.ensure(c->nv);
     c->nrm.ensure(3 * c->nv);
-    c->tri_hc.ensure(3 * c->nt);
-    c->tri_area.ensure(c->nt);
+    c->tri_rec.ensure(4 * c->nt);
     int *flag = c->flag.ensure(1);
     if (!c->host_flag) BFM_HIP(hipHostMalloc((void **)&c->host_flag, sizeof(int), 0));
     k_fill_flag<<<1, 1, 0, st>>>(flag);
     BFM_LAUNCHED();
-    k_tri_geom<<<nblk(c->nt, 256), 256, 0, st>>>(c->xyz.get(), c->tri.get(), c->nt, c->nv,
-                                                 c->tri_hc.get(), c->tri_area.get(), flag);
+    double4 *rec = reinterpret_cast<double4 *>(c->tri_rec.get());
+    k_tri_geom<<<nblk(c->nt, 256), 256, 0, st>>>(c->xyz.get(), c->tri.get(), c->nt, c->nv, rec, flag);
     BFM_LAUNCHED();
-    k_vertex_geom<<<nblk(c->nv, 256), 256, 0, st>>>(c->v2t_off.get(), c->v2t.get(), c->tri_hc.get(),
-                                                    c->tri_area.get(), c->nv, c->s.get(), c->nrm.get(),
-                                                    flag);
+    k_vertex_geom<<<nblk(c->nv, 256), 256, 0, st>>>(c->v2t_off.get(), c->v2t.get(), rec, c->nv, c->s.get(),
+                                                    c->nrm.get(), flag);
     BFM_LAUNCHED();
     BFM_HIP(hipMemcpyAsync(c->host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     corr_invalidate(c, false);

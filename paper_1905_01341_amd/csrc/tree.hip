@@ -9,6 +9,7 @@
 // of the parent's neighbours that are not adjacent) and M2M/L2L pairs,
 // grouped by translation operator.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "common.h"
@@ -358,11 +359,16 @@ __global__ void k_level_counts(const uint64_t *key, int64_t n, int lmax, unsigne
     __shared__ int c[kKeyBits + 1];
     if (threadIdx.x <= kKeyBits) c[threadIdx.x] = 0;
     __syncthreads();
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) {
+    // a grid of a few hundred workgroups strides over the points, so that the
+    // global counters take few adds; within a workgroup one LDS add per wave
+    // and level (at the deep levels nearly every point opens a box)
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        const uint64_t ki = i < n ? key[i] : 0, kp = (i > 0 && i < n) ? key[i - 1] : 0;
         for (int l = 0; l <= lmax; ++l) {
             const int sh = 3 * (kKeyBits - l);
-            if (i == 0 || (key[i] >> sh) != (key[i - 1] >> sh)) atomicAdd(&c[l], 1);
+            const uint64_t opens = __ballot(i < n && (i == 0 || (ki >> sh) != (kp >> sh)));
+            if ((threadIdx.x & 63) == 0 && opens) atomicAdd(&c[l], (int)__popcll(opens));
         }
     }
     __syncthreads();
@@ -475,42 +481,36 @@ __global__ void k_leaf_near(int64_t nleaf, int64_t leaf0, const int *box_pt0, in
 // Merged near-field source ranges per leaf: the existing neighbours' point
 // ranges sorted by start, touching ranges joined (Morton order makes many
 // neighbours adjacent in the sorted point array).
-__global__ void k_leaf_ranges(int64_t nleaf, int64_t leaf0, const int *leaf_pt, const int *nbr,
-                              int2 *rng, int *cnt) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nleaf) return;
+__global__ void __launch_bounds__(256) k_leaf_ranges(int64_t nleaf, int64_t leaf0, const int *leaf_pt,
+                                                     const int *nbr, int2 *rng, int *cnt) {
+    // one wave per leaf: lane s < 27 holds neighbour slot s's point range;
+    // the ranges are ranked by start, and contiguous ones merged
+    __shared__ int2 sorted[4][32];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    if (i >= nleaf) return;  // the whole wave
     const int64_t b = leaf0 + i;
-    int a[27], e[27], k = 0;
-    for (int s = 0; s < 27; ++s) {
-        const int q = nbr[27 * b + s];
-        if (q < 0) continue;
-        const int64_t qi = q - leaf0;
-        a[k] = leaf_pt[qi];
-        e[k] = leaf_pt[qi + 1];
-        ++k;
+    int a = INT_MAX, e = 0;
+    const int q = lane < 27 ? nbr[27 * b + lane] : -1;
+    if (q >= 0) {
+        a = leaf_pt[q - leaf0];
+        e = leaf_pt[q - leaf0 + 1];
     }
-    for (int x = 1; x < k; ++x) {
-        const int va = a[x], ve = e[x];
-        int y = x - 1;
-        while (y >= 0 && a[y] > va) {
-            a[y + 1] = a[y];
-            e[y + 1] = e[y];
-            --y;
-        }
-        a[y + 1] = va;
-        e[y + 1] = ve;
-    }
-    int m = 0;
-    int2 *out = rng + 27 * i;
-    for (int x = 0; x < k; ++x) {
-        if (m > 0 && out[m - 1].y == a[x]) {
-            out[m - 1].y = e[x];
-        } else {
-            out[m] = make_int2(a[x], e[x]);
-            ++m;
-        }
-    }
-    cnt[i] = m;
+    int rank = 0;  // leaves are non-empty, so the starts are distinct
+    for (int y = 0; y < 27; ++y) rank += __shfl(a, y) < a ? 1 : 0;
+    const int k = __popcll(__ballot(q >= 0));
+    if (q >= 0) sorted[w][rank] = make_int2(a, e);
+    __builtin_amdgcn_wave_barrier();
+    const int2 me = lane < k ? sorted[w][lane] : make_int2(0, 0);
+    const int eprev = __shfl_up(me.y, 1);
+    const bool start = lane < k && (lane == 0 || eprev != me.x);
+    const uint64_t starts = __ballot(start);
+    const bool last = lane < k && (lane == k - 1 || ((starts >> (lane + 1)) & 1ull));
+    const int run = __popcll(starts & ((2ull << lane) - 1ull)) - 1;  // runs begun at lanes <= this one
+    int *out = reinterpret_cast<int *>(rng + 27 * i);
+    if (start) out[2 * run] = me.x;
+    if (last) out[2 * run + 1] = me.y;
+    if (lane == 0) cnt[i] = __popcll(starts);
 }
 
 // Leaf work items (P2M, L2P): chunks of at most kLeafChunk points per leaf.
@@ -854,7 +854,7 @@ void prepare_tiles(TaskList &tl, int nch, int width, hipStream_t st) {
 
 __global__ void k_sort_points(const double *xyz, const int *perm, int64_t n, double *px, double *py,
                               double *pz, int *iperm) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;  // neighbouring boxes stay in one L2
     if (i >= n) return;
     const int o = perm[i];
     px[i] = xyz[3 * (int64_t)o];
@@ -865,7 +865,7 @@ __global__ void k_sort_points(const double *xyz, const int *perm, int64_t n, dou
 
 __global__ void k_sort_geom(const double *s, const double *nrm, const int *perm, int64_t n,
                             double *ps, double *pnx, double *pny, double *pnz) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int o = perm[i];
     ps[i] = s[o];
@@ -953,7 +953,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     auto count_levels = [&]() {
         k_fill_u64<<<1, 64, 0, st>>>(cnt.get(), kKeyBits + 1, 0ull);
         BFM_LAUNCHED();
-        k_level_counts<<<nblk(n, 256), 256, 0, st>>>(t.key_a.get(), n, kKeyBits, cnt.get());
+        k_level_counts<<<std::min(nblk(n, 256), 512u), 256, 0, st>>>(t.key_a.get(), n, kKeyBits, cnt.get());
         BFM_LAUNCHED();
         BFM_HIP(hipMemcpyAsync(hs->cnt, cnt.get(), sizeof(hs->cnt), hipMemcpyDeviceToHost, st));
         BFM_HIP(hipMemcpyAsync(hs->geo, geo, sizeof(hs->geo), hipMemcpyDeviceToHost, st));
@@ -1030,7 +1030,7 @@ void build_tree(Tree &t, const double *xyz, int64_t n, int lmax_req, int leaf_ta
     BFM_LAUNCHED();
     t.near_rng.ensure(27 * t.nleaf);
     t.near_cnt.ensure(t.nleaf);
-    k_leaf_ranges<<<nblk(t.nleaf, 128), 128, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.leaf_pt.get(), t.nbr.get(),
+    k_leaf_ranges<<<nblk(64 * t.nleaf, 256), 256, 0, st>>>(t.nleaf, t.lvl_off[lmax], t.leaf_pt.get(), t.nbr.get(),
                                                       t.near_rng.get(), t.near_cnt.get());
     BFM_LAUNCHED();
     // counts and offsets: leaf items (icnt, ioff), one-sided near-field
