@@ -253,6 +253,7 @@ int bfm_destroy(bfm_ctx *c) {
         mlp_free(c);
         step_free(c);
         graph_invalidate(c);
+        graph_release_stale(c);
         try {
             coarse_join(c);  // (an error of the build is of no interest here)
         } catch (...) {

@@ -56,11 +56,7 @@ struct NearCorr {
 };
 struct Mlp;      // learned initial guess (learn.hip)
 struct CoarseWorker;  // host thread queueing the coarse build (precond.hip)
-struct Stepper;  // captured product (tune.hip)
-void graph_invalidate(bfm_ctx *c);
-// out_s = A P^{-1} in_s (pc) or A in_s through the captured graph; captures on first use
-void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc);
-void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out);
+struct Stepper;
 
 // time-step harness (step.hip)
 }  // namespace bfm
@@ -123,6 +119,10 @@ struct bfm_ctx {
     // fast multipole product from gin to gout, valid for one octree
     hipGraphExec_t mvp_graph = nullptr;
     int mvp_graph_pc = -1;                 // preconditioner the graph was captured with
+    // an invalidated graph, destroyed later at a point where the stream has
+    // just been waited for (its destruction waits for the device, and in the
+    // octree build that wait would take in the coarse build beside it)
+    hipGraphExec_t mvp_graph_stale = nullptr;
     bfm::DevBuf<double> gin, gout;
 
     // GMRES workspace (sorted order)
@@ -201,6 +201,8 @@ void solve_impl(bfm_ctx *c, const double *phi_dev, double *q_dev, int guess, bfm
 
 // captured product (tune.hip)
 void graph_invalidate(bfm_ctx *c);
+// destroys an invalidated graph (call where the stream has just been waited for)
+void graph_release_stale(bfm_ctx *c);
 // out_s = A P^{-1} in_s (pc) or A in_s through the captured graph; captures on first use
 void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc);
 void autotune(bfm_ctx *c, double mvp_tol, bfm_tune_result *out);

@@ -551,6 +551,7 @@ void gmres_sorted(bfm_ctx *c, double *x, bool use_guess, bfm_solve_info *info) {
     // ||b||
     norm2_to(b, L.nrm);
     const double nb = std::sqrt(std::max(read_scalar(L.nrm), 0.0));
+    graph_release_stale(c);  // the stream has just been waited for
     info->iterations = 0;
     info->restarts = 0;
     if (!(nb > 0.0)) {

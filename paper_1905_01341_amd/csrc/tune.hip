@@ -27,10 +27,21 @@ static void copy_vec(const double *in, int64_t n, double *out, hipStream_t st) {
     BFM_LAUNCHED();
 }
 
+// An invalidated graph is kept until graph_release_stale: destroying an
+// executable graph waits for the device, and the octree build, which
+// invalidates it, runs beside the coarse build on a second stream.
 void graph_invalidate(bfm_ctx *c) {
-    if (c->mvp_graph) (void)hipGraphExecDestroy(c->mvp_graph);
+    if (c->mvp_graph) {
+        graph_release_stale(c);
+        c->mvp_graph_stale = c->mvp_graph;
+    }
     c->mvp_graph = nullptr;
     c->mvp_graph_pc = -1;
+}
+
+void graph_release_stale(bfm_ctx *c) {
+    if (c->mvp_graph_stale) (void)hipGraphExecDestroy(c->mvp_graph_stale);
+    c->mvp_graph_stale = nullptr;
 }
 
 // gout = A P^{-1} gin (pc) or A gin
@@ -61,6 +72,7 @@ void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc) {
     mvp_body(c, pc);
     copy_vec(c->gout.get(), n, out_s, st);
     BFM_HIP(hipStreamSynchronize(st));
+    graph_release_stale(c);
     hipGraph_t g = nullptr;
     BFM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {

@@ -22,7 +22,7 @@ from . import bfm
 PLAIN = dict(p=16, p_diag=0, leaf_target=64, lmax=0, m2l_shape=-1, gmres_tol=1e-8, gmres_restart=30,
              gmres_maxit=1000, precond=bfm.PRECOND_NONE, precond_degree=12, use_graph=0)
 TUNED = dict(p=16, p_diag=0, leaf_target=64, lmax=0, m2l_shape=-1, gmres_tol=1e-7, gmres_restart=30,
-             gmres_maxit=1000, precond=bfm.PRECOND_SH_COARSE, precond_degree=12, use_graph=1,
+             gmres_maxit=1000, precond=bfm.PRECOND_SH_COARSE, precond_degree=12, use_graph=0,
              precision=bfm.PREC_BF16X3, p_lo=0, ir_tol=1e-4, m2l_orders=1)
 # product accuracy the autotuner must keep (relative to the p = 20 product)
 TUNE_TOL = 1e-7
