@@ -424,14 +424,15 @@ def main():
     if tune is not None:
         tune["seconds"] = round(time.perf_counter() - t0, 3)
     graph_on = bool(sv.opt.use_graph)
-    # kernel classes are timed with HIP events around every launch; graph
-    # replays carry no per-kernel events and the timing runs the near field
-    # in line, so with graphs the same solve is profiled again afterwards
-    ms, info, prof = run(sv, a.steps, a.warmup, not a.no_profile and not graph_on)
-    # the error of the timed solve's result, before any profiling re-run
+    # kernel classes are timed with HIP events around every launch, which
+    # runs every product eagerly and each near field in line with its far
+    # field; so the timed steps run without it and the same solve is
+    # profiled again afterwards
+    ms, info, _ = run(sv, a.steps, a.warmup, False)
+    # the error of the timed solve's result, before the profiling re-run
     err = error_vs_oracle()
-    prof_steps = a.steps
-    if graph_on and not a.no_profile:
+    prof, prof_steps = None, 0
+    if not a.no_profile:
         prof_steps = max(1, min(a.steps, 3))
         _, _, prof = run(sv, prof_steps, 0, True)
     stats = sv.tree_stats()

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "xcd.h"
 
 namespace bfm {
 

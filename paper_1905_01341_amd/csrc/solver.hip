@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "xcd.h"
 
 namespace bfm {
 

@@ -15,6 +15,7 @@
 #include "common.h"
 #include "ops.h"
 #include "tree.h"
+#include "xcd.h"
 
 namespace bfm {
 
