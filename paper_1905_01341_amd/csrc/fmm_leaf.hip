@@ -87,6 +87,9 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
     constexpr int PP = P_ * P_;
     constexpr int NT = P_ * (P_ + 1) / 2;
     constexpr int NCOL = PP * NCH;
+    // channels with monopoles (bit c): every channel, except in the five-channel
+    // set of the diagonal pass, whose channels 0 and 4 are pure dipoles
+    constexpr unsigned QMASK = !MONO ? 0u : (NCH == 5 ? 0x0Eu : (1u << NCH) - 1u);
     // buffered columns at most (a power of two dividing 64); a loop trip adds
     // at most 4 NCH columns, so the buffer is flushed once it holds COLS
     constexpr int CAP = NCH == 1 ? 16 : 32;
@@ -135,7 +138,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
         r2[u] = x[u] * x[u] + y[u] * y[u] + z[u] * z[u];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            sq[u][c] = MONO ? (R)(ok ? q[(int64_t)c * n + j] : 0.0) : R(0);
+            sq[u][c] = ((QMASK >> c) & 1u) ? (R)(ok ? q[(int64_t)c * n + j] : 0.0) : R(0);
             sw[u][c] = DIP ? (R)(ok ? w[(int64_t)c * n + j] * ih : 0.0) : R(0);
         }
         ux[u] = DIP ? (R)pnx[j] : R(0);
@@ -231,19 +234,25 @@ __global__ void __launch_bounds__(64) k_p2m(const int2 *__restrict__ items, int6
         // the conjugated coefficient of degree k (held in C) for every channel
         auto emit = [&](const R(&Cr)[kPPL], const R(&Ci)[kPPL], const R(&DCr)[kPPL],
                         const R(&DCi)[kPPL]) {
+            // a term is left out where its channel has no monopole (or no dipole)
+            auto term = [&](int c, int u, R a, R da) -> R {
+                const bool hq = (QMASK >> c) & 1u;
+                if (hq && DIP) return sq[u][c] * a + sw[u][c] * da;
+                return hq ? sq[u][c] * a : sw[u][c] * da;
+            };
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                R v = sq[0][c] * Cr[0] + sw[0][c] * DCr[0];
+                R v = term(c, 0, Cr[0], DCr[0]);
 #pragma unroll
-                for (int u = 1; u < kPPL; ++u) v += sq[u][c] * Cr[u] + sw[u][c] * DCr[u];
+                for (int u = 1; u < kPPL; ++u) v += term(c, u, Cr[u], DCr[u]);
                 put(v);
             }
             if (m > 0) {
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    R v = sq[0][c] * Ci[0] + sw[0][c] * DCi[0];
+                    R v = term(c, 0, Ci[0], DCi[0]);
 #pragma unroll
-                    for (int u = 1; u < kPPL; ++u) v += sq[u][c] * Ci[u] + sw[u][c] * DCi[u];
+                    for (int u = 1; u < kPPL; ++u) v += term(c, u, Ci[u], DCi[u]);
                     put(-v);
                 }
             }

@@ -181,6 +181,8 @@ void to_original(bfm_ctx *c, const double *in, double *out) {
 //   ch0: w = s                          -> sum M_ij
 //   ch1..3: q = -s n_a, w = s r_a       -> sum M_ij r_ja - sum L_ij n_ja
 //   ch4: w = s phi                      -> sum M_ij phi_j
+// (channels 0 and 4 carry no monopole: the five-channel P2M leaves their
+// monopole terms out)
 
 __global__ void k_diag_sources(const double *px, const double *py, const double *pz, const double *ps,
                                const double *pnx, const double *pny, const double *pnz,
