@@ -237,7 +237,13 @@ __global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, int kslice
                                                  const double *B, int ldb, double *C, int ldc,
                                                  const double *rowscale, double beta, const double *D, int ldd,
                                                  double *W) {
-    __shared__ double As[kGemmKC][64 + 1], Bs[kGemmKC][64 + 1];  // [k][row], [k][col]
+    // A and B chunks ([k][row], [k][col]); after the products the same LDS
+    // holds the 64 x 64 result tile ([col][row]) for coalesced stores
+    __shared__ double sbuf[2 * kGemmKC * (64 + 1)];
+    static_assert(2 * kGemmKC >= 64, "the result tile fits in the chunk buffers");
+    double(*As)[64 + 1] = reinterpret_cast<double(*)[64 + 1]>(sbuf);
+    double(*Bs)[64 + 1] = reinterpret_cast<double(*)[64 + 1]>(sbuf + kGemmKC * (64 + 1));
+    double(*Cs)[64 + 1] = reinterpret_cast<double(*)[64 + 1]>(sbuf);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
     const int ka = blockIdx.z * kslice, kb = min(K, ka + kslice);
@@ -286,25 +292,32 @@ __global__ void __launch_bounds__(256) k_gemm_nn(int M, int N, int K, int kslice
         }
         __syncthreads();
     }
-    double *Wz = W ? W + (int64_t)blockIdx.z * M * N : nullptr;
+    // the tile through LDS, then each wave stores whole 64-row columns
+    // (512 contiguous bytes) instead of 16 columns x 4 rows
+    __syncthreads();
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gi = i0 + wi + 16 * a + lane / 16 + 4 * r, gj = j0 + wj + 16 * b + lane % 16;
-                if (gi < M && gj < N) {
-                    double val = acc[a][b][r];
-                    if (Wz) {
-                        Wz[(int64_t)gj * M + gi] = val;
-                    } else {
-                        if (rowscale) val *= rowscale[gi];
-                        if (D) val += beta * D[(int64_t)gj * ldd + gi];
-                        C[(int64_t)gj * ldc + gi] = val;
-                    }
-                }
+            for (int r = 0; r < 4; ++r) Cs[wj + 16 * b + lane % 16][wi + 16 * a + lane / 16 + 4 * r] = acc[a][b][r];
+    __syncthreads();
+    double *Wz = W ? W + (int64_t)blockIdx.z * M * N : nullptr;
+    const int gi = i0 + lane;
+#pragma unroll 4
+    for (int cc = wave; cc < 64; cc += 4) {
+        const int gj = j0 + cc;
+        if (gi < M && gj < N) {
+            double val = Cs[cc][lane];
+            if (Wz) {
+                Wz[(int64_t)gj * M + gi] = val;
+            } else {
+                if (rowscale) val *= rowscale[gi];
+                if (D) val += beta * D[(int64_t)gj * ldd + gi];
+                C[(int64_t)gj * ldc + gi] = val;
             }
+        }
+    }
 }
 
 // C = rowscale o (sum over the S slices of W) + beta D
