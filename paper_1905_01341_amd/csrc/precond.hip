@@ -679,17 +679,18 @@ __global__ void k_gj_negate(const double *S, int64_t m, double *P) {
 }
 
 // Column blocks of the sweep: 64 (each diagonal block inverted in LDS by
-// k_gj_block), or 128 on large matrices, whose diagonal blocks are inverted
-// by a 64-block sweep over a packed copy. A rank-128 trailing update reads
-// and writes the matrix once for 128 columns instead of 64, and the sweep
-// is bound by that traffic (79 passes over a 200 MB matrix at 5000 bubbles).
-constexpr int kGjOuter = 128;
-constexpr int kGjOuterMin = 2048;  // matrix size from which the sweep takes 128-column blocks
+// k_gj_block), or 256 on large matrices, whose diagonal blocks are inverted
+// by a 64-block sweep over a packed copy. A rank-256 trailing update reads
+// and writes the matrix once for 256 columns instead of 64, and the sweep
+// is bound by that traffic (with 64-column blocks, 79 passes over a 200 MB
+// matrix at 5000 bubbles).
+constexpr int kGjOuter = 256;
+constexpr int kGjOuterMin = 2048;  // matrix size from which the sweep takes 256-column blocks
 
-// One blocked Gauss-Jordan sweep with B-column blocks (B = 64 or 128):
+// One blocked Gauss-Jordan sweep with B-column blocks (B = 64 or 256):
 // per diagonal block K, P = A_KK^{-1}; A_Kj <- P A_Kj, A_ij <- A_ij - A_iK P A_Kj,
 // A_iK <- -A_iK P, A_KK <- P (j, i outside K). Work: Pn (B x B), Rn (B x n),
-// Cn (n x B); for B = 128 also `inner` (B^2 + 64^2 + 2 * 64 B doubles).
+// Cn (n x B); for B = 256 also `inner` (B^2 + 64^2 + 2 * 64 B doubles).
 static void gj_sweep(double *A, int nb, int B, double *Pn, double *Rn, double *Cn, double *inner, hipStream_t st) {
     for (int k0 = 0; k0 < nb; k0 += B) {
         const int bs = std::min(B, nb - k0);

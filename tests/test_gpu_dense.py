@@ -21,7 +21,7 @@ def test_dgemm_matches_numpy(M, N, K):
     np.testing.assert_allclose(C, ref, rtol=0, atol=1e-13 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max())
 
 
-# n >= 2048 takes 128-column blocks, each diagonal block inverted by a
+# n >= 2048 takes 256-column blocks, each diagonal block inverted by a
 # 64-block sweep (2100: a ragged last block of 52)
 @pytest.mark.parametrize("n", [1, 5, 64, 100, 130, 1000, 2100, 3000])
 def test_spd_inverse_matches_numpy(n):
