@@ -123,6 +123,7 @@ struct bfm_ctx {
     // just been waited for (its destruction waits for the device, and in the
     // octree build that wait would take in the coarse build beside it)
     hipGraphExec_t mvp_graph_stale = nullptr;
+    int mvp_graph_stale_pc = -1;
     bfm::DevBuf<double> gin, gout;
 
     // GMRES workspace (sorted order)

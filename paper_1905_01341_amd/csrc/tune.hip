@@ -34,6 +34,7 @@ void graph_invalidate(bfm_ctx *c) {
     if (c->mvp_graph) {
         graph_release_stale(c);
         c->mvp_graph_stale = c->mvp_graph;
+        c->mvp_graph_stale_pc = c->mvp_graph_pc;
     }
     c->mvp_graph = nullptr;
     c->mvp_graph_pc = -1;
@@ -68,11 +69,11 @@ void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc) {
     }
     graph_invalidate(c);
     // eager run first: every lazy preparation (tiles, buffers, operators)
-    // happens here, outside the capture, and its result is this call's product
+    // happens here, outside the capture, and its result is this call's product.
+    // The capture follows while it runs: capturing records the launches
+    // without running them, so the stream need not be idle.
     mvp_body(c, pc);
     copy_vec(c->gout.get(), n, out_s, st);
-    BFM_HIP(hipStreamSynchronize(st));
-    graph_release_stale(c);
     hipGraph_t g = nullptr;
     BFM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
@@ -85,7 +86,24 @@ void graph_mvp(bfm_ctx *c, const double *in_s, double *out_s, bool pc) {
     }
     BFM_HIP(hipStreamEndCapture(st, &g));
     hipGraphExec_t ge = nullptr;
-    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    // the previous octree's executable graph is updated in place when the
+    // new capture has the same launches (new arguments and grid sizes),
+    // which spares an instantiation and the destruction of the old one
+    if (c->mvp_graph_stale && c->mvp_graph_stale_pc == (int)pc) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(c->mvp_graph_stale, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+            ge = c->mvp_graph_stale;
+            c->mvp_graph_stale = nullptr;
+        } else {
+            (void)hipGetLastError();  // a refused update leaves no error behind
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!ge) {
+        graph_release_stale(c);
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    }
     (void)hipGraphDestroy(g);
     BFM_CHECK(e == hipSuccess, BFM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     c->mvp_graph = ge;
